@@ -1,0 +1,527 @@
+/*
+ * Plain FP64 CPU reference for one weakly-compressible SPH (WCSPH) time step.
+ *
+ * TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library. It shares no code, header, table or
+ * constant with the HIP path; both are written independently from the paper
+ * (Valdez-Balderas et al., "Towards accelerating SPH simulations for
+ * free-surface flows on multi-GPU clusters") and from the readings listed in
+ * the design notes.
+ *
+ * Precision: every physical quantity is FP64. Two integer decisions are taken
+ * in FP32 on purpose, in the same precision as the GPU kernels that the oracle
+ * checks, so that both sides make the same decision:
+ *   - the cell coordinate floorf((x - o) * (1/cs)) of Sec. 3.1 (cells of 2h);
+ *   - the neighbour test |r_i - r_j|^2 < (2h)^2 of Sec. 2.2 (compact support,
+ *     kappa = 2), evaluated as fmaf(dz,dz, fmaf(dy,dy, dx*dx)) < (float)(4h^2).
+ * Build with -ffp-contract=off so that no other expression is contracted.
+ *
+ * Particle types: 0 fluid, 1 boundary (dynamic boundary, Sec. 2.3),
+ * 2 ghost (halo copy of a neighbouring sub-domain, Sec. 4.2).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { T_FLUID = 0, T_BOUNDARY = 1, T_GHOST = 2 };
+
+typedef struct {
+    double dp, h, rho0, gamma, c0, alpha, eta_over_h, cfl, mass;
+    double g[3];
+    double origin[3];
+    int32_t ncell[3];
+    int32_t euler_every;
+    int32_t slab_mode;
+    int32_t pad_;
+    double slab_xlo, slab_xhi;
+} orc_params;
+
+int orc_abi_version(void) { return 1; }
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------- keys (a1) */
+
+/* Bits of a linear cell index: smallest b with 2^b >= number of cells. */
+int orc_cell_bits(const orc_params *p)
+{
+    int64_t nc = (int64_t)p->ncell[0] * p->ncell[1] * p->ncell[2];
+    int b = 1;
+    while (((int64_t)1 << b) < nc) b++;
+    return b;
+}
+
+/*
+ * Sec. 3.1: one label per particle naming its cubic cell of side 2h; Sec. 4.2
+ * (migration): 0 stays, 1 moved out to the left, 2 moved out to the right.
+ * Label 3 marks a particle outside the cell grid (excluded, never lost
+ * silently). Ghosts inside the grid are always label 0.
+ * key = label << Bc | ((cx*ncy + cy)*ncz + cz); label-3 keys carry cell 0.
+ */
+void orc_keys(const orc_params *p, int64_t n, const double *x, const double *y,
+              const double *z, const uint8_t *type, uint32_t *key)
+{
+    const int bc = orc_cell_bits(p);
+    const double cs = 2.0 * p->h;
+    const float inv = (float)(1.0 / cs);
+    const float o[3] = {(float)p->origin[0], (float)p->origin[1], (float)p->origin[2]};
+    const float xlo = (float)p->slab_xlo, xhi = (float)p->slab_xhi;
+    for (int64_t i = 0; i < n; i++) {
+        const float r[3] = {(float)x[i], (float)y[i], (float)z[i]};
+        int c[3];
+        int inside = 1;
+        for (int a = 0; a < 3; a++) {
+            const float t = (r[a] - o[a]) * inv;
+            if (!(t >= 0.0f && t < (float)p->ncell[a])) { inside = 0; c[a] = 0; }
+            else c[a] = (int)floorf(t);
+            if (inside && c[a] >= p->ncell[a]) inside = 0;
+        }
+        uint32_t label = 0, cell = 0;
+        if (!inside) {
+            label = 3;
+        } else {
+            cell = (uint32_t)(((int64_t)c[0] * p->ncell[1] + c[1]) * p->ncell[2] + c[2]);
+            if (p->slab_mode && type[i] != T_GHOST) {
+                if (r[0] < xlo) label = 1;
+                else if (r[0] >= xhi) label = 2;
+            }
+        }
+        key[i] = (label << bc) | cell;
+    }
+}
+
+/* --------------------------------------------------------- stable sort (a2) */
+
+typedef struct { uint32_t k; int32_t i; } kv_t;
+
+static int kv_cmp(const void *a, const void *b)
+{
+    const kv_t *u = (const kv_t *)a, *v = (const kv_t *)b;
+    if (u->k != v->k) return u->k < v->k ? -1 : 1;
+    return (u->i > v->i) - (u->i < v->i);  /* ties keep input order (stable) */
+}
+
+/* Sort (key, original index) by key; equal keys keep their input order, as in
+ * the radix-sort example of Sec. 4.3. perm[k] = input position of output k. */
+void orc_stable_sort(int64_t n, const uint32_t *key, uint32_t *key_out, int32_t *perm)
+{
+    kv_t *t = (kv_t *)malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; i++) { t[i].k = key[i]; t[i].i = (int32_t)i; }
+    qsort(t, (size_t)n, sizeof(kv_t), kv_cmp);
+    for (int64_t i = 0; i < n; i++) { key_out[i] = t[i].k; perm[i] = t[i].i; }
+    free(t);
+}
+
+/* Sort arbitrary (key, value) pairs stably by key (values travel with keys). */
+void orc_stable_sort_kv(int64_t n, const uint32_t *key, const int32_t *val,
+                        uint32_t *key_out, int32_t *val_out)
+{
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    orc_stable_sort(n, key, key_out, perm);
+    for (int64_t i = 0; i < n; i++) val_out[i] = val[perm[i]];
+    free(perm);
+}
+
+/* ------------------------------------------------------- cell tables (a4/a5) */
+
+static int64_t lower_bound_u32(const uint32_t *a, int64_t n, uint32_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/*
+ * Sec. 3.1 (index of the first particle of each cell) and Sec. 4.4 (first and
+ * last particle of a region). Over the label-0 prefix of the sorted keys:
+ * begin[c] = lower_bound(c), end[c] = upper_bound(c); an empty cell has
+ * begin = end = lower_bound(c). counts[l] = particles with label l.
+ */
+void orc_cell_tables(const orc_params *p, int64_t n, const uint32_t *skey,
+                     uint32_t *begin, uint32_t *end, uint32_t *counts)
+{
+    const int bc = orc_cell_bits(p);
+    const int64_t nc = (int64_t)p->ncell[0] * p->ncell[1] * p->ncell[2];
+    int64_t start[5];
+    for (uint32_t l = 0; l < 4; l++) start[l] = lower_bound_u32(skey, n, l << bc);
+    start[4] = n;
+    for (int l = 0; l < 4; l++) counts[l] = (uint32_t)(start[l + 1] - start[l]);
+    const int64_t n0 = start[1];
+    for (int64_t c = 0; c < nc; c++) {
+        begin[c] = (uint32_t)lower_bound_u32(skey, n0, (uint32_t)c);
+        end[c] = (uint32_t)lower_bound_u32(skey, n0, (uint32_t)c + 1u);
+    }
+}
+
+/*
+ * Packing ranges of Sec. 4.2-4.3 read off the x-major cell order: every
+ * x-layer of cells is one contiguous index range. out[0..1] left halo (layer
+ * 0), out[2..3] left edge (layer 1), out[4..5] right edge (layer ncx-2),
+ * out[6..7] right halo (layer ncx-1), out[8..9] moved-left range,
+ * out[10..11] moved-right range, out[12..13] excluded range.
+ */
+void orc_ranges(const orc_params *p, const uint32_t *begin, const uint32_t *end,
+                const uint32_t *counts, uint32_t *out)
+{
+    const int64_t layer = (int64_t)p->ncell[1] * p->ncell[2];
+    const int ncx = p->ncell[0];
+    const int lay[4] = {0, 1, ncx - 2, ncx - 1};
+    for (int k = 0; k < 4; k++) {
+        int L = lay[k] < 0 ? 0 : lay[k];
+        out[2 * k] = begin[L * layer];
+        out[2 * k + 1] = end[(L + 1) * layer - 1];
+    }
+    uint32_t n0 = counts[0], n1 = counts[1], n2 = counts[2], n3 = counts[3];
+    out[8] = n0; out[9] = n0 + n1;
+    out[10] = n0 + n1; out[11] = n0 + n1 + n2;
+    out[12] = n0 + n1 + n2; out[13] = n0 + n1 + n2 + n3;
+}
+
+/* ------------------------------------------------------------ kernel, EOS */
+
+/* Wendland C2 kernel in 3-D (the workload's choice in place of the cubic
+ * spline of Sec. 2.2): W(q) = aD (1 - q/2)^4 (2q + 1), q = r/h <= 2,
+ * aD = 21 / (16 pi h^3). */
+double orc_kernel_w(double r, double h)
+{
+    const double q = r / h;
+    if (q >= 2.0) return 0.0;
+    const double aD = 21.0 / (16.0 * M_PI * h * h * h);
+    const double t = 1.0 - 0.5 * q;
+    return aD * t * t * t * t * (2.0 * q + 1.0);
+}
+
+/* grad_i W_ij = F(r) * (r_i - r_j): dW/dq = -5 aD q (1 - q/2)^3, so
+ * F = (dW/dr) / r = -5 aD (1 - q/2)^3 / h^2. */
+double orc_kernel_f(double r, double h)
+{
+    const double q = r / h;
+    if (q >= 2.0) return 0.0;
+    const double aD = 21.0 / (16.0 * M_PI * h * h * h);
+    const double t = 1.0 - 0.5 * q;
+    return -5.0 * aD * t * t * t / (h * h);
+}
+
+/* Tait equation of state, Sec. 2.2: p = B[(rho/rho0)^gamma - 1],
+ * B = c0^2 rho0 / gamma; sound speed c = sqrt(dp/drho) =
+ * c0 (rho/rho0)^((gamma-1)/2). */
+void orc_eos(const orc_params *p, double rho, double *press, double *c)
+{
+    const double B = p->c0 * p->c0 * p->rho0 / p->gamma;
+    const double r = rho / p->rho0;
+    *press = B * (pow(r, p->gamma) - 1.0);
+    *c = p->c0 * pow(r, 0.5 * (p->gamma - 1.0));
+}
+
+/* ----------------------------------------------------------- pair terms (b) */
+
+typedef struct { double ax, ay, az, drho, nu; } acc_t;
+
+/*
+ * Contribution of neighbour j to particle i, Sec. 2.2:
+ *   continuity  drho_i/dt += m v_ij . grad_i W_ij
+ *   momentum    dv_i/dt   -= m (p_i/rho_i^2 + p_j/rho_j^2 + Pi_ij) grad_i W_ij
+ *   Pi_ij = -alpha cbar_ij mu_ij / rhobar_ij if r_ij . v_ij < 0, else 0,
+ *   mu_ij = h v_ij . r_ij / (r_ij^2 + eta^2), eta = 0.1 h,
+ *   cbar = (c_i + c_j)/2, rhobar = (rho_i + rho_j)/2,
+ * and nu_i = max_j |mu_ij| for the CFL limit.
+ * (rx, ry, rz) = r_i - r_j and (ux, uy, uz) = v_i - v_j, in FP64.
+ */
+static void pair_terms(const orc_params *p, double rx, double ry, double rz,
+                       double ux, double uy, double uz, double rho_i, double rho_j,
+                       double P_i, double P_j, double c_i, double c_j, acc_t *a)
+{
+    const double h = p->h, m = p->mass;
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double F = orc_kernel_f(sqrt(r2), h);
+    const double vr = ux * rx + uy * ry + uz * rz;
+    const double eta = p->eta_over_h * h;
+    const double mu = h * vr / (r2 + eta * eta);
+    double Pi = 0.0;
+    if (vr < 0.0)
+        Pi = -p->alpha * 0.5 * (c_i + c_j) * mu / (0.5 * (rho_i + rho_j));
+    const double s = P_i + P_j + Pi;
+    a->ax -= m * s * F * rx;
+    a->ay -= m * s * F * ry;
+    a->az -= m * s * F * rz;
+    a->drho += m * vr * F;
+    if (fabs(mu) > a->nu) a->nu = fabs(mu);
+}
+
+/* Neighbour decision in FP32 (see header). */
+static int within_support(float xi, float yi, float zi, float xj, float yj, float zj,
+                          float r2max)
+{
+    const float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    return r2 < r2max;
+}
+
+static float support_r2(const orc_params *p)
+{
+    return (float)(4.0 * p->h * p->h);
+}
+
+/*
+ * Interaction (Sec. 3.2): for each selected non-ghost particle i of the
+ * label-0 prefix, neighbours j != i are searched in i's cell and the 26 cells
+ * around it (cells of 2h, Sec. 3.1). Outputs per selected particle k:
+ *   a = -sum_j m(P_i+P_j+Pi_ij) grad W + g for fluid i, 0 otherwise;
+ *   D = drho/dt for fluid and boundary i (boundary i: same equations,
+ *       Sec. 2.3);
+ *   nu = max_j |mu_ij|; p, c from the equation of state; npair = |N(i)|.
+ * sel == NULL selects every index in [0, n0); ghosts get zeros.
+ */
+void orc_interact(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, const double *vx, const double *vy,
+                  const double *vz, const double *rho, const uint8_t *type,
+                  const uint32_t *skey, const uint32_t *begin, const uint32_t *end,
+                  int64_t n0, int64_t nsel, const int64_t *sel, double *ax, double *ay,
+                  double *az, double *drho, double *nu, double *press, double *csound,
+                  int64_t *npair)
+{
+    (void)n;
+    const int bc = orc_cell_bits(p);
+    const uint32_t cmask = (bc >= 32) ? 0xffffffffu : ((1u << bc) - 1u);
+    const int ncx = p->ncell[0], ncy = p->ncell[1], ncz = p->ncell[2];
+    const float r2max = support_r2(p);
+    const int64_t cnt = sel ? nsel : n0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; k++) {
+        const int64_t i = sel ? sel[k] : k;
+        acc_t a = {0, 0, 0, 0, 0};
+        double Pi_, ci, pi;
+        orc_eos(p, rho[i], &pi, &ci);
+        Pi_ = pi / (rho[i] * rho[i]);
+        int64_t np_ = 0;
+        if (type[i] != T_GHOST && i < n0) {
+            const uint32_t cell = skey[i] & cmask;
+            const int cz = (int)(cell % (uint32_t)ncz);
+            const int cy = (int)((cell / (uint32_t)ncz) % (uint32_t)ncy);
+            const int cx = (int)(cell / ((uint32_t)ncz * (uint32_t)ncy));
+            const float xi = (float)x[i], yi = (float)y[i], zi = (float)z[i];
+            for (int ox = -1; ox <= 1; ox++)
+            for (int oy = -1; oy <= 1; oy++)
+            for (int oz = -1; oz <= 1; oz++) {
+                const int X = cx + ox, Y = cy + oy, Z = cz + oz;
+                if (X < 0 || X >= ncx || Y < 0 || Y >= ncy || Z < 0 || Z >= ncz) continue;
+                const int64_t c = ((int64_t)X * ncy + Y) * ncz + Z;
+                for (int64_t j = begin[c]; j < (int64_t)end[c]; j++) {
+                    if (j == i) continue;
+                    if (!within_support(xi, yi, zi, (float)x[j], (float)y[j], (float)z[j], r2max))
+                        continue;
+                    double pj, cj;
+                    orc_eos(p, rho[j], &pj, &cj);
+                    pair_terms(p, x[i] - x[j], y[i] - y[j], z[i] - z[j], vx[i] - vx[j],
+                               vy[i] - vy[j], vz[i] - vz[j], rho[i], rho[j], Pi_,
+                               pj / (rho[j] * rho[j]), ci, cj, &a);
+                    np_++;
+                }
+            }
+        }
+        if (type[i] == T_FLUID && i < n0) {
+            ax[k] = a.ax + p->g[0];
+            ay[k] = a.ay + p->g[1];
+            az[k] = a.az + p->g[2];
+        } else {
+            ax[k] = ay[k] = az[k] = 0.0;
+        }
+        drho[k] = (type[i] != T_GHOST && i < n0) ? a.drho : 0.0;
+        nu[k] = a.nu;
+        if (press) press[k] = pi;
+        if (csound) csound[k] = ci;
+        if (npair) npair[k] = np_;
+    }
+}
+
+/*
+ * Brute-force O(N^2) version of the same sums over every pair (for tests):
+ * no cells, every non-ghost i against every j != i. With box != NULL the
+ * domain is periodic with those side lengths (minimum image), which gives a
+ * closed system for momentum-conservation checks.
+ */
+void orc_interact_brute(const orc_params *p, int64_t n, const double *x, const double *y,
+                        const double *z, const double *vx, const double *vy,
+                        const double *vz, const double *rho, const uint8_t *type,
+                        const double *box, double *ax, double *ay, double *az,
+                        double *drho, double *nu, int64_t *npair)
+{
+    const float r2max = support_r2(p);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        acc_t a = {0, 0, 0, 0, 0};
+        double pi, ci;
+        orc_eos(p, rho[i], &pi, &ci);
+        const double Pi_ = pi / (rho[i] * rho[i]);
+        int64_t np_ = 0;
+        if (type[i] != T_GHOST) {
+            for (int64_t j = 0; j < n; j++) {
+                if (j == i) continue;
+                double r[3] = {x[i] - x[j], y[i] - y[j], z[i] - z[j]};
+                if (box)
+                    for (int d = 0; d < 3; d++) r[d] -= box[d] * nearbyint(r[d] / box[d]);
+                /* same FP32 test on the (minimum-image) separation */
+                const float dx = (float)r[0], dy = (float)r[1], dz = (float)r[2];
+                if (box) {
+                    if (!(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < r2max)) continue;
+                } else if (!within_support((float)x[i], (float)y[i], (float)z[i], (float)x[j],
+                                           (float)y[j], (float)z[j], r2max)) {
+                    continue;
+                }
+                double pj, cj;
+                orc_eos(p, rho[j], &pj, &cj);
+                pair_terms(p, r[0], r[1], r[2], vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j],
+                           rho[i], rho[j], Pi_, pj / (rho[j] * rho[j]), ci, cj, &a);
+                np_++;
+            }
+        }
+        if (type[i] == T_FLUID) {
+            ax[i] = a.ax + p->g[0]; ay[i] = a.ay + p->g[1]; az[i] = a.az + p->g[2];
+        } else {
+            ax[i] = ay[i] = az[i] = 0.0;
+        }
+        drho[i] = type[i] != T_GHOST ? a.drho : 0.0;
+        nu[i] = a.nu;
+        if (npair) npair[i] = np_;
+    }
+}
+
+/* Neighbour lists by brute force (CSR, j ascending) for sets-equality tests. */
+int64_t orc_neighbours_brute(const orc_params *p, int64_t n, const double *x,
+                             const double *y, const double *z, int64_t *rowptr,
+                             int32_t *cols, int64_t cap)
+{
+    const float r2max = support_r2(p);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++) {
+        rowptr[i] = m;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            if (!within_support((float)x[i], (float)y[i], (float)z[i], (float)x[j],
+                                (float)y[j], (float)z[j], r2max))
+                continue;
+            if (m < cap) cols[m] = (int32_t)j;
+            m++;
+        }
+    }
+    rowptr[n] = m;
+    return m;
+}
+
+/* The same lists through the cell tables (27 cells), in input order of i. */
+int64_t orc_neighbours_cells(const orc_params *p, int64_t n0, const double *x,
+                             const double *y, const double *z, const uint32_t *skey,
+                             const uint32_t *begin, const uint32_t *end, int64_t *rowptr,
+                             int32_t *cols, int64_t cap)
+{
+    const int bc = orc_cell_bits(p);
+    const uint32_t cmask = (bc >= 32) ? 0xffffffffu : ((1u << bc) - 1u);
+    const int ncx = p->ncell[0], ncy = p->ncell[1], ncz = p->ncell[2];
+    const float r2max = support_r2(p);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n0; i++) {
+        rowptr[i] = m;
+        const uint32_t cell = skey[i] & cmask;
+        const int cz = (int)(cell % (uint32_t)ncz);
+        const int cy = (int)((cell / (uint32_t)ncz) % (uint32_t)ncy);
+        const int cx = (int)(cell / ((uint32_t)ncz * (uint32_t)ncy));
+        for (int ox = -1; ox <= 1; ox++)
+        for (int oy = -1; oy <= 1; oy++)
+        for (int oz = -1; oz <= 1; oz++) {
+            const int X = cx + ox, Y = cy + oy, Z = cz + oz;
+            if (X < 0 || X >= ncx || Y < 0 || Y >= ncy || Z < 0 || Z >= ncz) continue;
+            const int64_t c = ((int64_t)X * ncy + Y) * ncz + Z;
+            for (int64_t j = begin[c]; j < (int64_t)end[c]; j++) {
+                if (j == i) continue;
+                if (!within_support((float)x[i], (float)y[i], (float)z[i], (float)x[j],
+                                    (float)y[j], (float)z[j], r2max))
+                    continue;
+                if (m < cap) cols[m] = (int32_t)j;
+                m++;
+            }
+        }
+    }
+    rowptr[n0] = m;
+    return m;
+}
+
+/* ------------------------------------------------------------- dt (c1) */
+
+/*
+ * Variable time step (Sec. 3.3: CFL condition and magnitude of the
+ * interactions; Monaghan-Kos form of the cited SPHysics formulation):
+ *   dt = CFL * min( min_fluid sqrt(h/|a_i|), min_nonghost h/(c_i + nu_i) ),
+ * over the first n0 particles. A particle with |a| = 0 imposes no force limit.
+ */
+double orc_dt(const orc_params *p, int64_t n0, const uint8_t *type, const double *ax,
+              const double *ay, const double *az, const double *rho, const double *nu)
+{
+    double dtf = INFINITY, dtcv = INFINITY;
+    for (int64_t i = 0; i < n0; i++) {
+        if (type[i] == T_GHOST) continue;
+        double pr, c;
+        orc_eos(p, rho[i], &pr, &c);
+        const double v = p->h / (c + nu[i]);
+        if (v < dtcv) dtcv = v;
+        if (type[i] == T_FLUID) {
+            const double amag = sqrt(ax[i] * ax[i] + ay[i] * ay[i] + az[i] * az[i]);
+            if (amag > 0.0) {
+                const double f = sqrt(p->h / amag);
+                if (f < dtf) dtf = f;
+            }
+        }
+    }
+    return p->cfl * (dtf < dtcv ? dtf : dtcv);
+}
+
+/* ---------------------------------------------------------- Verlet (c2) */
+
+/*
+ * Second-order Verlet update (Sec. 3.3) in leapfrog form, with an Euler step
+ * every euler_every steps (step 0 included):
+ *   Euler:    v' = v + dt a,        rho' = rho + dt D
+ *   leapfrog: v' = v_prev + 2dt a,  rho' = rho_prev + 2dt D
+ *   always    r' = r + dt v + dt^2 a / 2,  then (v_prev, rho_prev) <- (v, rho).
+ * Fluid updates r, v, rho. Boundary particles update rho only (position and
+ * velocity fixed, Sec. 2.3). Ghosts are not updated. Applies to [0, n0).
+ */
+void orc_verlet(const orc_params *p, int64_t n0, int64_t step, double dt,
+                const uint8_t *type, double *x, double *y, double *z, double *vx,
+                double *vy, double *vz, double *rho, double *vxp, double *vyp, double *vzp,
+                double *rhop, const double *ax, const double *ay, const double *az,
+                const double *drho)
+{
+    const int euler = p->euler_every > 0 ? (step % p->euler_every == 0) : (step == 0);
+    for (int64_t i = 0; i < n0; i++) {
+        if (type[i] == T_GHOST) continue;
+        const double r_new = euler ? rho[i] + dt * drho[i] : rhop[i] + 2.0 * dt * drho[i];
+        rhop[i] = rho[i];
+        rho[i] = r_new;
+        if (type[i] != T_FLUID) continue;
+        double v[3] = {vx[i], vy[i], vz[i]};
+        double vp[3] = {vxp[i], vyp[i], vzp[i]};
+        double a[3] = {ax[i], ay[i], az[i]};
+        double vn[3];
+        for (int d = 0; d < 3; d++) vn[d] = euler ? v[d] + dt * a[d] : vp[d] + 2.0 * dt * a[d];
+        x[i] += dt * v[0] + 0.5 * dt * dt * a[0];
+        y[i] += dt * v[1] + 0.5 * dt * dt * a[1];
+        z[i] += dt * v[2] + 0.5 * dt * dt * a[2];
+        vxp[i] = v[0]; vyp[i] = v[1]; vzp[i] = v[2];
+        vx[i] = vn[0]; vy[i] = vn[1]; vz[i] = vn[2];
+    }
+}

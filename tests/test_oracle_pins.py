@@ -1,0 +1,469 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a worked
+example printed in the paper, a library routine, brute force, a closed form
+or an invariant. None of these tests touches the GPU.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from paper_1210_1017_amd import cases
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *v = line.split()
+            rows[k] = v
+    return rows
+
+
+# ------------------------------------------------------------ sort (a2)
+
+def test_paper_radix_example(orc):
+    g = _golden("paper_radix_example.txt")
+    k = np.array(g["label_in"], dtype=np.uint32)
+    v = np.array(g["id_in"], dtype=np.int32)
+    ko, vo = orc.stable_sort_kv(k, v)
+    assert ko.tolist() == [int(t) for t in g["label_out"]]
+    assert vo.tolist() == [int(t) for t in g["id_out"]]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 1000, (1 << 16) + 1])
+@pytest.mark.parametrize("dist", ["random", "dups", "equal", "sorted", "reversed"])
+def test_stable_sort_vs_numpy(orc, n, dist):
+    rng = np.random.default_rng(n * 7 + len(dist))
+    if dist == "random":
+        k = rng.integers(0, 1 << 22, size=n, dtype=np.uint32)
+    elif dist == "dups":
+        k = rng.integers(0, 17, size=n, dtype=np.uint32) << np.uint32(20)
+    elif dist == "equal":
+        k = np.full(n, 12345, dtype=np.uint32)
+    elif dist == "sorted":
+        k = np.sort(rng.integers(0, 1 << 22, size=n, dtype=np.uint32))
+    else:
+        k = np.sort(rng.integers(0, 1 << 22, size=n, dtype=np.uint32))[::-1].copy()
+    ko, perm = orc.stable_sort(k)
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(perm, ref.astype(np.int32))
+    assert np.array_equal(ko, k[ref])
+
+
+# ----------------------------------------------------- keys, tables (a1, a4)
+
+def test_keys_match_cell_definition(orc):
+    case = cases.shuffle(cases.small_tank(), 5)
+    p = case.params
+    k = orc.keys(p, case.state)
+    bc = orc.cell_bits(p)
+    assert bc == cases.cell_bits(p)
+    cs = 2.0 * p["h"]
+    st = case.state
+    # cells from FP64 arithmetic agree with the FP32 rule away from cell faces
+    c = [np.floor((st[a].astype(np.float64) - p["origin"][i]) / cs).astype(np.int64)
+         for i, a in enumerate("xyz")]
+    lin = (c[0] * p["ncell"][1] + c[1]) * p["ncell"][2] + c[2]
+    frac = [((st[a].astype(np.float64) - p["origin"][i]) / cs) % 1.0 for i, a in enumerate("xyz")]
+    safe = np.all([(f > 1e-5) & (f < 1 - 1e-5) for f in frac], axis=0)
+    assert safe.sum() > 0.5 * case.n
+    assert np.array_equal((k[safe] & ((1 << bc) - 1)).astype(np.int64), lin[safe])
+    assert np.all(k >> bc == 0)
+
+
+def test_cell_tables_vs_searchsorted(orc):
+    case = cases.perturb(cases.small_tank(), 3)
+    p = case.params
+    srt = orc.sort_state(p, case.state)
+    sk = srt["keys"]
+    n0 = int(srt["counts"][0])
+    nc = orc.ncells(p)
+    cells = np.arange(nc, dtype=np.uint32)
+    assert np.array_equal(srt["begin"], np.searchsorted(sk[:n0], cells, side="left"))
+    assert np.array_equal(srt["end"], np.searchsorted(sk[:n0], cells, side="right"))
+    assert int(srt["counts"].sum()) == case.n
+    assert int((srt["end"] - srt["begin"]).sum()) == n0
+
+
+def test_slab_labels_counts_and_layers(orc):
+    """Migration labels (Sec. 4.3): 1 = moved left, 2 = moved right; ghosts 0.
+    Edge / halo (Sec. 4.2): strips of width 2h inside / outside each face, here
+    whole x-layers of cells, hence contiguous ranges of the sorted arrays."""
+    case = cases.small_slab()
+    p = case.params
+    srt = orc.sort_state(p, case.state)
+    st = case.state
+    x = st["x"].astype(np.float64)
+    t = st["type"]
+    xlo, xhi = p["slab_xlo"], p["slab_xhi"]
+    want1 = int(((x < xlo) & (t != cases.GHOST)).sum())
+    want2 = int(((x >= xhi) & (t != cases.GHOST)).sum())
+    assert want1 == 12 and want2 == 12
+    cnt = srt["counts"]
+    assert cnt[1] == want1 and cnt[2] == want2 and cnt[3] == 0
+    assert int(cnt.sum()) == case.n
+    r = srt["ranges"]
+    s = srt["state"]
+    sx = s["x"]
+    cs = 2.0 * p["h"]
+    # left halo = every ghost left of the slab; right halo likewise
+    assert np.all(s["type"][r[0]:r[1]] == cases.GHOST)
+    assert r[1] - r[0] == int(((x < xlo) & (t == cases.GHOST)).sum())
+    assert np.all(s["type"][r[6]:r[7]] == cases.GHOST)
+    assert r[7] - r[6] == int(((x > xhi) & (t == cases.GHOST)).sum())
+    # edges: label-0 particles within 2h inside each face
+    inside = (t != cases.GHOST) & (x >= xlo) & (x < xhi)
+    assert r[3] - r[2] == int((inside & (x < xlo + cs)).sum())
+    assert r[5] - r[4] == int((inside & (x >= xhi - cs)).sum())
+    assert np.all((sx[r[2]:r[3]] >= xlo) & (sx[r[2]:r[3]] < xlo + cs))
+    # out-ranges hold exactly the migrants; equal keys keep input order
+    ids1 = s["id"][r[8]:r[9]]
+    assert np.all(sx[r[8]:r[9]] < xlo)
+    sk, perm = srt["keys"], srt["perm"]
+    same = sk[1:] == sk[:-1]
+    assert np.all(perm[1:][same] > perm[:-1][same])
+    assert ids1.size == 12
+    assert np.all(sx[r[10]:r[11]] >= xhi)
+
+
+def test_outside_grid_excluded_and_counted(orc):
+    case = cases.small_tank()
+    st = {k: v.copy() for k, v in case.state.items()}
+    st["z"][:5] = 1e6
+    st["x"][5] = np.nan
+    st["y"][6] = -1.0
+    srt = orc.sort_state(case.params, st)
+    assert srt["counts"][3] == 7
+    assert int(srt["counts"].sum()) == case.n
+    assert sorted(srt["state"]["id"][-7:].tolist()) == [0, 1, 2, 3, 4, 5, 6]
+
+
+# ------------------------------------------------------------ neighbours
+
+@pytest.mark.parametrize("which", ["cloud", "tank"])
+def test_cell_list_equals_brute_force(orc, which):
+    if which == "cloud":
+        case = cases.random_cloud(2000, 0.02, (0.3, 0.2, 0.25), seed=9)
+    else:
+        case = cases.perturb(cases.small_tank(nx=14, ny=8, nz=10, nfx=6, nfz=6), 4)
+    p = case.params
+    srt = orc.sort_state(p, case.state)
+    row_c, col_c = orc.neighbours_cells(p, srt)
+    row_b, col_b = orc.neighbours_brute(p, srt["state"])
+    n0 = int(srt["counts"][0])
+    assert n0 == case.n
+    assert np.array_equal(np.diff(row_c), np.diff(row_b[: n0 + 1]))
+    for i in range(n0):
+        a = np.sort(col_c[row_c[i]:row_c[i + 1]])
+        b = col_b[row_b[i]:row_b[i + 1]]
+        assert np.array_equal(a, b), i
+    # same sets from an FP64 distance test: no pair lies on the 2h boundary here
+    s = srt["state"]
+    P = np.stack([s["x"], s["y"], s["z"]], 1)
+    d2 = ((P[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    assert np.array_equal((d2 < (2 * p["h"]) ** 2).sum(1), np.diff(row_b))
+
+
+def test_interact_cells_equals_brute(orc):
+    case = cases.perturb(cases.small_tank(), 7)
+    p = case.params
+    srt = orc.sort_state(p, case.state)
+    a = orc.interact(p, srt)
+    b = orc.interact_brute(p, srt["state"])
+    for k in ("ax", "ay", "az", "drho", "nu"):
+        scale = np.abs(b[k]).max() + 1e-300
+        assert np.abs(a[k] - b[k]).max() <= 1e-12 * scale, k
+    assert np.array_equal(a["npair"], b["npair"])
+
+
+# --------------------------------------------------------- kernel, EOS
+
+def test_wendland_unit_integral_and_support(orc):
+    for h in (0.026, 1.3, 0.00169):
+        val, err = quad(lambda r: 4 * math.pi * r * r * orc.kernel_w(r, h), 0, 2 * h,
+                        epsabs=0, epsrel=1e-13, limit=200)
+        assert abs(val - 1.0) <= 1e-10
+        assert orc.kernel_w(2 * h, h) == 0.0 and orc.kernel_f(2 * h, h) == 0.0
+        assert orc.kernel_w(2.5 * h, h) == 0.0
+        rs = np.linspace(0, 2 * h, 401)
+        w = np.array([orc.kernel_w(r, h) for r in rs])
+        assert np.all(np.diff(w) < 0)
+
+
+def test_wendland_gradient_is_derivative(orc):
+    h = 0.026
+    for q in np.linspace(0.05, 1.95, 39):
+        r = q * h
+        eps = 1e-6 * h
+        dw = (orc.kernel_w(r + eps, h) - orc.kernel_w(r - eps, h)) / (2 * eps)
+        assert abs(orc.kernel_f(r, h) * r - dw) <= 1e-6 * abs(dw) + 1e-9
+
+
+def test_wendland_lattice_sum(orc):
+    g = _golden("kernel_lattice_sum.txt")
+    hq = float(g["h_over_dp"][0])
+    s, cnt = 0.0, 0
+    for i in range(-3, 4):
+        for j in range(-3, 4):
+            for k in range(-3, 4):
+                r = math.sqrt(i * i + j * j + k * k)
+                if r < 2 * hq:
+                    s += orc.kernel_w(r, hq)
+                    cnt += 1
+    assert cnt == int(g["points"][0])
+    assert abs(s - float(g["sum"][0])) <= float(g["tol"][0])
+
+
+def test_tait_eos_closed_forms(orc):
+    p = cases.base_params(0.02)
+    pr0, c0 = orc.eos(p, p["rho0"])
+    assert pr0 == 0.0
+    assert abs(c0 - 10 * math.sqrt(9.81 * 0.3)) < 1e-12
+    assert abs(p["c0"] - 17.155174) < 1e-6
+    B = p["c0"] ** 2 * p["rho0"] / 7.0
+    assert abs(B - 42042.857) < 1e-3
+    for rho in (990.0, 1000.0, 1003.0, 1030.0):
+        e = 1e-4
+        dpdr = (orc.eos(p, rho + e)[0] - orc.eos(p, rho - e)[0]) / (2 * e)
+        c = orc.eos(p, rho)[1]
+        assert abs(c * c - dpdr) <= 1e-6 * dpdr  # c = sqrt(dp/drho)
+
+
+def test_hydrostatic_initial_pressure(orc):
+    case = cases.case_c1()
+    p = case.params
+    st = case.state
+    fl = st["type"] == cases.FLUID
+    depth = 15 * p["dp"] - st["z"][fl].astype(np.float64)
+    rho = st["rho"][fl].astype(np.float64)
+    # the generator rounds rho to FP32; compare through that rounding
+    pr = np.array([orc.eos(p, r)[0] for r in rho])
+    want = p["rho0"] * 9.81 * np.maximum(depth, 0)
+    dpdrho = p["c0"] ** 2 * (rho / 1000.0) ** 6
+    err = np.abs(pr - want) - dpdrho * np.abs(rho) * 2.0 ** -24
+    assert np.all(err <= 1e-9 * (want + 1.0))
+    # and exactly in FP64 before the FP32 rounding
+    r64 = cases.hydrostatic_rho(p, depth)
+    pr64 = np.array([orc.eos(p, r)[0] for r in r64])
+    assert np.all(np.abs(pr64 - want) <= 1e-12 * np.maximum(want, 1.0) + 1e-9)
+
+
+# ------------------------------------------------------- momentum, continuity
+
+def test_zero_net_force_periodic(orc):
+    """Pairwise terms are antisymmetric: sum_i m (a_i - g) = 0 in a closed box."""
+    case = cases.periodic_block(9, 0.02, seed=3)
+    p = case.params
+    out = orc.interact_brute(p, case.state, box=p["box"])
+    g = np.array(p["g"])
+    a = np.stack([out["ax"], out["ay"], out["az"]], 1) - g
+    m = p["mass"]
+    net = m * a.sum(0)
+    scale = m * np.abs(a).sum()
+    assert np.all(np.abs(net) <= 1e-12 * scale)
+    assert np.abs(a).max() > 1.0  # forces are not trivially zero
+    assert out["npair"].min() > 40
+
+
+def test_zero_net_torque_free_blob(orc):
+    """Central pair forces conserve angular momentum: sum m r x (a - g) = 0."""
+    case = cases.random_cloud(600, 0.02, (0.12, 0.1, 0.11), seed=12)
+    p = case.params
+    out = orc.interact_brute(p, case.state)
+    st = orc.to_f64(case.state)
+    r = np.stack([st["x"], st["y"], st["z"]], 1)
+    a = np.stack([out["ax"], out["ay"], out["az"]], 1) - np.array(p["g"])
+    tq = (np.cross(r, a) * p["mass"]).sum(0)
+    scale = p["mass"] * (np.linalg.norm(r, axis=1) * np.linalg.norm(a, axis=1)).sum()
+    assert np.all(np.abs(tq) <= 1e-12 * scale)
+
+
+def test_galilean_invariance_and_uniform_velocity(orc):
+    case = cases.perturb(cases.small_tank(), 8)
+    st = {k: v.copy() for k, v in case.state.items()}
+    fl = st["type"] != cases.GHOST
+    for k in ("vx", "vy", "vz"):  # velocities on a coarse grid: shifts are exact
+        st[k] = (np.round(st[k] * 1024) / 1024).astype(np.float32)
+    p = case.params
+    base = orc.interact(p, orc.sort_state(p, st))
+    sh = {k: v.copy() for k, v in st.items()}
+    for k, u in (("vx", 0.25), ("vy", -0.5), ("vz", 0.125)):
+        sh[k] = (sh[k] + np.float32(u)).astype(np.float32)
+    moved = orc.interact(p, orc.sort_state(p, sh))
+    for k in ("ax", "ay", "az", "drho", "nu"):
+        assert np.array_equal(base[k], moved[k]), k
+    # uniform velocity: no compression (D = 0) and no viscosity
+    un = {k: v.copy() for k, v in st.items()}
+    for k in ("vx", "vy", "vz"):
+        un[k][:] = np.float32(0.3)
+    u = orc.interact(p, orc.sort_state(p, un))
+    rest = {k: v.copy() for k, v in st.items()}
+    for k in ("vx", "vy", "vz"):
+        rest[k][:] = 0
+    r0 = orc.interact(p, orc.sort_state(p, rest))
+    assert np.all(u["drho"] == 0.0) and np.all(u["nu"] == 0.0)
+    for k in ("ax", "ay", "az"):
+        assert np.array_equal(u[k], r0[k])
+    assert fl.any()
+
+
+def test_viscosity_only_for_approaching_pairs(orc):
+    """Two fluid particles: separating -> no viscous term; approaching -> the
+    viscous term adds a repulsion along r_ij."""
+    p = cases.base_params(0.02)
+    cases.set_grid(p, (-0.1, -0.1, -0.1), (0.1, 0.1, 0.1))
+    p["g"] = (0.0, 0.0, 0.0)
+    def pair_acc(v):
+        st = cases._make_state(np.array([[0.0, 0, 0], [0.03, 0, 0]]), np.zeros(2),
+                               np.full(2, 1000.0), np.array([[v, 0, 0], [-v, 0, 0]]))
+        return orc.interact(p, orc.sort_state(p, st))
+    sep, still, app = pair_acc(-0.2), pair_acc(0.0), pair_acc(0.2)
+    # at rho = rho0 the pressure is zero: only viscosity can act
+    assert sep["ax"][0] == 0.0 and still["ax"][0] == 0.0
+    assert app["ax"][0] < 0.0 and app["ax"][1] > 0.0  # pushes them apart
+    assert sep["nu"][0] > 0 and sep["nu"][0] == app["nu"][0]  # |mu| either way
+    assert sep["drho"][0] < 0 < app["drho"][0]  # continuity sign
+    assert sep["drho"][0] == sep["drho"][1]  # v_ij . grad_i W_ij is symmetric in i, j
+
+
+def test_hydrostatic_interior_in_equilibrium(orc):
+    """Water at rest: in the interior, pressure gradient balances gravity up to
+    the lattice discretisation of the kernel (a few per cent)."""
+    case = cases.case_c1()
+    p = case.params
+    srt = orc.sort_state(p, case.state)
+    acc = orc.interact(p, srt)
+    s = srt["state"]
+    dp, h = p["dp"], p["h"]
+    inner = ((s["type"] == cases.FLUID) & (s["z"] > 4 * h) & (s["z"] < 15 * dp - 4 * h)
+             & (s["x"] > 4 * h) & (s["x"] < 20 * dp - 4 * h)
+             & (s["y"] > 4 * h) & (s["y"] < 34 * dp - 4 * h))
+    assert inner.sum() > 300
+    a = np.stack([acc["ax"], acc["ay"], acc["az"]], 1)[inner]
+    assert np.abs(a).max() < 0.05 * 9.81
+    # with gravity switched off the same state accelerates upward by ~g
+    p2 = dict(p, g=(0.0, 0.0, 0.0))
+    acc2 = orc.interact(p2, srt)
+    assert np.all(np.abs(acc2["az"][inner] - 9.81) < 0.05 * 9.81)
+
+
+# ----------------------------------------------------------- dt, Verlet
+
+def test_dt_isolated_particle_closed_form(orc):
+    p = cases.base_params(0.02)
+    cases.set_grid(p, (-1, -1, -1), (1, 1, 1))
+    st = cases._make_state(np.array([[0.1, 0.2, 0.3]]), np.zeros(1), np.full(1, 1000.0))
+    r = orc.step(p, st, 0)
+    want = 0.2 * min(math.sqrt(p["h"] / 9.81), p["h"] / p["c0"])
+    assert abs(r["dt"] - want) <= 1e-15 * want
+    assert r["pairs"] == 0
+
+
+def test_free_fall_is_exact(orc):
+    """No neighbours: a = g, and the Verlet scheme (Euler steps included) is
+    exact for constant acceleration: r_n = r0 + v0 t + g t^2 / 2."""
+    p = cases.base_params(0.02)
+    cases.set_grid(p, (-1, -1, -1), (1, 1, 1))
+    st = cases._make_state(np.array([[0.1, 0.2, 0.3], [0.8, 0.8, 0.8]]), np.zeros(2),
+                           np.full(2, 1000.0), np.array([[0.5, -0.25, 1.0], [0, 0, 0]]))
+    s = orc.to_f64(st)
+    r0 = np.array([s["x"][0], s["y"][0], s["z"][0]])
+    v0 = np.array([s["vx"][0], s["vy"][0], s["vz"][0]])
+    t = 0.0
+    for n in range(100):
+        r = orc.step(p, s, n)
+        s = r["state"]
+        t += r["dt"]
+    i = int(np.nonzero(s["id"] == 0)[0][0])
+    want = r0 + v0 * t + 0.5 * np.array([0.0, 0.0, -9.81]) * t * t
+    got = np.array([s["x"][i], s["y"][i], s["z"][i]])
+    assert np.all(np.abs(got - want) <= 1e-12 * (1 + np.abs(want)))
+    assert abs(s["vz"][i] - (1.0 - 9.81 * t)) <= 1e-12
+
+
+def test_verlet_constant_rates_and_roles(orc):
+    """Constant rates: v_n = v0 + n dt a and rho_n = rho0 + n dt D for fluid;
+    boundary keeps r and v, updates rho; ghost is untouched."""
+    p = cases.base_params(0.02)
+    p["euler_every"] = 7
+    st = orc.to_f64(cases._make_state(np.array([[0.0, 0, 0], [1, 1, 1], [2, 2, 2]]),
+                                      np.array([0, 1, 2]), np.full(3, 1000.0),
+                                      np.array([[0.125, 0.25, 0.375]] * 3)))
+    acc = dict(ax=np.full(3, 0.5), ay=np.full(3, -1.0), az=np.full(3, 2.0),
+               drho=np.full(3, 3.0))
+    dtv = 1e-3
+    s = st
+    for n in range(30):
+        s = orc.verlet(p, s, 3, n, dtv, acc)
+    T = 30 * dtv
+    assert abs(s["vx"][0] - (0.125 + 0.5 * T)) < 1e-14
+    assert abs(s["rho"][0] - (1000 + 3 * T)) < 1e-11
+    assert abs(s["z"][0] - (0.375 * T + 0.5 * 2.0 * T * T)) < 1e-14
+    assert abs(s["rho"][1] - (1000 + 3 * T)) < 1e-11
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert s[k][1] == st[k][1]
+    for k in s:
+        assert np.array_equal(s[k][2:], st[k][2:]), k
+
+
+def test_verlet_second_order(orc):
+    """Pure leapfrog (Euler only at start) is second order: the error of a
+    harmonic oscillator at fixed time falls ~4x per halving of dt."""
+    p = cases.base_params(0.02)
+    p["euler_every"] = 1 << 30
+    w = 3.0
+    errs = []
+    for nsteps in (200, 400, 800):
+        dtv = 1.0 / nsteps
+        s = orc.to_f64(cases._make_state(np.array([[1.0, 0, 0]]), np.zeros(1), np.full(1, 1000.0)))
+        for n in range(nsteps):
+            acc = dict(ax=-w * w * s["x"], ay=np.zeros(1), az=np.zeros(1), drho=np.zeros(1))
+            s = orc.verlet(p, s, 1, n, dtv, acc)
+        errs.append(abs(s["vx"][0] - (-w * math.sin(w * 1.0))))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.3 < r1 < 4.7 and 3.3 < r2 < 4.7, errs
+
+
+def test_dt_at_rest_scales_with_dp(orc):
+    """At rest dt = CFL h / c_max (c from dp/drho at the deepest density), so
+    dt is proportional to dp up to that depth factor (Sec. 6 footnote)."""
+    out = []
+    for case in (cases.case_c1(), cases.small_tank(dp=0.01, nx=20, ny=8, nz=40, nfx=8, nfz=30)):
+        p = case.params
+        r = orc.step(p, case.state, 0)
+        rho_max = float(case.state["rho"][case.state["type"] == cases.FLUID].max())
+        e = 1e-4
+        c_max = math.sqrt((orc.eos(p, rho_max + e)[0] - orc.eos(p, rho_max - e)[0]) / (2 * e))
+        want = p["cfl"] * p["h"] / c_max
+        assert abs(r["dt_cfl"] - want) <= 1e-6 * want
+        out.append(r["dt_cfl"] / p["dp"])
+    assert abs(out[0] / out[1] - 1.0) < 2e-3
+
+
+def test_boundaries_fixed_and_counts_conserved(orc):
+    case = cases.small_tank()
+    p = case.params
+    s = orc.to_f64(case.state)
+    b0 = {k: s[k][s["type"] == cases.BOUNDARY] for k in ("x", "y", "z", "vx", "vy", "vz")}
+    ids0 = np.sort(s["id"][s["type"] == cases.BOUNDARY])
+    for n in range(12):
+        r = orc.step(p, s, n)
+        s = r["state"]
+        assert int(r["srt"]["counts"].sum()) == case.n
+    order = np.argsort(s["id"][s["type"] == cases.BOUNDARY])
+    assert np.array_equal(np.sort(s["id"][s["type"] == cases.BOUNDARY]), ids0)
+    for k, v in b0.items():
+        cur = s[k][s["type"] == cases.BOUNDARY][order]
+        ref = v[np.argsort(case.state["id"][case.state["type"] == cases.BOUNDARY])]
+        assert np.array_equal(cur, ref), k
+    assert not np.array_equal(s["rho"][s["type"] == cases.BOUNDARY], 1000.0)
