@@ -1,0 +1,211 @@
+/*
+ * sph.h - C ABI of libsph.so: one weakly-compressible SPH (WCSPH) time step of
+ * free-surface flow on one MI355X (gfx950) GPU, in hand-written HIP.
+ *
+ * The method is that of Valdez-Balderas, Dominguez, Rogers and Crespo,
+ * "Towards accelerating Smoothed Particle Hydrodynamics simulations for
+ * free-surface flows on multi-GPU clusters": per sub-domain, particles are
+ * binned in cubic cells of side 2h and radix-sorted by cell (Sec. 3.1), the
+ * pairwise sums of the SPH continuity and momentum equations are taken over
+ * the 27 surrounding cells (Sec. 3.2, Sec. 2.2), and the state is advanced by
+ * a second-order Verlet scheme with a CFL-limited time step (Sec. 3.3). The
+ * sort key also carries the sub-domain migration label of Sec. 4.2-4.3, so
+ * outgoing particles pack contiguously behind the in-domain ones, and the
+ * edge and halo strips of width 2h are whole x-layers of cells, hence
+ * contiguous index ranges of the sorted arrays.
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success or a negative SPH_E_* code. Nothing aborts and no
+ *    C++ exception crosses the ABI. sph_last_error() gives a message.
+ *  - Particle arrays are device pointers owned by the caller (structure of
+ *    arrays, FP32 unless noted). The context owns only its scratch memory,
+ *    allocated once in sph_create and released in sph_destroy; no entry
+ *    point allocates device memory after sph_create.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream except sph_get_* (which
+ *    synchronise it). One context serves one stream at a time: calls on a
+ *    context must not overlap on different streams.
+ *  - Units are SI. Host parameters are FP64 and are converted to FP32 once.
+ *
+ * Particle types (uint8): 0 fluid, 1 boundary (dynamic boundary particle,
+ * Sec. 2.3: same equations, position and velocity held fixed), 2 ghost
+ * (halo copy of a neighbouring sub-domain's edge, Sec. 4.2: a neighbour
+ * for others, never updated itself).
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1
+
+enum {
+    SPH_OK = 0,
+    SPH_E_INVALID_ARG = -1, /* null pointer, bad parameter, n out of range     */
+    SPH_E_CAPACITY = -2,    /* n larger than the capacity given to sph_create   */
+    SPH_E_KEY_BITS = -3,    /* cell grid needs more than 30 index bits          */
+    SPH_E_HIP = -4,         /* a HIP runtime call or kernel launch failed       */
+    SPH_E_STATE = -5        /* call order violated (e.g. interact before sort)  */
+};
+
+/* Status bits reported by sph_get_status (set on the device, sticky). */
+enum {
+    SPH_S_NONFINITE = 1u << 0,    /* non-finite position/velocity/density after an update */
+    SPH_S_DT = 1u << 1,           /* dt not finite or not positive                        */
+    SPH_S_RUN_OVERFLOW = 1u << 2, /* a 3-cell neighbour run held > 4095 particles: the
+                                     excess was skipped, results invalid                  */
+    SPH_S_EXCLUDED = 1u << 3      /* some particles lie outside the cell grid (label 3)   */
+};
+
+/* Run parameters. */
+typedef struct sph_params {
+    double dp;          /* lattice spacing (m)                                  */
+    double h;           /* smoothing length (m); cell side is 2h (Sec. 3.1)     */
+    double rho0;        /* reference density, 1000 kg/m^3 (Sec. 2.2)            */
+    double gamma;       /* Tait exponent; must be 7 (Sec. 2.2)                  */
+    double c0;          /* speed of sound at rho0 (m/s)                         */
+    double alpha;       /* artificial-viscosity coefficient (Sec. 2.2)          */
+    double eta_over_h;  /* eta / h in the viscosity denominator, 0.1 (Sec. 2.2) */
+    double cfl;         /* CFL number of the time step (Sec. 3.3)               */
+    double mass;        /* particle mass (kg), the same for every particle      */
+    double g[3];        /* gravity (m/s^2)                                      */
+    double origin[3];   /* lower corner of the cell grid (m)                    */
+    int32_t ncell[3];   /* cells per axis (grid incl. halo / margin layers)     */
+    int32_t euler_every;/* Verlet: an Euler step every this many steps (40)     */
+    int32_t slab_mode;  /* 1: sub-domain [slab_xlo, slab_xhi) with migration
+                           labels; the grid must then run from slab_xlo - 2h
+                           and hold (slab_xhi - slab_xlo)/2h + 2 x-layers       */
+    int32_t reserved_;  /* must be 0                                            */
+    double slab_xlo, slab_xhi;
+    uint32_t capacity;  /* maximum particle count of any call                   */
+    uint32_t reserved2_;
+} sph_params;
+
+/* Structure-of-arrays particle state; every pointer is a device array of
+ * at least n elements. v*p / rhop are the Verlet "previous" values. */
+typedef struct sph_soa {
+    float *x, *y, *z;
+    float *vx, *vy, *vz;
+    float *rho;
+    float *vxp, *vyp, *vzp;
+    float *rhop;
+    uint8_t *type;
+    int32_t *id;
+} sph_soa;
+
+/* Time derivatives from the interaction (device arrays of >= n floats).
+ * press and nu are optional (NULL: not written). */
+typedef struct sph_rates {
+    float *ax, *ay, *az; /* dv/dt (fluid; 0 for boundary and ghost)      */
+    float *arho;         /* drho/dt (fluid and boundary; 0 for ghost)    */
+    float *press;        /* Tait pressure p_i (all in-domain particles)  */
+    float *nu;           /* max_j |h v_ij.r_ij / (r_ij^2 + eta^2)|        */
+} sph_rates;
+
+/* Label counts and packing ranges of the last sort. Ranges are [first, end)
+ * indices of the sorted arrays. Layers are x-layers of cells: halo_lo = layer
+ * 0, edge_lo = layer 1, edge_hi = layer ncx-2, halo_hi = layer ncx-1 (in slab
+ * mode: the incoming ghost strips and the outgoing edge strips, Sec. 4.2). */
+typedef struct sph_counts {
+    uint32_t n_label[4]; /* 0 in domain, 1 moved left, 2 moved right, 3 outside grid */
+    uint32_t halo_lo[2];
+    uint32_t edge_lo[2];
+    uint32_t edge_hi[2];
+    uint32_t halo_hi[2];
+    uint32_t out_lo[2];   /* label-1 range */
+    uint32_t out_hi[2];   /* label-2 range */
+    uint32_t excluded[2]; /* label-3 range */
+} sph_counts;
+
+typedef struct sph_ctx sph_ctx;
+
+/* Library ABI version (SPH_ABI_VERSION). */
+int sph_abi_version(void);
+
+/* Message for a return code. Never NULL. */
+const char *sph_error_string(int code);
+
+/* Last error message recorded on ctx (empty string if none); ctx may be NULL
+ * for errors of sph_create. The pointer stays valid until the next call. */
+const char *sph_last_error(const sph_ctx *ctx);
+
+/* Validate params, bind the current HIP device and allocate all scratch for
+ * params->capacity particles (keys, values, radix histograms, cell tables,
+ * packed interaction inputs, rates, dt partials). On success *out receives
+ * the context. Errors: INVALID_ARG (bad params), KEY_BITS (grid needs more
+ * than 30 cell bits: label bits would not fit a uint32 key), HIP (allocation). */
+int sph_create(const sph_params *params, sph_ctx **out);
+
+/* Free the context and its scratch (waits for the device). NULL is a no-op. */
+void sph_destroy(sph_ctx *ctx);
+
+/* Bits of the linear cell index (smallest b with 2^b >= cells); keys are
+ * label << bits | cell. */
+int sph_cell_bits(const sph_ctx *ctx);
+
+/* Stable key-value LSD radix sort of n (uint32 key, int32 value) pairs on the
+ * low key_bits bits (1..32), 8-bit digits (Sec. 3.1 and 4.3: the paper's
+ * radix sort; equal keys keep their input order, as in the worked example of
+ * Sec. 4.3). Inputs are not modified; outputs must not alias inputs. */
+int sph_sort_kv(sph_ctx *ctx, const uint32_t *keys, const int32_t *vals, uint32_t *keys_out,
+                int32_t *vals_out, uint32_t n, int key_bits, void *stream);
+
+/* Sort step (Sec. 3.1, 4.2-4.3): cell key + migration label per particle,
+ * stable radix sort, reorder of every SoA array of `in` into `out`, cell
+ * begin/end tables over the label-0 prefix (an empty cell c has
+ * begin = end = first index with cell >= c), label counts and packing ranges.
+ * `in` and `out` must not share arrays. */
+int sph_sort(sph_ctx *ctx, const sph_soa *in, sph_soa *out, uint32_t n, void *stream);
+
+/* Interaction (Sec. 3.2, equations of Sec. 2.2, boundaries of Sec. 2.3) on the
+ * state that the last sph_sort on ctx wrote (same n, unmodified since):
+ * rates for every in-domain particle, the neighbour-pair count and the CFL
+ * time step (Sec. 3.3), which stays on the device (sph_get_dt). */
+int sph_interact(sph_ctx *ctx, const sph_soa *sorted, uint32_t n, const sph_rates *out,
+                 void *stream);
+
+/* Verlet update (Sec. 3.3) of the in-domain particles of `sorted` in place,
+ * with the rates in `rates` and the dt of the last sph_interact. `step` is
+ * the step counter (an Euler step when step % euler_every == 0). */
+int sph_update(sph_ctx *ctx, sph_soa *sorted, const sph_rates *rates, uint32_t n,
+               uint64_t step, void *stream);
+
+/* One whole time step: sph_sort(cur -> next), interaction into the context's
+ * own rate buffers, dt, Verlet update of next. On return `next` holds the new
+ * state (sorted); `cur` is left as it was. No host synchronisation. */
+int sph_step(sph_ctx *ctx, const sph_soa *cur, sph_soa *next, uint32_t n, uint64_t step,
+             void *stream);
+
+/* Readbacks (synchronise `stream`). */
+int sph_get_counts(sph_ctx *ctx, sph_counts *out, void *stream);
+int sph_get_dt(sph_ctx *ctx, float *dt, void *stream);
+int sph_get_pairs(sph_ctx *ctx, uint64_t *pairs, void *stream);
+int sph_get_status(sph_ctx *ctx, uint32_t *flags, void *stream);
+/* Neighbour pairs summed over every interaction since sph_create. */
+int sph_get_pair_total(sph_ctx *ctx, uint64_t *pairs, void *stream);
+
+/* Optional phase timing of sph_step with HIP events recorded on the step's
+ * stream (no host synchronisation inside the steps). sph_timing_begin creates
+ * 4 events for each of the next max_steps (<= 65536) calls of sph_step
+ * (0 switches timing off); these are runtime event objects, not device
+ * memory. sph_timing_read waits for the recorded steps and writes, per step,
+ * 3 durations in ms: sort (keys, radix passes, tables, reorder), interaction
+ * kernel, and dt reduction + Verlet update. *count receives the number of
+ * steps written. */
+int sph_timing_begin(sph_ctx *ctx, uint32_t max_steps);
+int sph_timing_read(sph_ctx *ctx, float *ms, uint32_t max_steps, uint32_t *count);
+
+/* Device-to-device copies of the last sort's sorted keys (n of them) and
+ * of the cell tables (ncells each) into caller buffers. */
+int sph_copy_keys(sph_ctx *ctx, uint32_t *keys_out, uint32_t n, void *stream);
+int sph_copy_cell_tables(sph_ctx *ctx, uint32_t *begin_out, uint32_t *end_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

@@ -1,0 +1,433 @@
+// C ABI of libsph.so (declared in include/sph.h): validation, context and
+// scratch management, and the order of kernel launches of each entry point.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "sph_internal.h"
+
+using namespace sph;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(sph_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(sph_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_create_err = buf;
+    return code;
+}
+
+int hip_fail(sph_ctx *c, hipError_t e, const char *what) {
+    return fail(c, SPH_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int cell_bits_for(uint64_t ncells) {
+    int b = 1;
+    while ((1ull << b) < ncells) b++;
+    return b;
+}
+
+bool soa_ok(const sph_soa *s) {
+    return s && s->x && s->y && s->z && s->vx && s->vy && s->vz && s->rho && s->vxp && s->vyp &&
+           s->vzp && s->rhop && s->type && s->id;
+}
+
+bool rates_ok(const sph_rates *r) { return r && r->ax && r->ay && r->az && r->arho; }
+
+int enter(sph_ctx *c) {
+    if (!c) return SPH_E_INVALID_ARG;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    return SPH_OK;
+}
+
+void free_events(sph_ctx *c) {
+    if (c->events) {
+        for (uint32_t k = 0; k < 4 * c->ev_slots; k++) (void)hipEventDestroy(c->events[k]);
+        delete[] c->events;
+    }
+    c->events = nullptr;
+    c->ev_slots = c->ev_used = 0;
+}
+
+void free_all(sph_ctx *c) {
+    free_events(c);
+    void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
+                    c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->pos4, c->vel4,
+                    c->rate, c->dt_part, c->pair_part, c->info};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sph_abi_version(void) { return SPH_ABI_VERSION; }
+
+const char *sph_error_string(int code) {
+    switch (code) {
+        case SPH_OK: return "ok";
+        case SPH_E_INVALID_ARG: return "invalid argument";
+        case SPH_E_CAPACITY: return "particle count exceeds the context capacity";
+        case SPH_E_KEY_BITS: return "cell grid too large for 32-bit keys with 2 label bits";
+        case SPH_E_HIP: return "HIP runtime error";
+        case SPH_E_STATE: return "entry points called out of order";
+        default: return "unknown error";
+    }
+}
+
+const char *sph_last_error(const sph_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int sph_create(const sph_params *p, sph_ctx **out) {
+    g_create_err.clear();
+    if (!p || !out) return fail(nullptr, SPH_E_INVALID_ARG, "null params or output pointer");
+    *out = nullptr;
+    if (!(p->dp > 0 && p->h > 0 && p->rho0 > 0 && p->c0 > 0 && p->alpha >= 0 &&
+          p->eta_over_h > 0 && p->cfl > 0 && p->mass > 0))
+        return fail(nullptr, SPH_E_INVALID_ARG, "physical parameters must be positive");
+    if (p->gamma != 7.0)
+        return fail(nullptr, SPH_E_INVALID_ARG, "gamma must be 7 (Tait law of the method)");
+    if (p->reserved_ != 0 || p->reserved2_ != 0)
+        return fail(nullptr, SPH_E_INVALID_ARG, "reserved fields must be zero");
+    for (int a = 0; a < 3; a++)
+        if (p->ncell[a] < 1 || !isfinite(p->origin[a]) || !isfinite(p->g[a]))
+            return fail(nullptr, SPH_E_INVALID_ARG, "bad grid or gravity on axis %d", a);
+    if (p->capacity < 1 || p->capacity > 0x7fffffffu)
+        return fail(nullptr, SPH_E_INVALID_ARG, "capacity must be in [1, 2^31-1]");
+    const uint64_t ncells = (uint64_t)p->ncell[0] * p->ncell[1] * p->ncell[2];
+    const int bits = cell_bits_for(ncells);
+    if (bits > 30)
+        return fail(nullptr, SPH_E_KEY_BITS, "grid of %llu cells needs %d bits (max 30)",
+                    (unsigned long long)ncells, bits);
+    const double cs = 2.0 * p->h;
+    if (p->slab_mode != 0 && p->slab_mode != 1)
+        return fail(nullptr, SPH_E_INVALID_ARG, "slab_mode must be 0 or 1");
+    if (p->slab_mode) {
+        const double w = (p->slab_xhi - p->slab_xlo) / cs;
+        if (!(w >= 1.0) || fabs(w - nearbyint(w)) > 1e-6 ||
+            fabs(p->origin[0] - (p->slab_xlo - cs)) > 1e-6 * cs ||
+            p->ncell[0] != (int32_t)nearbyint(w) + 2)
+            return fail(nullptr, SPH_E_INVALID_ARG,
+                        "slab mode needs origin_x = slab_xlo - 2h and ncell_x = width/2h + 2 "
+                        "with an integer width in cells");
+    }
+
+    sph_ctx *c = new (std::nothrow) sph_ctx();
+    if (!c) return fail(nullptr, SPH_E_HIP, "out of host memory");
+    c->prm = *p;
+    (void)hipGetDevice(&c->device);
+    c->capacity = p->capacity;
+    c->cell_bits = bits;
+    c->ncells = (uint32_t)ncells;
+
+    KParams &k = c->kp;
+    k.ox = (float)p->origin[0];
+    k.oy = (float)p->origin[1];
+    k.oz = (float)p->origin[2];
+    k.inv_cs = (float)(1.0 / cs);
+    k.ncx = p->ncell[0];
+    k.ncy = p->ncell[1];
+    k.ncz = p->ncell[2];
+    k.cell_bits = bits;
+    k.ncells = (uint32_t)ncells;
+    k.cell_mask = (1u << bits) - 1u;
+    k.slab_mode = p->slab_mode;
+    k.slab_xlo = (float)p->slab_xlo;
+    k.slab_xhi = (float)p->slab_xhi;
+    k.h = (float)p->h;
+    k.inv_h = (float)(1.0 / p->h);
+    k.r2max = (float)(4.0 * p->h * p->h);
+    const double eta = p->eta_over_h * p->h;
+    k.eta2 = (float)(eta * eta);
+    k.mass = (float)p->mass;
+    k.alpha = (float)p->alpha;
+    k.rho0 = (float)p->rho0;
+    k.inv_rho0 = (float)(1.0 / p->rho0);
+    k.B = (float)(p->c0 * p->c0 * p->rho0 / p->gamma);
+    k.c0 = (float)p->c0;
+    k.gx = (float)p->g[0];
+    k.gy = (float)p->g[1];
+    k.gz = (float)p->g[2];
+    const double aD = 21.0 / (16.0 * M_PI * p->h * p->h * p->h);
+    k.kgrad = (float)(-5.0 * aD / (p->h * p->h));
+    k.cfl = (float)p->cfl;
+    k.euler_every = p->euler_every;
+
+    const size_t cap = p->capacity;
+    c->max_tiles = (uint32_t)((cap + kSortTile - 1) / kSortTile);
+    c->max_iblocks = (uint32_t)((cap + kInteractThreads - 1) / kInteractThreads);
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, bytes)                                               \
+    do {                                                                \
+        if (e == hipSuccess) e = hipMalloc((void **)&(ptr), (bytes));   \
+    } while (0)
+    ALLOC(c->keys_a, cap * 4);
+    ALLOC(c->keys_b, cap * 4);
+    ALLOC(c->keys_sorted, cap * 4);
+    ALLOC(c->vals_a, cap * 4);
+    ALLOC(c->vals_b, cap * 4);
+    ALLOC(c->perm, cap * 4);
+    ALLOC(c->hist, (size_t)256 * c->max_tiles * 4);
+    ALLOC(c->digit_tot, 256 * 4);
+    ALLOC(c->cell_begin, (size_t)ncells * 4);
+    ALLOC(c->cell_end, (size_t)ncells * 4);
+    ALLOC(c->pos4, cap * sizeof(float4));
+    ALLOC(c->vel4, cap * sizeof(float4));
+    ALLOC(c->rate, cap * 4 * sizeof(float));
+    ALLOC(c->dt_part, (size_t)c->max_iblocks * 4);
+    ALLOC(c->pair_part, (size_t)c->max_iblocks * 4);
+    ALLOC(c->info, sizeof(DevInfo));
+#undef ALLOC
+    if (e == hipSuccess) e = hipMemset(c->info, 0, sizeof(DevInfo));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        fail(nullptr, SPH_E_HIP, "scratch allocation for %zu particles: %s", cap,
+             hipGetErrorString(e));
+        free_all(c);
+        delete c;
+        return SPH_E_HIP;
+    }
+    *out = c;
+    return SPH_OK;
+}
+
+void sph_destroy(sph_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_all(c);
+    delete c;
+}
+
+int sph_cell_bits(const sph_ctx *c) { return c ? c->cell_bits : SPH_E_INVALID_ARG; }
+
+int sph_sort_kv(sph_ctx *c, const uint32_t *keys, const int32_t *vals, uint32_t *keys_out,
+                int32_t *vals_out, uint32_t n, int key_bits, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    if (key_bits < 1 || key_bits > 32) return fail(c, SPH_E_INVALID_ARG, "key_bits must be 1..32");
+    if (n > 0 && (!keys || !vals || !keys_out || !vals_out))
+        return fail(c, SPH_E_INVALID_ARG, "null array");
+    if (n > 0 && ((const void *)keys == (const void *)keys_out ||
+                  (const void *)vals == (const void *)vals_out))
+        return fail(c, SPH_E_INVALID_ARG, "outputs must not alias inputs");
+    hipError_t e = radix_sort(c, keys, vals, keys_out, vals_out, n, key_bits, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "radix sort");
+    return SPH_OK;
+}
+
+static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n, hipStream_t s) {
+    hipError_t e = launch_keys(c->kp, *in, n, c->keys_a, c->vals_a, s);
+    if (e == hipSuccess) e = radix_sort(c, c->keys_a, c->vals_a, c->keys_sorted, c->perm, n,
+                                        c->cell_bits + 2, s);
+    if (e == hipSuccess) e = launch_tables(c, n, s);
+    if (e == hipSuccess) e = launch_gather(c, *in, *out, n, s);
+    if (e != hipSuccess) return hip_fail(c, e, "sort step");
+    c->sorted_n = n;
+    c->have_sort = true;
+    c->have_dt = false;
+    return SPH_OK;
+}
+
+int sph_sort(sph_ctx *c, const sph_soa *in, sph_soa *out, uint32_t n, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    if (!soa_ok(in) || !soa_ok(out)) return fail(c, SPH_E_INVALID_ARG, "null state array");
+    if (in->x == out->x || in->rho == out->rho || in->type == out->type || in->id == out->id)
+        return fail(c, SPH_E_INVALID_ARG, "in and out must not share arrays");
+    return do_sort(c, in, out, n, (hipStream_t)stream);
+}
+
+int sph_interact(sph_ctx *c, const sph_soa *sorted, uint32_t n, const sph_rates *out,
+                 void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!soa_ok(sorted) || !rates_ok(out)) return fail(c, SPH_E_INVALID_ARG, "null array");
+    if (!c->have_sort || n != c->sorted_n)
+        return fail(c, SPH_E_STATE, "sph_interact needs a preceding sph_sort of the same n");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_pack(c, *sorted, n, s);
+    if (e == hipSuccess) e = launch_interact(c, sorted->type, n, *out, s);
+    if (e != hipSuccess) return hip_fail(c, e, "interaction");
+    c->have_dt = true;
+    return SPH_OK;
+}
+
+int sph_update(sph_ctx *c, sph_soa *sorted, const sph_rates *rates, uint32_t n, uint64_t step,
+               void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!soa_ok(sorted) || !rates_ok(rates)) return fail(c, SPH_E_INVALID_ARG, "null array");
+    if (!c->have_dt || n != c->sorted_n)
+        return fail(c, SPH_E_STATE, "sph_update needs a preceding sph_interact of the same n");
+    hipError_t e = launch_update(c, *sorted, rates->ax, rates->ay, rates->az, rates->arho, n, step,
+                                 (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "update");
+    return SPH_OK;
+}
+
+int sph_step(sph_ctx *c, const sph_soa *cur, sph_soa *next, uint32_t n, uint64_t step,
+             void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    if (!soa_ok(cur) || !soa_ok(next)) return fail(c, SPH_E_INVALID_ARG, "null state array");
+    if (cur->x == next->x || cur->rho == next->rho || cur->type == next->type || cur->id == next->id)
+        return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t *ev = (c->events && c->ev_used < c->ev_slots) ? c->events + 4 * c->ev_used : nullptr;
+    if (ev) {
+        c->ev_used++;
+        (void)hipEventRecord(ev[0], s);
+    }
+    r = do_sort(c, cur, next, n, s);
+    if (r) return r;
+    if (ev) (void)hipEventRecord(ev[1], s);
+    const size_t cap = c->capacity;
+    sph_rates rt = {c->rate, c->rate + cap, c->rate + 2 * cap, c->rate + 3 * cap, nullptr, nullptr};
+    hipError_t e = launch_interact(c, next->type, n, rt, s, ev ? ev[2] : nullptr);
+    if (e == hipSuccess) e = launch_update(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, step, s);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    if (e != hipSuccess) return hip_fail(c, e, "step");
+    c->have_dt = true;
+    return SPH_OK;
+}
+
+static int read_info(sph_ctx *c, DevInfo *h, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(h, c->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "readback");
+    return SPH_OK;
+}
+
+int sph_get_counts(sph_ctx *c, sph_counts *out, void *stream) {
+    if (!out) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    memcpy(out->n_label, h.n_label, sizeof h.n_label);
+    memcpy(out->halo_lo, h.ranges + 0, 8);
+    memcpy(out->edge_lo, h.ranges + 2, 8);
+    memcpy(out->edge_hi, h.ranges + 4, 8);
+    memcpy(out->halo_hi, h.ranges + 6, 8);
+    memcpy(out->out_lo, h.ranges + 8, 8);
+    memcpy(out->out_hi, h.ranges + 10, 8);
+    memcpy(out->excluded, h.ranges + 12, 8);
+    return SPH_OK;
+}
+
+int sph_get_dt(sph_ctx *c, float *dt, void *stream) {
+    if (!dt) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    *dt = h.dt;
+    return SPH_OK;
+}
+
+int sph_get_pairs(sph_ctx *c, uint64_t *pairs, void *stream) {
+    if (!pairs) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    *pairs = h.pairs;
+    return SPH_OK;
+}
+
+int sph_get_pair_total(sph_ctx *c, uint64_t *pairs, void *stream) {
+    if (!pairs) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    *pairs = h.pairs_total;
+    return SPH_OK;
+}
+
+int sph_timing_begin(sph_ctx *c, uint32_t max_steps) {
+    int r = enter(c);
+    if (r) return r;
+    if (max_steps > 65536) return fail(c, SPH_E_INVALID_ARG, "max_steps must be <= 65536");
+    free_events(c);
+    if (max_steps == 0) return SPH_OK;
+    c->events = new (std::nothrow) hipEvent_t[4 * (size_t)max_steps];
+    if (!c->events) return fail(c, SPH_E_HIP, "out of host memory");
+    for (uint32_t k = 0; k < 4 * max_steps; k++) {
+        hipError_t e = hipEventCreate(&c->events[k]);
+        if (e != hipSuccess) {
+            for (uint32_t q = 0; q < k; q++) (void)hipEventDestroy(c->events[q]);
+            delete[] c->events;
+            c->events = nullptr;
+            return hip_fail(c, e, "hipEventCreate");
+        }
+    }
+    c->ev_slots = max_steps;
+    c->ev_used = 0;
+    return SPH_OK;
+}
+
+int sph_timing_read(sph_ctx *c, float *ms, uint32_t max_steps, uint32_t *count) {
+    int r = enter(c);
+    if (r) return r;
+    if (!count || (!ms && max_steps)) return fail(c, SPH_E_INVALID_ARG, "null output");
+    const uint32_t m = c->ev_used < max_steps ? c->ev_used : max_steps;
+    for (uint32_t k = 0; k < m; k++) {
+        hipEvent_t *ev = c->events + 4 * k;
+        hipError_t e = hipEventSynchronize(ev[3]);
+        for (int q = 0; q < 3 && e == hipSuccess; q++) e = hipEventElapsedTime(&ms[3 * k + q], ev[q], ev[q + 1]);
+        if (e != hipSuccess) return hip_fail(c, e, "event timing");
+    }
+    *count = m;
+    return SPH_OK;
+}
+
+int sph_get_status(sph_ctx *c, uint32_t *flags, void *stream) {
+    if (!flags) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    *flags = h.flags;
+    return SPH_OK;
+}
+
+int sph_copy_keys(sph_ctx *c, uint32_t *keys_out, uint32_t n, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!keys_out && n) return fail(c, SPH_E_INVALID_ARG, "null output");
+    if (!c->have_sort || n > c->sorted_n) return fail(c, SPH_E_STATE, "no sort of that size yet");
+    if (n == 0) return SPH_OK;
+    hipError_t e = hipMemcpyAsync(keys_out, c->keys_sorted, (size_t)n * 4,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? SPH_OK : hip_fail(c, e, "copy keys");
+}
+
+int sph_copy_cell_tables(sph_ctx *c, uint32_t *begin_out, uint32_t *end_out, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!begin_out || !end_out) return fail(c, SPH_E_INVALID_ARG, "null output");
+    if (!c->have_sort) return fail(c, SPH_E_STATE, "no sort yet");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(begin_out, c->cell_begin, (size_t)c->ncells * 4,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(end_out, c->cell_end, (size_t)c->ncells * 4, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? SPH_OK : hip_fail(c, e, "copy cell tables");
+}
+
+}  // extern "C"

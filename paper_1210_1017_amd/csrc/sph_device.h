@@ -1,0 +1,65 @@
+// Device helpers shared by the HIP kernels of libsph.so.
+#pragma once
+
+#include "sph_internal.h"
+
+namespace sph {
+
+// Tait equation of state (Sec. 2.2), gamma = 7, in FP32 without the
+// cancellation of (rho/rho0)^7 - 1 near rho0: with s = rho/rho0,
+// s^7 - 1 = (s - 1)(1 + s + ... + s^6), and rho - rho0 is exact in FP32.
+__device__ __forceinline__ float tait_p(const KParams &kp, float rho) {
+    const float e = (rho - kp.rho0) * kp.inv_rho0;
+    const float s = rho * kp.inv_rho0;
+    float q = s + 1.0f;
+    q = fmaf(q, s, 1.0f);
+    q = fmaf(q, s, 1.0f);
+    q = fmaf(q, s, 1.0f);
+    q = fmaf(q, s, 1.0f);
+    q = fmaf(q, s, 1.0f);
+    return kp.B * e * q;
+}
+
+// p / rho^2, the pressure factor of the symmetric momentum equation.
+__device__ __forceinline__ float tait_p_over_rho2(const KParams &kp, float rho) {
+    return tait_p(kp, rho) / (rho * rho);
+}
+
+// Sound speed c = sqrt(dp/drho) = c0 (rho/rho0)^3 for gamma = 7.
+__device__ __forceinline__ float sound_speed(const KParams &kp, float rho) {
+    const float s = rho * kp.inv_rho0;
+    return kp.c0 * (s * s * s);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over a block of NT threads (NT a multiple of 64).
+// s_w must hold NT/64 words of shared memory. Every thread must call it.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w,
+                                                    uint32_t *total = nullptr) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; k++) {
+        const uint32_t t = s_w[k];
+        if (k < w) pre += t;
+        tot += t;
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return pre + incl - v;
+}
+
+}  // namespace sph

@@ -1,0 +1,101 @@
+// Internal declarations shared by the HIP translation units of libsph.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sph.h"
+
+namespace sph {
+
+enum : uint8_t { kFluid = 0, kBoundary = 1, kGhost = 2 };
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix tile
+constexpr int kInteractThreads = 256;
+constexpr int kRunBits = 12;                          // offset bits of a neighbour entry
+constexpr uint32_t kRunMax = (1u << kRunBits) - 1u;
+
+// Constants of the step in the precision the kernels use (converted once).
+struct KParams {
+    float ox, oy, oz, inv_cs;
+    int32_t ncx, ncy, ncz, cell_bits;
+    uint32_t ncells, cell_mask;
+    int32_t slab_mode;
+    float slab_xlo, slab_xhi;
+    float h, inv_h, r2max, eta2, mass, alpha;
+    float rho0, inv_rho0, B, c0;
+    float gx, gy, gz;
+    float kgrad;  // -5 aD / h^2, aD = 21 / (16 pi h^3): grad W = kgrad (1 - q/2)^3 r_ij
+    float cfl;
+    int32_t euler_every;
+};
+
+// Device-resident results of the last sort / interaction.
+struct DevInfo {
+    uint32_t n_label[4];
+    uint32_t ranges[14];  // halo_lo, edge_lo, edge_hi, halo_hi, out_lo, out_hi, excluded
+    float dt;
+    uint32_t flags;
+    unsigned long long pairs;        // neighbour pairs of the last interaction
+    unsigned long long pairs_total;  // summed over every interaction since creation
+};
+
+}  // namespace sph
+
+struct sph_ctx {
+    sph_params prm;
+    sph::KParams kp;
+    int device = 0;
+    uint32_t capacity = 0;
+    int cell_bits = 0;
+    uint32_t ncells = 0;
+    uint32_t max_tiles = 0;
+    uint32_t max_iblocks = 0;
+    // scratch (device)
+    uint32_t *keys_a = nullptr, *keys_b = nullptr, *keys_sorted = nullptr;
+    int32_t *vals_a = nullptr, *vals_b = nullptr, *perm = nullptr;
+    uint32_t *hist = nullptr;       // 256 * max_tiles, digit-major
+    uint32_t *digit_tot = nullptr;  // 256
+    uint32_t *cell_begin = nullptr, *cell_end = nullptr;
+    float4 *pos4 = nullptr, *vel4 = nullptr;  // packed (x,y,z,p/rho^2), (vx,vy,vz,rho)
+    float *rate = nullptr;                    // 4 * capacity: ax, ay, az, arho
+    float *dt_part = nullptr;
+    uint32_t *pair_part = nullptr;
+    sph::DevInfo *info = nullptr;
+    // optional per-phase timing of sph_step (events: start, sorted, interacted, updated)
+    hipEvent_t *events = nullptr;
+    uint32_t ev_slots = 0, ev_used = 0;
+    // bookkeeping
+    uint32_t sorted_n = 0;
+    bool have_sort = false;
+    bool have_dt = false;
+    std::string err;
+};
+
+namespace sph {
+
+// sort.hip
+hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_t *keys,
+                       int32_t *vals, hipStream_t s);
+hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_in,
+                      uint32_t *keys_out, int32_t *vals_out, uint32_t n, int key_bits,
+                      hipStream_t s);
+hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s);
+hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
+                         hipStream_t s);
+hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s);
+
+// interact.hip
+hipError_t launch_interact(sph_ctx *c, const uint8_t *type, uint32_t n, const sph_rates &out,
+                           hipStream_t s, hipEvent_t after_kernel = nullptr);
+
+// update.hip
+hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
+                         const float *az, const float *arho, uint32_t n, uint64_t step,
+                         hipStream_t s);
+
+}  // namespace sph

@@ -1,0 +1,60 @@
+// Verlet update of the WCSPH step (Sec. 3.3) with the dynamic-boundary rule
+// of Sec. 2.3: fluid advances position, velocity and density; boundary
+// particles advance density only; ghosts are not updated.
+#include "sph_device.h"
+
+namespace sph {
+
+// Leapfrog form of the second-order Verlet scheme, with an Euler step every
+// euler_every steps (step 0 included):
+//   Euler:    v' = v + dt a,        rho' = rho + dt D
+//   leapfrog: v' = v_prev + 2dt a,  rho' = rho_prev + 2dt D
+//   r' = r + dt v + dt^2 a / 2, then (v_prev, rho_prev) <- (v, rho).
+__global__ __launch_bounds__(256) void k_verlet(KParams kp, sph_soa st,
+                                                const float *__restrict__ ax,
+                                                const float *__restrict__ ay,
+                                                const float *__restrict__ az,
+                                                const float *__restrict__ arho,
+                                                DevInfo *__restrict__ info, int euler) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= info->n_label[0]) return;
+    const uint8_t t = st.type[k];
+    if (t == kGhost) return;
+    const float dt = info->dt;
+    const float rho = st.rho[k];
+    const float rn = euler ? fmaf(dt, arho[k], rho) : fmaf(2.0f * dt, arho[k], st.rhop[k]);
+    st.rhop[k] = rho;
+    st.rho[k] = rn;
+    bool ok = isfinite(rn);
+    if (t == kFluid) {
+        const float a[3] = {ax[k], ay[k], az[k]};
+        float *pos[3] = {st.x, st.y, st.z};
+        float *vel[3] = {st.vx, st.vy, st.vz};
+        float *velp[3] = {st.vxp, st.vyp, st.vzp};
+        const float hdt2 = 0.5f * dt * dt;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const float v = vel[d][k];
+            const float vn = euler ? fmaf(dt, a[d], v) : fmaf(2.0f * dt, a[d], velp[d][k]);
+            const float xn = pos[d][k] + fmaf(hdt2, a[d], dt * v);
+            pos[d][k] = xn;
+            velp[d][k] = v;
+            vel[d][k] = vn;
+            ok = ok && isfinite(vn) && isfinite(xn);
+        }
+    }
+    if (!ok) atomicOr(&info->flags, (uint32_t)SPH_S_NONFINITE);
+}
+
+hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
+                         const float *az, const float *arho, uint32_t n, uint64_t step,
+                         hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int E = c->kp.euler_every;
+    const int euler = E > 0 ? (step % (uint64_t)E == 0) : (step == 0);
+    hipLaunchKernelGGL(k_verlet, dim3((n + 255) / 256), dim3(256), 0, s, c->kp, st, ax, ay, az,
+                       arho, c->info, euler);
+    return hipGetLastError();
+}
+
+}  // namespace sph

@@ -1,0 +1,282 @@
+"""ctypes binding of libsph.so (include/sph.h): argument marshalling only.
+
+Every step of the path runs in the HIP kernels of the library; PyTorch is used
+for device memory (tensors) and streams. If the library is missing the
+binding raises: there is no other implementation to fall back on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sph.h")
+
+F32_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop")
+SOA_FIELDS = F32_FIELDS + ("type", "id")
+
+SPH_OK = 0
+STATUS_NONFINITE, STATUS_DT, STATUS_RUN_OVERFLOW, STATUS_EXCLUDED = 1, 2, 4, 8
+
+
+class SphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsph error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("dp", C.c_double), ("h", C.c_double), ("rho0", C.c_double),
+                ("gamma", C.c_double), ("c0", C.c_double), ("alpha", C.c_double),
+                ("eta_over_h", C.c_double), ("cfl", C.c_double), ("mass", C.c_double),
+                ("g", C.c_double * 3), ("origin", C.c_double * 3), ("ncell", C.c_int32 * 3),
+                ("euler_every", C.c_int32), ("slab_mode", C.c_int32), ("reserved_", C.c_int32),
+                ("slab_xlo", C.c_double), ("slab_xhi", C.c_double),
+                ("capacity", C.c_uint32), ("reserved2_", C.c_uint32)]
+
+
+class SoA(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in SOA_FIELDS]
+
+
+class Rates(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ax", "ay", "az", "arho", "press", "nu")]
+
+
+class Counts(C.Structure):
+    _fields_ = [("n_label", C.c_uint32 * 4), ("halo_lo", C.c_uint32 * 2),
+                ("edge_lo", C.c_uint32 * 2), ("edge_hi", C.c_uint32 * 2),
+                ("halo_hi", C.c_uint32 * 2), ("out_lo", C.c_uint32 * 2),
+                ("out_hi", C.c_uint32 * 2), ("excluded", C.c_uint32 * 2)]
+
+    def as_dict(self) -> dict:
+        return {k: list(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libsph.so (built by ``paper_1210_1017_amd.build``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1210_1017_amd.build` (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, u64 = C.c_void_p, C.c_int, C.c_uint32, C.c_uint64
+        P = C.POINTER
+        L.sph_abi_version.restype = i32
+        L.sph_error_string.argtypes = [i32]
+        L.sph_error_string.restype = C.c_char_p
+        L.sph_last_error.argtypes = [vp]
+        L.sph_last_error.restype = C.c_char_p
+        L.sph_create.argtypes = [P(Params), P(vp)]
+        L.sph_destroy.argtypes = [vp]
+        L.sph_destroy.restype = None
+        L.sph_cell_bits.argtypes = [vp]
+        L.sph_sort_kv.argtypes = [vp, vp, vp, vp, vp, u32, i32, vp]
+        L.sph_sort.argtypes = [vp, P(SoA), P(SoA), u32, vp]
+        L.sph_interact.argtypes = [vp, P(SoA), u32, P(Rates), vp]
+        L.sph_update.argtypes = [vp, P(SoA), P(Rates), u32, u64, vp]
+        L.sph_step.argtypes = [vp, P(SoA), P(SoA), u32, u64, vp]
+        L.sph_get_counts.argtypes = [vp, P(Counts), vp]
+        L.sph_get_dt.argtypes = [vp, P(C.c_float), vp]
+        L.sph_get_pairs.argtypes = [vp, P(C.c_uint64), vp]
+        L.sph_get_status.argtypes = [vp, P(C.c_uint32), vp]
+        L.sph_get_pair_total.argtypes = [vp, P(C.c_uint64), vp]
+        L.sph_timing_begin.argtypes = [vp, u32]
+        L.sph_timing_read.argtypes = [vp, P(C.c_float), u32, P(C.c_uint32)]
+        L.sph_copy_keys.argtypes = [vp, vp, u32, vp]
+        L.sph_copy_cell_tables.argtypes = [vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions that include/sph.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", txt)))
+
+
+def make_params(p: dict, capacity: int) -> Params:
+    s = Params()
+    for k in ("dp", "h", "rho0", "gamma", "c0", "alpha", "eta_over_h", "cfl", "mass"):
+        setattr(s, k, float(p[k]))
+    for a in range(3):
+        s.g[a] = float(p["g"][a])
+        s.origin[a] = float(p["origin"][a])
+        s.ncell[a] = int(p["ncell"][a])
+    s.euler_every = int(p["euler_every"])
+    s.slab_mode = int(p.get("slab_mode", 0))
+    s.slab_xlo = float(p.get("slab_xlo", 0.0))
+    s.slab_xhi = float(p.get("slab_xhi", 0.0))
+    s.capacity = int(capacity)
+    return s
+
+
+def _stream_ptr(stream) -> C.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _addr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+class DeviceState:
+    """A particle state as torch tensors on the GPU (SoA, one tensor per field)."""
+
+    def __init__(self, tensors: dict):
+        self.t = tensors
+
+    @classmethod
+    def empty(cls, capacity: int, device="cuda") -> "DeviceState":
+        import torch
+        t = {k: torch.empty(capacity, dtype=torch.float32, device=device) for k in F32_FIELDS}
+        t["type"] = torch.empty(capacity, dtype=torch.uint8, device=device)
+        t["id"] = torch.empty(capacity, dtype=torch.int32, device=device)
+        return cls(t)
+
+    @classmethod
+    def from_numpy(cls, st: dict, capacity: int | None = None, device="cuda") -> "DeviceState":
+        import torch
+        n = st["x"].shape[0]
+        cap = n if capacity is None else capacity
+        ds = cls.empty(max(cap, 1), device)
+        for k in SOA_FIELDS:
+            ds.t[k][:n].copy_(torch.from_numpy(np.ascontiguousarray(st[k])))
+        return ds
+
+    def to_numpy(self, n: int) -> dict:
+        return {k: self.t[k][:n].cpu().numpy().copy() for k in SOA_FIELDS}
+
+    def soa(self) -> SoA:
+        return SoA(*[self.t[k].data_ptr() for k in SOA_FIELDS])
+
+
+def make_rates(capacity: int, with_aux: bool = True, device="cuda") -> dict:
+    import torch
+    keys = ("ax", "ay", "az", "arho") + (("press", "nu") if with_aux else ())
+    return {k: torch.zeros(max(capacity, 1), dtype=torch.float32, device=device) for k in keys}
+
+
+def _rates_struct(r: dict) -> Rates:
+    return Rates(*[(r[k].data_ptr() if k in r and r[k] is not None else None)
+                   for k in ("ax", "ay", "az", "arho", "press", "nu")])
+
+
+class Context:
+    """One libsph context (scratch for ``capacity`` particles on the current GPU)."""
+
+    def __init__(self, params: dict, capacity: int):
+        self.L = lib()
+        self.params = dict(params)
+        self.capacity = int(capacity)
+        self._p = make_params(params, capacity)
+        h = C.c_void_p()
+        rc = self.L.sph_create(C.byref(self._p), C.byref(h))
+        if rc != SPH_OK:
+            raise SphError(rc, self.L.sph_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.sph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != SPH_OK:
+            raise SphError(rc, self.L.sph_last_error(self.h).decode())
+
+    @property
+    def cell_bits(self) -> int:
+        return int(self.L.sph_cell_bits(self.h))
+
+    def sort_kv(self, keys, vals, keys_out, vals_out, n: int, key_bits: int, stream=None):
+        self._check(self.L.sph_sort_kv(self.h, _addr(keys), _addr(vals), _addr(keys_out),
+                                       _addr(vals_out), n, key_bits, _stream_ptr(stream)))
+
+    def sort(self, cur: DeviceState, out: DeviceState, n: int, stream=None):
+        a, b = cur.soa(), out.soa()
+        self._check(self.L.sph_sort(self.h, C.byref(a), C.byref(b), n, _stream_ptr(stream)))
+
+    def interact(self, srt: DeviceState, n: int, rates: dict, stream=None):
+        a, r = srt.soa(), _rates_struct(rates)
+        self._check(self.L.sph_interact(self.h, C.byref(a), n, C.byref(r), _stream_ptr(stream)))
+
+    def update(self, srt: DeviceState, rates: dict, n: int, step: int, stream=None):
+        a, r = srt.soa(), _rates_struct(rates)
+        self._check(self.L.sph_update(self.h, C.byref(a), C.byref(r), n, step,
+                                      _stream_ptr(stream)))
+
+    def step(self, cur: DeviceState, nxt: DeviceState, n: int, step: int, stream=None):
+        a, b = cur.soa(), nxt.soa()
+        self._check(self.L.sph_step(self.h, C.byref(a), C.byref(b), n, step, _stream_ptr(stream)))
+
+    def counts(self, stream=None) -> dict:
+        c = Counts()
+        self._check(self.L.sph_get_counts(self.h, C.byref(c), _stream_ptr(stream)))
+        return c.as_dict()
+
+    def dt(self, stream=None) -> float:
+        v = C.c_float()
+        self._check(self.L.sph_get_dt(self.h, C.byref(v), _stream_ptr(stream)))
+        return float(v.value)
+
+    def pairs(self, stream=None) -> int:
+        v = C.c_uint64()
+        self._check(self.L.sph_get_pairs(self.h, C.byref(v), _stream_ptr(stream)))
+        return int(v.value)
+
+    def pair_total(self, stream=None) -> int:
+        v = C.c_uint64()
+        self._check(self.L.sph_get_pair_total(self.h, C.byref(v), _stream_ptr(stream)))
+        return int(v.value)
+
+    def timing_begin(self, max_steps: int):
+        self._check(self.L.sph_timing_begin(self.h, max_steps))
+
+    def timing_read(self, max_steps: int) -> np.ndarray:
+        """Per timed step: [sort ms, interaction-kernel ms, dt+update ms]."""
+        buf = (C.c_float * (3 * max(max_steps, 1)))()
+        cnt = C.c_uint32()
+        self._check(self.L.sph_timing_read(self.h, buf, max_steps, C.byref(cnt)))
+        return np.frombuffer(buf, dtype=np.float32, count=3 * cnt.value).reshape(-1, 3).copy()
+
+    def status(self, stream=None) -> int:
+        v = C.c_uint32()
+        self._check(self.L.sph_get_status(self.h, C.byref(v), _stream_ptr(stream)))
+        return int(v.value)
+
+    def sorted_keys(self, n: int, stream=None):
+        import torch
+        out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        self._check(self.L.sph_copy_keys(self.h, _addr(out), n, _stream_ptr(stream)))
+        return out[:n]
+
+    def cell_tables(self, stream=None):
+        import torch
+        nc = int(np.prod(self.params["ncell"]))
+        b = torch.empty(nc, dtype=torch.int32, device="cuda")
+        e = torch.empty(nc, dtype=torch.int32, device="cuda")
+        self._check(self.L.sph_copy_cell_tables(self.h, _addr(b), _addr(e), _stream_ptr(stream)))
+        return b, e
+
+
+def u32(t) -> np.ndarray:
+    """View a device int32 tensor (holding uint32 bits) as a host uint32 array."""
+    return t.cpu().numpy().view(np.uint32)
