@@ -60,15 +60,19 @@ def _traffic(kernel_src: str, launches_key: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(case, steps: int) -> dict:
+def cpu_baseline(case, seconds: float) -> dict:
+    """The FP64 oracle as it stands, full steps of the same workload from its
+    initial state, until about ``seconds`` of wall time have passed."""
     import oracle
     st = case.state
     pairs = 0
+    steps = 0
     t0 = time.perf_counter()
-    for s in range(steps):
-        r = oracle.step(case.params, st, s)
+    while steps < 3 or (time.perf_counter() - t0 < seconds and steps < 200):
+        r = oracle.step(case.params, st, steps)
         st = r["state"]
         pairs += r["pairs"]
+        steps += 1
     el = time.perf_counter() - t0
     return {"value": pairs / el, "unit": "pair interactions/s", "cores": oracle.threads(),
             "kind": "oracle",
@@ -77,14 +81,33 @@ def cpu_baseline(case, steps: int) -> dict:
             "steps_per_s": steps / el}
 
 
+def copy_probe(mib: int, reps: int) -> None:
+    """A plain device-to-device copy of known size, for scaling the HBM
+    counters of rocprofv3 (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "reps": reps}), flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=3,
-                    help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall time of the CPU-oracle baseline (0: skip)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter scaling) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe, 5)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU "
               "exchange of the method is not part of this build.", file=sys.stderr)
@@ -107,6 +130,7 @@ def main() -> int:
         a, b = b, a
     torch.cuda.synchronize()
     pairs0 = ctx.pair_total()
+    cand0 = ctx.candidate_total()
     ctx.timing_begin(args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -117,7 +141,7 @@ def main() -> int:
     elapsed = time.perf_counter() - t0
     pairs = ctx.pair_total() - pairs0
     phases = ctx.timing_read(args.steps)
-    cand = ctx.candidate_total() if hasattr(ctx, "candidate_total") else None
+    cand = ctx.candidate_total() - cand0
     status = ctx.status()
     counts = ctx.counts()
     ctx.timing_begin(0)
@@ -126,9 +150,7 @@ def main() -> int:
 
     t_int = float(phases[:, 1].mean()) * 1e-3
     pairs_per_launch = pairs / args.steps
-    flop = FLOP_PER_PAIR * pairs_per_launch
-    if cand is not None:
-        flop += FLOP_PER_CANDIDATE * (cand / args.steps)
+    flop = FLOP_PER_PAIR * pairs_per_launch + FLOP_PER_CANDIDATE * (cand / args.steps)
     achieved = flop / t_int / 1e12
     kernel_src = os.path.join(ROOT, "paper_1210_1017_amd", "csrc", "interact.hip")
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
@@ -136,6 +158,7 @@ def main() -> int:
             "traffic": _traffic(kernel_src, "k_interact:c2"),
             "kernel": "k_interact", "kernel_ms": t_int * 1e3,
             "flop_per_launch": flop, "pairs_per_launch": pairs_per_launch,
+            "candidates_per_launch": cand / args.steps,
             "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
             "hbm_gbs_algorithmic": BYTES_PER_PARTICLE_INTERACT * counts["n_label"][0] / t_int / 1e9}
     out = {
@@ -154,9 +177,9 @@ def main() -> int:
                      "dt_update": float(phases[:, 2].mean())},
         "roofline": roof,
     }
-    if args.cpu_steps > 0:
-        print(f"[bench] CPU oracle baseline: {args.cpu_steps} steps", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    if args.cpu_seconds > 0:
+        print(f"[bench] CPU oracle baseline: ~{args.cpu_seconds:.0f} s", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -81,7 +81,7 @@ typedef struct sph_params {
                            and hold (slab_xhi - slab_xlo)/2h + 2 x-layers       */
     int32_t reserved_;  /* must be 0                                            */
     double slab_xlo, slab_xhi;
-    uint32_t capacity;  /* maximum particle count of any call                   */
+    uint32_t capacity;  /* maximum particle count of any call, < 2^28           */
     uint32_t reserved2_;
 } sph_params;
 
@@ -97,13 +97,14 @@ typedef struct sph_soa {
     int32_t *id;
 } sph_soa;
 
-/* Time derivatives from the interaction (device arrays of >= n floats).
- * press and nu are optional (NULL: not written). */
+/* Time derivatives from the interaction (device arrays of >= n elements).
+ * press, nu and npair are optional (NULL: not written). */
 typedef struct sph_rates {
     float *ax, *ay, *az; /* dv/dt (fluid; 0 for boundary and ghost)      */
     float *arho;         /* drho/dt (fluid and boundary; 0 for ghost)    */
     float *press;        /* Tait pressure p_i (all in-domain particles)  */
     float *nu;           /* max_j |h v_ij.r_ij / (r_ij^2 + eta^2)|        */
+    uint32_t *npair;     /* number of neighbours j of i                  */
 } sph_rates;
 
 /* Label counts and packing ranges of the last sort. Ranges are [first, end)
@@ -187,6 +188,9 @@ int sph_get_pairs(sph_ctx *ctx, uint64_t *pairs, void *stream);
 int sph_get_status(sph_ctx *ctx, uint32_t *flags, void *stream);
 /* Neighbour pairs summed over every interaction since sph_create. */
 int sph_get_pair_total(sph_ctx *ctx, uint64_t *pairs, void *stream);
+/* Candidates (particles of the 27 cells) given the support test, summed over
+ * every interaction since sph_create. */
+int sph_get_candidate_total(sph_ctx *ctx, uint64_t *cands, void *stream);
 
 /* Optional phase timing of sph_step with HIP events recorded on the step's
  * stream (no host synchronisation inside the steps). sph_timing_begin creates

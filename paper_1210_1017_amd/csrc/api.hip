@@ -62,8 +62,8 @@ void free_events(sph_ctx *c) {
 void free_all(sph_ctx *c) {
     free_events(c);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
-                    c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->pos4, c->vel4,
-                    c->rate, c->dt_part, c->pair_part, c->info};
+                    c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->cell_blockmin, c->pos4, c->vel4,
+                    c->rate, c->dt_part, c->pair_part, c->cand_part, c->info};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -104,8 +104,8 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     for (int a = 0; a < 3; a++)
         if (p->ncell[a] < 1 || !isfinite(p->origin[a]) || !isfinite(p->g[a]))
             return fail(nullptr, SPH_E_INVALID_ARG, "bad grid or gravity on axis %d", a);
-    if (p->capacity < 1 || p->capacity > 0x7fffffffu)
-        return fail(nullptr, SPH_E_INVALID_ARG, "capacity must be in [1, 2^31-1]");
+    if (p->capacity < 1 || p->capacity >= (1u << 28))
+        return fail(nullptr, SPH_E_INVALID_ARG, "capacity must be in [1, 2^28)");
     const uint64_t ncells = (uint64_t)p->ncell[0] * p->ncell[1] * p->ncell[2];
     const int bits = cell_bits_for(ncells);
     if (bits > 30)
@@ -183,11 +183,13 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     ALLOC(c->digit_tot, 256 * 4);
     ALLOC(c->cell_begin, (size_t)ncells * 4);
     ALLOC(c->cell_end, (size_t)ncells * 4);
+    ALLOC(c->cell_blockmin, (size_t)((ncells + kCellScanBlock - 1) / kCellScanBlock) * 4);
     ALLOC(c->pos4, cap * sizeof(float4));
     ALLOC(c->vel4, cap * sizeof(float4));
     ALLOC(c->rate, cap * 4 * sizeof(float));
     ALLOC(c->dt_part, (size_t)c->max_iblocks * 4);
     ALLOC(c->pair_part, (size_t)c->max_iblocks * 4);
+    ALLOC(c->cand_part, (size_t)c->max_iblocks * 4);
     ALLOC(c->info, sizeof(DevInfo));
 #undef ALLOC
     if (e == hipSuccess) e = hipMemset(c->info, 0, sizeof(DevInfo));
@@ -298,7 +300,8 @@ int sph_step(sph_ctx *c, const sph_soa *cur, sph_soa *next, uint32_t n, uint64_t
     if (r) return r;
     if (ev) (void)hipEventRecord(ev[1], s);
     const size_t cap = c->capacity;
-    sph_rates rt = {c->rate, c->rate + cap, c->rate + 2 * cap, c->rate + 3 * cap, nullptr, nullptr};
+    sph_rates rt = {c->rate, c->rate + cap, c->rate + 2 * cap, c->rate + 3 * cap,
+                    nullptr, nullptr, nullptr};
     hipError_t e = launch_interact(c, next->type, n, rt, s, ev ? ev[2] : nullptr);
     if (e == hipSuccess) e = launch_update(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, step, s);
     if (ev) (void)hipEventRecord(ev[3], s);
@@ -357,6 +360,15 @@ int sph_get_pair_total(sph_ctx *c, uint64_t *pairs, void *stream) {
     int r = read_info(c, &h, stream);
     if (r) return r;
     *pairs = h.pairs_total;
+    return SPH_OK;
+}
+
+int sph_get_candidate_total(sph_ctx *c, uint64_t *cands, void *stream) {
+    if (!cands) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    *cands = h.cand_total;
     return SPH_OK;
 }
 

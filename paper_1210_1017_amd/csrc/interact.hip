@@ -6,7 +6,34 @@
 
 namespace sph {
 
-constexpr int kCap = 128;  // neighbour entries buffered per lane before a flush
+#ifndef SPH_INTERACT_CAP
+#define SPH_INTERACT_CAP 128
+#endif
+#ifndef SPH_TEST_UNROLL
+#define SPH_TEST_UNROLL 8
+#endif
+#ifndef SPH_COL_SLACK
+#define SPH_COL_SLACK 0
+#endif
+constexpr int kCap = SPH_INTERACT_CAP;   // neighbour entries buffered per lane before a flush
+// At each run boundary the whole wave flushes together if any lane has more
+// than kCap - kColSlack entries (a converged flush); inside a run a lane
+// flushes alone only if it reaches kCap (rare with a suitable slack).
+constexpr int kColSlack = SPH_COL_SLACK;
+constexpr int kUnroll = SPH_TEST_UNROLL; // candidates loaded together in the support test
+constexpr int kSlots = kCap + kUnroll;   // list slots (a group of candidates may overrun kCap)
+constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9 buffer resource: 32-bit raw dwords
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Workgroups are handed to the 8 XCDs round-robin; renumber them so that each
+// XCD works on one contiguous share of the sorted particles (neighbour data
+// then stays in that XCD's L2). A bijection of [0, nb).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    constexpr uint32_t X = 8;
+    const uint32_t q = nb / X, r = nb % X, x = b % X, k = b / X;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
 
 // One lane per particle i of the label-0 prefix (Sec. 3.2: one thread per
 // particle, neighbours in its own cell and the 26 adjacent ones). With an
@@ -15,38 +42,48 @@ constexpr int kCap = 128;  // neighbour entries buffered per lane before a flush
 //
 // Two phases per lane keep the wave converged on the expensive part:
 //   test:    every candidate of the 9 runs gets the FP32 support test
-//            |r_ij|^2 < 4h^2; hits are appended to the lane's own list in LDS
-//            as 16-bit (run, offset) entries;
+//            |r_ij|^2 < 4h^2 (groups of kUnroll bounds-checked buffer loads in
+//            flight); hits are appended to the lane's own list in LDS as
+//            16-bit (run, offset) entries;
 //   compute: the pair terms are evaluated for the listed neighbours only.
 // The list is flushed early if it fills (dense regions), so any neighbour
-// count is handled.
-__global__ __launch_bounds__(kInteractThreads) void k_interact(
-    KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4,
+// count is handled. The gradient constant -5 aD / h^2 and the mass are
+// applied once per particle after the sums.
+__global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
+    KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4, uint32_t n,
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
     const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend,
     DevInfo *__restrict__ info, float *__restrict__ oax, float *__restrict__ oay,
     float *__restrict__ oaz, float *__restrict__ orho, float *__restrict__ opress,
-    float *__restrict__ onu, float *__restrict__ dt_part, uint32_t *__restrict__ pair_part) {
-    __shared__ uint16_t s_list[kCap][kInteractThreads];
+    float *__restrict__ onu, uint32_t *__restrict__ onpair, float *__restrict__ dt_part,
+    uint32_t *__restrict__ pair_part, uint32_t *__restrict__ cand_part) {
+    __shared__ uint16_t s_list[kSlots][kInteractThreads];
     __shared__ uint32_t s_base[9][kInteractThreads];
     __shared__ float s_rdt[kInteractThreads / 64];
     __shared__ uint32_t s_rnp[kInteractThreads / 64];
+    __shared__ uint32_t s_rnc[kInteractThreads / 64];
 
     const int tid = threadIdx.x;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t n0 = info->n_label[0];
-    const uint32_t i = blockIdx.x * kInteractThreads + tid;
+    const uint32_t i = blk * kInteractThreads + tid;
     const bool inrange = i < n0;
     const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;
     float dtmin = INFINITY;
-    uint32_t npair = 0;
+    uint32_t npair = 0, ncand = 0;
 
     if (inrange) {
         const float4 pi = pos4[i], vi = vel4[i];
         const float rhoi = vi.w, Pi = pi.w;
         const float si = rhoi * kp.inv_rho0;
-        const float ci = kp.c0 * (si * si * si);
+        const float si3 = si * si * si;
+        const float ci = kp.c0 * si3;
         float axs = 0.f, ays = 0.f, azs = 0.f, drho = 0.f, nu = 0.f;
         if (ti != kGhost) {
+            const __amdgpu_buffer_rsrc_t rp =
+                __builtin_amdgcn_make_buffer_rsrc((void *)pos4, 0, (int)(n * 16u), kRsrcWord3);
+            const __amdgpu_buffer_rsrc_t rv =
+                __builtin_amdgcn_make_buffer_rsrc((void *)vel4, 0, (int)(n * 16u), kRsrcWord3);
             const uint32_t cell = sk[i] & kp.cell_mask;
             const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
             const int cz = (int)(cell % ncz);
@@ -55,29 +92,32 @@ __global__ __launch_bounds__(kInteractThreads) void k_interact(
             const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
             const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
             const float hinv2 = -0.5f * kp.inv_h;
-            const float vr_h = kp.h;
+            const float eta2 = kp.eta2, h = kp.h;
+            const float kvis = -kp.alpha * kp.h * kp.c0;  // Pi_ij = kvis (s_i^3 + s_j^3) vr R
 
             auto flush = [&](int cnt) {
+#pragma unroll 2
                 for (int k = 0; k < cnt; k++) {
                     const uint32_t e = s_list[k][tid];
                     const uint32_t j = s_base[e >> kRunBits][tid] + (e & kRunMax);
-                    const float4 pj = pos4[j];
-                    const float4 vj = vel4[j];
+                    const v4f pj = __builtin_amdgcn_raw_buffer_load_b128(rp, j * 16u, 0, 0);
+                    const v4f vj = __builtin_amdgcn_raw_buffer_load_b128(rv, j * 16u, 0, 0);
                     const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
                     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const float r = __builtin_amdgcn_sqrtf(r2);
-                    const float t = fmaf(hinv2, r, 1.0f);  // 1 - q/2
-                    const float F = kp.kgrad * (t * t * t);
+                    const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
+                    const float F = t * t * t;  // grad W / (kgrad r_ij)
                     const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
                     const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
                     drho = fmaf(F, vr, drho);
-                    const float mu = vr_h * vr * __builtin_amdgcn_rcpf(r2 + kp.eta2);
+                    // one reciprocal for mu = h vr / (r^2 + eta^2) and for the
+                    // viscous term -alpha cbar mu / rhobar
+                    const float rs = rhoi + vj.w;
+                    const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
+                    const float vR = vr * R;
+                    const float mu = (h * rs) * vR;
                     nu = fmaxf(nu, fabsf(mu));
                     const float sj = vj.w * kp.inv_rho0;
-                    const float cj = kp.c0 * (sj * sj * sj);
-                    const float visc =
-                        vr < 0.0f ? -kp.alpha * (ci + cj) * mu * __builtin_amdgcn_rcpf(rhoi + vj.w)
-                                  : 0.0f;
+                    const float visc = vr < 0.0f ? kvis * fmaf(sj * sj, sj, si3) * vR : 0.0f;
                     const float f = (Pi + pj.w + visc) * F;
                     axs = fmaf(f, dx, axs);
                     ays = fmaf(f, dy, ays);
@@ -85,8 +125,20 @@ __global__ __launch_bounds__(kInteractThreads) void k_interact(
                 }
             };
 
-            int cnt = 0;
+            // The list keeps i itself (found in its own run): the self pair has
+            // r_ij = v_ij = 0 and adds exactly zero to every sum and to nu, so
+            // it costs one list entry instead of a j != i test per candidate.
+            uint16_t *const lp0 = &s_list[0][tid];
+            uint16_t *const lpcap = &s_list[kCap][tid];
+            uint16_t *lp = lp0;  // next free slot of this lane's list (stride: one slot row)
+            uint32_t listed = 0;
             for (int col = 0; col < 9; col++) {
+                if (kColSlack > 0 && __any(lp > lpcap - (size_t)kColSlack * kInteractThreads)) {
+                    const int cnt = (int)((lp - lp0) / kInteractThreads);
+                    flush(cnt);
+                    listed += cnt;
+                    lp = lp0;
+                }
                 const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
                 uint32_t jb = 0, je = 0;
                 if (X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
@@ -99,31 +151,46 @@ __global__ __launch_bounds__(kInteractThreads) void k_interact(
                     je = jb + kRunMax + 1u;
                 }
                 s_base[col][tid] = jb;
-                for (uint32_t j = jb; j < je; j++) {
-                    const float4 pj = pos4[j];
-                    const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    if (r2 < kp.r2max && j != i) {
-                        s_list[cnt][tid] = (uint16_t)(((uint32_t)col << kRunBits) | (j - jb));
-                        npair++;
-                        if (++cnt == kCap) {
-                            flush(cnt);
-                            cnt = 0;
+                const uint32_t len = je - jb;
+                ncand += len;
+                const uint32_t voff = jb * 16u;
+                // k0 is the same for every lane (the group counter of the wave), so
+                // the list entry (col << 12) + k0 + u is wave-uniform as well.
+                for (uint32_t k0 = 0; k0 < len; k0 += kUnroll) {
+                    v4f q[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++)  // past the run: in-bounds data or 0
+                        q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++) {
+                        const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
+                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        if (k0 + u < len && r2 < kp.r2max) {
+                            *lp = (uint16_t)(((uint32_t)col << kRunBits) + k0 + u);
+                            lp += kInteractThreads;
                         }
+                    }
+                    if (lp >= lpcap) {
+                        const int cnt = (int)((lp - lp0) / kInteractThreads);
+                        flush(cnt);
+                        listed += cnt;
+                        lp = lp0;
                     }
                 }
             }
+            const int cnt = (int)((lp - lp0) / kInteractThreads);
             flush(cnt);
+            npair = listed + cnt - 1u;  // minus the self entry
         }
-        const float m = kp.mass;
+        const float m = kp.mass, mk = kp.mass * kp.kgrad;
         float ax = 0.f, ay = 0.f, az = 0.f, ar = 0.f;
         if (ti == kFluid) {
-            ax = fmaf(-m, axs, kp.gx);
-            ay = fmaf(-m, ays, kp.gy);
-            az = fmaf(-m, azs, kp.gz);
+            ax = fmaf(-mk, axs, kp.gx);
+            ay = fmaf(-mk, ays, kp.gy);
+            az = fmaf(-mk, azs, kp.gz);
         }
         if (ti != kGhost) {
-            ar = m * drho;
+            ar = mk * drho;
             // CFL limits (Sec. 3.3): h / (c_i + nu_i), and sqrt(h/|a_i|) for fluid
             dtmin = kp.h / (ci + nu);
             if (ti == kFluid) {
@@ -131,67 +198,79 @@ __global__ __launch_bounds__(kInteractThreads) void k_interact(
                 if (a2 > 0.0f) dtmin = fminf(dtmin, sqrtf(kp.h / sqrtf(a2)));
             }
         }
+        (void)m;
         oax[i] = ax;
         oay[i] = ay;
         oaz[i] = az;
         orho[i] = ar;
         if (opress) opress[i] = tait_p(kp, rhoi);
         if (onu) onu[i] = nu;
+        if (onpair) onpair[i] = npair;
     }
 
-    // block-local reduction of the dt limit and of the pair count
+    // block-local reduction of the dt limit, the pair and candidate counts
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         dtmin = fminf(dtmin, __shfl_xor(dtmin, o, 64));
         npair += __shfl_xor(npair, o, 64);
+        ncand += __shfl_xor(ncand, o, 64);
     }
     if ((tid & 63) == 0) {
         s_rdt[tid >> 6] = dtmin;
         s_rnp[tid >> 6] = npair;
+        s_rnc[tid >> 6] = ncand;
     }
     __syncthreads();
     if (tid == 0) {
         float d = s_rdt[0];
-        uint32_t np = s_rnp[0];
+        uint32_t np = s_rnp[0], nc = s_rnc[0];
         for (int k = 1; k < kInteractThreads / 64; k++) {
             d = fminf(d, s_rdt[k]);
             np += s_rnp[k];
+            nc += s_rnc[k];
         }
         dt_part[blockIdx.x] = d;
         pair_part[blockIdx.x] = np;
+        cand_part[blockIdx.x] = nc;
     }
 }
 
 // dt = CFL * min over blocks; total neighbour pairs.
 __global__ __launch_bounds__(256) void k_dt_final(KParams kp, const float *__restrict__ dt_part,
                                                   const uint32_t *__restrict__ pair_part,
+                                                  const uint32_t *__restrict__ cand_part,
                                                   uint32_t nblocks, DevInfo *__restrict__ info) {
     __shared__ float s_d[4];
-    __shared__ unsigned long long s_p[4];
+    __shared__ unsigned long long s_p[4], s_c[4];
     const int tid = threadIdx.x;
     float d = INFINITY;
-    unsigned long long np = 0;
+    unsigned long long np = 0, nc = 0;
     for (uint32_t b = tid; b < nblocks; b += 256) {
         d = fminf(d, dt_part[b]);
         np += pair_part[b];
+        nc += cand_part[b];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         d = fminf(d, __shfl_xor(d, o, 64));
         np += __shfl_xor(np, o, 64);
+        nc += __shfl_xor(nc, o, 64);
     }
     if ((tid & 63) == 0) {
         s_d[tid >> 6] = d;
         s_p[tid >> 6] = np;
+        s_c[tid >> 6] = nc;
     }
     __syncthreads();
     if (tid == 0) {
         d = fminf(fminf(s_d[0], s_d[1]), fminf(s_d[2], s_d[3]));
         np = s_p[0] + s_p[1] + s_p[2] + s_p[3];
+        nc = s_c[0] + s_c[1] + s_c[2] + s_c[3];
         const float dt = kp.cfl * d;
         info->dt = dt;
         info->pairs = np;
         info->pairs_total += np;
+        info->cand_total += nc;
         if (!(dt > 0.0f) || !(dt < INFINITY)) atomicOr(&info->flags, (uint32_t)SPH_S_DT);
     }
 }
@@ -200,12 +279,12 @@ hipError_t launch_interact(sph_ctx *c, const uint8_t *type, uint32_t n, const sp
                            hipStream_t s, hipEvent_t after_kernel) {
     const uint32_t nb = n == 0 ? 1 : (n + kInteractThreads - 1) / kInteractThreads;
     hipLaunchKernelGGL(k_interact, dim3(nb), dim3(kInteractThreads), 0, s, c->kp, c->pos4,
-                       c->vel4, type, c->keys_sorted, c->cell_begin, c->cell_end, c->info,
-                       out.ax, out.ay, out.az, out.arho, out.press, out.nu, c->dt_part,
-                       c->pair_part);
+                       c->vel4, n, type, c->keys_sorted, c->cell_begin, c->cell_end, c->info,
+                       out.ax, out.ay, out.az, out.arho, out.press, out.nu, out.npair, c->dt_part,
+                       c->pair_part, c->cand_part);
     if (after_kernel) (void)hipEventRecord(after_kernel, s);
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, c->kp, c->dt_part, c->pair_part, nb,
-                       c->info);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, c->kp, c->dt_part, c->pair_part,
+                       c->cand_part, nb, c->info);
     return hipGetLastError();
 }
 

@@ -227,27 +227,145 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
 }
 
 // ---------------------------------------------------- counts and ranges
-__device__ __forceinline__ uint32_t lower_bound_dev(const uint32_t *a, uint32_t n, uint32_t v) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (a[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+// Cell tables over the label-0 prefix of the sorted keys (Sec. 3.1 first
+// index of each cell; Sec. 4.4 first and last of a region) and label counts:
+//   k_fill:        begin[c] = EMPTY for every cell;
+//   k_mark:        thread k marks the label boundaries around k (label starts
+//                  lstart[l] = lower_bound(l << Bc)) and, for label 0, the first
+//                  and one-past-last index of k's cell;
+//   k_cells_min:   per block of cells, the minimum begin (EMPTY if all empty);
+//   k_cells_carry: suffix minimum over the blocks (n0 past the last one);
+//   k_cells_apply: an empty cell c gets begin = end = min over cells >= c of
+//                  begin, i.e. lower_bound(c) (begins rise with the cell index);
+//   k_counts:      label counts, and the packing ranges of x-layers 0, 1,
+//                  ncx-2, ncx-1 read off begin[] (each layer is one contiguous
+//                  range of the x-major order, Sec. 4.2-4.3).
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+__global__ __launch_bounds__(256) void k_fill(uint32_t *__restrict__ a, uint32_t n, uint32_t v) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
 }
 
-// Label counts from the label boundaries of the sorted keys, and the packing
-// ranges: x-layers 0, 1, ncx-2, ncx-1 of the x-major cell order are each one
-// contiguous range of the label-0 prefix (Sec. 4.2-4.3).
-__global__ void k_counts(KParams kp, const uint32_t *__restrict__ sk, uint32_t n,
-                         DevInfo *__restrict__ info) {
-    __shared__ uint32_t st[5];
-    const int t = threadIdx.x;
-    if (t < 4) st[t] = t == 0 ? 0u : lower_bound_dev(sk, n, (uint32_t)t << kp.cell_bits);
-    if (t == 4) st[4] = n;
+__global__ __launch_bounds__(256) void k_mark(KParams kp, const uint32_t *__restrict__ sk,
+                                              uint32_t n, DevInfo *__restrict__ info,
+                                              uint32_t *__restrict__ begin,
+                                              uint32_t *__restrict__ end) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > n) return;
+    const uint32_t kc = k < n ? sk[k] : 0u;
+    const int lprev = k == 0 ? -1 : (int)(sk[k - 1] >> kp.cell_bits);
+    const int lcur = k == n ? 4 : (int)(kc >> kp.cell_bits);
+    for (int l = lprev + 1; l <= lcur && l < 4; l++) info->lstart[l] = k;
+    if (k < n && lcur == 0) {
+        const uint32_t c = kc & kp.cell_mask;
+        if (k == 0 || sk[k - 1] != kc) begin[c] = k;
+        if (k + 1 == n || sk[k + 1] != kc) end[c] = k + 1;
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_suffix_min(uint32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_down(v, o, 64);
+        if (lane + o < 64) v = min(v, t);
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kCellScanThreads) void k_cells_min(const uint32_t *__restrict__ begin,
+                                                               uint32_t ncells,
+                                                               uint32_t *__restrict__ bmin) {
+    __shared__ uint32_t s_w[kCellScanThreads / 64];
+    const uint32_t base = blockIdx.x * (uint32_t)kCellScanBlock;
+    uint32_t m = kEmpty;
+#pragma unroll
+    for (int r = 0; r < kCellScanItems; r++) {
+        const uint32_t c = base + r * kCellScanThreads + threadIdx.x;
+        if (c < ncells) m = min(m, begin[c]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = m;
     __syncthreads();
-    const uint32_t n0 = st[1];
-    if (t < 4) info->n_label[t] = st[t + 1] - st[t];
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kCellScanThreads / 64; w++) m = min(m, s_w[w]);
+        bmin[blockIdx.x] = m;
+    }
+}
+
+// One block: bmin[b] <- min(n0, bmin[b+1], bmin[b+2], ...) (exclusive suffix).
+__global__ __launch_bounds__(256) void k_cells_carry(uint32_t *__restrict__ bmin, uint32_t nb,
+                                                     const DevInfo *__restrict__ info) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_carry;
+    const uint32_t n0 = info->lstart[1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_carry = n0;
+    __syncthreads();
+    // chunks of 256 blocks, from the last chunk down
+    const uint32_t nchunk = (nb + 255) / 256;
+    for (uint32_t ch = nchunk; ch-- > 0;) {
+        const uint32_t b = ch * 256 + tid;
+        const uint32_t v = b < nb ? bmin[b] : kEmpty;
+        const uint32_t wsuf = wave_suffix_min(v);  // min over lanes >= lane
+        if (lane == 0) s_w[w] = wsuf;
+        __syncthreads();
+        uint32_t later = s_carry;  // min over chunks after this one
+        for (int q = w + 1; q < 4; q++) later = min(later, s_w[q]);
+        const uint32_t nxt = __shfl_down(wsuf, 1, 64);
+        const uint32_t excl = min(later, lane < 63 ? nxt : kEmpty);
+        __syncthreads();
+        if (b < nb) bmin[b] = excl;
+        if (tid == 0) {
+            uint32_t all = s_carry;
+            for (int q = 0; q < 4; q++) all = min(all, s_w[q]);
+            s_carry = all;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kCellScanThreads) void k_cells_apply(uint32_t *__restrict__ begin,
+                                                                 uint32_t *__restrict__ end,
+                                                                 uint32_t ncells,
+                                                                 const uint32_t *__restrict__ carry) {
+    __shared__ uint32_t s_w[kCellScanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // thread t owns cells base + t*4 .. base + t*4 + 3 (contiguous, in order)
+    const uint32_t base = blockIdx.x * (uint32_t)kCellScanBlock + (uint32_t)tid * kCellScanItems;
+    uint32_t v[kCellScanItems];
+#pragma unroll
+    for (int r = 0; r < kCellScanItems; r++) v[r] = base + r < ncells ? begin[base + r] : kEmpty;
+    uint32_t tmin = kEmpty;
+#pragma unroll
+    for (int r = 0; r < kCellScanItems; r++) tmin = min(tmin, v[r]);
+    const uint32_t wsuf = wave_suffix_min(tmin);
+    if (lane == 0) s_w[w] = wsuf;
+    __syncthreads();
+    uint32_t after = carry[blockIdx.x];
+    for (int q = w + 1; q < kCellScanThreads / 64; q++) after = min(after, s_w[q]);
+    const uint32_t nxt = __shfl_down(wsuf, 1, 64);
+    after = min(after, lane < 63 ? nxt : kEmpty);  // min over cells after this thread's
+#pragma unroll
+    for (int r = kCellScanItems - 1; r >= 0; r--) {
+        if (v[r] == kEmpty) {
+            if (base + r < ncells) {
+                begin[base + r] = after;
+                end[base + r] = after;
+            }
+        } else {
+            after = v[r];
+        }
+    }
+}
+
+__global__ void k_counts(KParams kp, const uint32_t *__restrict__ begin, uint32_t n,
+                         DevInfo *__restrict__ info) {
+    const int t = threadIdx.x;
+    const uint32_t n0 = info->lstart[1];
+    if (t < 4) info->n_label[t] = (t < 3 ? info->lstart[t + 1] : n) - info->lstart[t];
     if (t < 8) {
         const uint32_t L = (uint32_t)kp.ncy * (uint32_t)kp.ncz;
         int lay;
@@ -258,44 +376,32 @@ __global__ void k_counts(KParams kp, const uint32_t *__restrict__ sk, uint32_t n
             default: lay = kp.ncx - 1; break;
         }
         lay = lay < 0 ? 0 : (lay >= kp.ncx ? kp.ncx - 1 : lay);
-        const uint32_t bound = (uint32_t)(lay + (t & 1)) * L;
-        info->ranges[t] = lower_bound_dev(sk, n0, bound);
+        const uint32_t c = (uint32_t)(lay + (t & 1)) * L;
+        info->ranges[t] = c < kp.ncells ? begin[c] : n0;
     }
     if (t == 8) {
-        info->ranges[8] = st[1];
-        info->ranges[9] = st[2];
-        info->ranges[10] = st[2];
-        info->ranges[11] = st[3];
-        info->ranges[12] = st[3];
-        info->ranges[13] = st[4];
-        if (st[4] > st[3]) atomicOr(&info->flags, (uint32_t)SPH_S_EXCLUDED);
+        info->ranges[8] = info->lstart[1];
+        info->ranges[9] = info->lstart[2];
+        info->ranges[10] = info->lstart[2];
+        info->ranges[11] = info->lstart[3];
+        info->ranges[12] = info->lstart[3];
+        info->ranges[13] = n;
+        if (n > info->lstart[3]) atomicOr(&info->flags, (uint32_t)SPH_S_EXCLUDED);
     }
-}
-
-// Cell begin/end tables over the label-0 prefix. Thread k (0..n0) owns the
-// gap between sorted particles k-1 and k: every cell c in (cell(k-1), cell(k)]
-// starts at k, every cell in [cell(k-1), cell(k)) ends at k. Each table entry
-// is written exactly once; empty cells get begin = end = lower_bound(c).
-__global__ __launch_bounds__(256) void k_cell_tables(KParams kp, const uint32_t *__restrict__ sk,
-                                                     const DevInfo *__restrict__ info,
-                                                     uint32_t nthreads,
-                                                     uint32_t *__restrict__ begin,
-                                                     uint32_t *__restrict__ end) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nthreads) return;
-    const uint32_t n0 = info->n_label[0];
-    if (k > n0) return;
-    const int64_t cprev = k == 0 ? -1 : (int64_t)(sk[k - 1] & kp.cell_mask);
-    const int64_t ccur = k == n0 ? (int64_t)kp.ncells : (int64_t)(sk[k] & kp.cell_mask);
-    for (int64_t c = cprev + 1; c <= ccur && c < (int64_t)kp.ncells; c++) begin[c] = k;
-    for (int64_t c = cprev < 0 ? 0 : cprev; c < ccur; c++) end[c] = k;
 }
 
 hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, s, c->kp, c->keys_sorted, n, c->info);
-    const uint32_t nt = n + 1;
-    hipLaunchKernelGGL(k_cell_tables, dim3((nt + 255) / 256), dim3(256), 0, s, c->kp,
-                       c->keys_sorted, c->info, nt, c->cell_begin, c->cell_end);
+    const uint32_t nc = c->ncells;
+    const uint32_t nb = (nc + kCellScanBlock - 1) / kCellScanBlock;
+    hipLaunchKernelGGL(k_fill, dim3((nc + 255) / 256), dim3(256), 0, s, c->cell_begin, nc, kEmpty);
+    hipLaunchKernelGGL(k_mark, dim3((n + 1 + 255) / 256), dim3(256), 0, s, c->kp, c->keys_sorted,
+                       n, c->info, c->cell_begin, c->cell_end);
+    hipLaunchKernelGGL(k_cells_min, dim3(nb), dim3(kCellScanThreads), 0, s, c->cell_begin, nc,
+                       c->cell_blockmin);
+    hipLaunchKernelGGL(k_cells_carry, dim3(1), dim3(256), 0, s, c->cell_blockmin, nb, c->info);
+    hipLaunchKernelGGL(k_cells_apply, dim3(nb), dim3(kCellScanThreads), 0, s, c->cell_begin,
+                       c->cell_end, nc, c->cell_blockmin);
+    hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, s, c->kp, c->cell_begin, n, c->info);
     return hipGetLastError();
 }
 

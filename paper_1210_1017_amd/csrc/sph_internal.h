@@ -16,6 +16,9 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix tile
 constexpr int kInteractThreads = 256;
+constexpr int kCellScanThreads = 256;
+constexpr int kCellScanItems = 4;
+constexpr int kCellScanBlock = kCellScanThreads * kCellScanItems;  // cells per scan block
 constexpr int kRunBits = 12;                          // offset bits of a neighbour entry
 constexpr uint32_t kRunMax = (1u << kRunBits) - 1u;
 
@@ -36,12 +39,14 @@ struct KParams {
 
 // Device-resident results of the last sort / interaction.
 struct DevInfo {
+    uint32_t lstart[4];   // first sorted index with label >= l
     uint32_t n_label[4];
     uint32_t ranges[14];  // halo_lo, edge_lo, edge_hi, halo_hi, out_lo, out_hi, excluded
     float dt;
     uint32_t flags;
     unsigned long long pairs;        // neighbour pairs of the last interaction
     unsigned long long pairs_total;  // summed over every interaction since creation
+    unsigned long long cand_total;   // candidates tested, summed likewise
 };
 
 }  // namespace sph
@@ -61,10 +66,12 @@ struct sph_ctx {
     uint32_t *hist = nullptr;       // 256 * max_tiles, digit-major
     uint32_t *digit_tot = nullptr;  // 256
     uint32_t *cell_begin = nullptr, *cell_end = nullptr;
+    uint32_t *cell_blockmin = nullptr;  // per scan block of cells
     float4 *pos4 = nullptr, *vel4 = nullptr;  // packed (x,y,z,p/rho^2), (vx,vy,vz,rho)
     float *rate = nullptr;                    // 4 * capacity: ax, ay, az, arho
     float *dt_part = nullptr;
     uint32_t *pair_part = nullptr;
+    uint32_t *cand_part = nullptr;
     sph::DevInfo *info = nullptr;
     // optional per-phase timing of sph_step (events: start, sorted, interacted, updated)
     hipEvent_t *events = nullptr;

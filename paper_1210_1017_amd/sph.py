@@ -43,8 +43,11 @@ class SoA(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in SOA_FIELDS]
 
 
+RATE_FIELDS = ("ax", "ay", "az", "arho", "press", "nu", "npair")
+
+
 class Rates(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("ax", "ay", "az", "arho", "press", "nu")]
+    _fields_ = [(k, C.c_void_p) for k in RATE_FIELDS]
 
 
 class Counts(C.Structure):
@@ -89,6 +92,7 @@ def lib() -> C.CDLL:
         L.sph_get_pairs.argtypes = [vp, P(C.c_uint64), vp]
         L.sph_get_status.argtypes = [vp, P(C.c_uint32), vp]
         L.sph_get_pair_total.argtypes = [vp, P(C.c_uint64), vp]
+        L.sph_get_candidate_total.argtypes = [vp, P(C.c_uint64), vp]
         L.sph_timing_begin.argtypes = [vp, u32]
         L.sph_timing_read.argtypes = [vp, P(C.c_float), u32, P(C.c_uint32)]
         L.sph_copy_keys.argtypes = [vp, vp, u32, vp]
@@ -165,12 +169,15 @@ class DeviceState:
 def make_rates(capacity: int, with_aux: bool = True, device="cuda") -> dict:
     import torch
     keys = ("ax", "ay", "az", "arho") + (("press", "nu") if with_aux else ())
-    return {k: torch.zeros(max(capacity, 1), dtype=torch.float32, device=device) for k in keys}
+    r = {k: torch.zeros(max(capacity, 1), dtype=torch.float32, device=device) for k in keys}
+    if with_aux:
+        r["npair"] = torch.zeros(max(capacity, 1), dtype=torch.int32, device=device)
+    return r
 
 
 def _rates_struct(r: dict) -> Rates:
     return Rates(*[(r[k].data_ptr() if k in r and r[k] is not None else None)
-                   for k in ("ax", "ay", "az", "arho", "press", "nu")])
+                   for k in RATE_FIELDS])
 
 
 class Context:
@@ -245,6 +252,11 @@ class Context:
     def pair_total(self, stream=None) -> int:
         v = C.c_uint64()
         self._check(self.L.sph_get_pair_total(self.h, C.byref(v), _stream_ptr(stream)))
+        return int(v.value)
+
+    def candidate_total(self, stream=None) -> int:
+        v = C.c_uint64()
+        self._check(self.L.sph_get_candidate_total(self.h, C.byref(v), _stream_ptr(stream)))
         return int(v.value)
 
     def timing_begin(self, max_steps: int):

@@ -67,6 +67,8 @@ def interact_compare(p: dict, srt: dict, g: dict, sel=None, acc=None):
         err["p"] = relnorm(g["press"][idx][ng], acc["p"][ng])
     if "nu" in g:
         err["nu"] = relnorm(g["nu"][idx][ng], acc["nu"][ng])
+    if "npair" in g:  # same FP32 support test on both sides: exact
+        assert np.array_equal(g["npair"][idx][ng].astype(np.int64), acc["npair"][ng])
     # ghosts and non-fluid accelerations are exactly zero
     for k in ("ax", "ay", "az"):
         assert np.all(g[k][idx][~fl] == 0.0)

@@ -1,0 +1,131 @@
+"""GPU parity at the workloads' full sizes, through the C ABI.
+
+* 1.47M-particle obstacle dam break (the benchmark workload), in the launch
+  configuration that bench.py times (sph_step) and through the separate
+  entry points: sort products bit-exact, the full interaction against the
+  full FP64 oracle (normwise 1e-4, per-particle neighbour counts exact),
+  the updated state at sampled particles.
+* 8.8M-particle slab with ghosts and migrants: raw (key, id) pairs and the
+  whole sorted state, tables and packing ranges bit-exact; interaction on
+  sampled particles that the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1210_1017_amd import cases, sph
+from parity_util import TOL, announce, assert_sorted_equal, gpu_sort, interact_compare, ulp32
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return cases.perturb(cases.case_c2(), 6)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return cases.slab_c3()
+
+
+def _sample(n0, k, seed, types=None):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n0, size=min(k, n0), replace=False))
+
+
+def test_c2_sort_and_full_interaction(c2):
+    p, n = c2.params, c2.n
+    announce(f"c2 sort+interact n={n}")
+    ctx = sph.Context(p, n)
+    _, out = gpu_sort(ctx, c2.state, n)
+    rates = sph.make_rates(n)
+    ctx.interact(out, n, rates)
+    torch.cuda.synchronize()
+    srt = oracle.sort_state(p, c2.state)
+    assert_sorted_equal(out.to_numpy(n), srt, n)
+    b, e = ctx.cell_tables()
+    assert np.array_equal(sph.u32(b), srt["begin"]) and np.array_equal(sph.u32(e), srt["end"])
+    g = {k: v.cpu().numpy() for k, v in rates.items()}
+    err, acc = interact_compare(p, srt, g)
+    print("c2", err, flush=True)
+    for k, v in err.items():
+        assert v <= TOL, (k, v)
+    assert ctx.pairs() == int(acc["npair"].sum())
+    dt_ref = oracle.dt(p, srt, acc)
+    assert abs(ctx.dt() - dt_ref) <= 1e-4 * dt_ref
+
+
+def test_c2_step_sampled(c2):
+    """sph_step (the benchmark's call) against the oracle's step on sampled particles."""
+    p, n = c2.params, c2.n
+    announce(f"c2 step sampled n={n}")
+    ctx = sph.Context(p, n)
+    cur = sph.DeviceState.from_numpy(c2.state, capacity=n)
+    nxt = sph.DeviceState.empty(n)
+    ctx.step(cur, nxt, n, 0)
+    torch.cuda.synchronize()
+    got = nxt.to_numpy(n)
+    dt = float(ctx.dt())
+    srt = oracle.sort_state(p, c2.state)
+    assert np.array_equal(got["id"], srt["state"]["id"])
+    n0 = int(srt["counts"][0])
+    sel = _sample(n0, 20000, 1)
+    acc = oracle.interact(p, srt, sel=sel)
+    s0 = {k: v[sel] for k, v in srt["state"].items()}
+    ref = oracle.verlet(p, s0, len(sel), 0, dt, acc)
+    fl = s0["type"] == cases.FLUID
+    for k in ("vx", "vy", "vz", "rho"):
+        inc_ref = ref[k] - s0[k]
+        inc_gpu = got[k][sel].astype(np.float64) - s0[k]
+        excess = np.maximum(np.abs(inc_gpu - inc_ref) - ulp32(ref[k]), 0.0)
+        assert np.linalg.norm(excess) <= 1e-3 * np.linalg.norm(inc_ref), k
+    for k in ("x", "y", "z"):
+        assert np.all(np.abs(got[k][sel] - ref[k]) <= 2 * ulp32(ref[k]) + 1e-3 * np.abs(ref[k] - s0[k]))
+    assert fl.sum() > 10000
+    assert ctx.status() & (sph.STATUS_NONFINITE | sph.STATUS_DT | sph.STATUS_RUN_OVERFLOW) == 0
+
+
+def test_c3_raw_pairs_sort_bit_exact(c3):
+    p, n = c3.params, c3.n
+    announce(f"c3 sort_kv raw pairs n={n}")
+    keys = oracle.keys(p, c3.state)
+    ids = c3.state["id"]
+    ctx = sph.Context(p, n)
+    kd = torch.from_numpy(keys.view(np.int32)).cuda()
+    vd = torch.from_numpy(ids).cuda()
+    ko = torch.empty_like(kd)
+    vo = torch.empty_like(vd)
+    ctx.sort_kv(kd, vd, ko, vo, n, ctx.cell_bits + 2)
+    torch.cuda.synchronize()
+    rk, rv = oracle.stable_sort_kv(keys, ids)
+    assert np.array_equal(ko.cpu().numpy().view(np.uint32), rk)
+    assert np.array_equal(vo.cpu().numpy(), rv)
+
+
+def test_c3_sort_state_ranges_and_sampled_interaction(c3):
+    p, n = c3.params, c3.n
+    announce(f"c3 sort+interact n={n}")
+    ctx = sph.Context(p, n)
+    _, out = gpu_sort(ctx, c3.state, n)
+    rates = sph.make_rates(n)
+    ctx.interact(out, n, rates)
+    torch.cuda.synchronize()
+    srt = oracle.sort_state(p, c3.state)
+    assert_sorted_equal(out.to_numpy(n), srt, n)
+    cnt = ctx.counts()
+    assert cnt["n_label"] == srt["counts"].tolist()
+    assert cnt["n_label"][1] == 20001 and cnt["n_label"][2] == 20001
+    flat = cnt["halo_lo"] + cnt["edge_lo"] + cnt["edge_hi"] + cnt["halo_hi"] + cnt["out_lo"] + \
+        cnt["out_hi"] + cnt["excluded"]
+    assert flat == srt["ranges"].tolist()
+    b, e = ctx.cell_tables()
+    assert np.array_equal(sph.u32(b), srt["begin"]) and np.array_equal(sph.u32(e), srt["end"])
+    n0 = int(srt["counts"][0])
+    sel = _sample(n0, 20000, 2)
+    g = {k: v.cpu().numpy() for k, v in rates.items()}
+    err, _ = interact_compare(p, srt, g, sel=sel)
+    print("c3", err, flush=True)
+    for k, v in err.items():
+        assert v <= TOL, (k, v)
