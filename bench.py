@@ -95,6 +95,112 @@ def copy_probe(mib: int, reps: int) -> None:
                       "reps": reps}), flush=True)
 
 
+def _by_id(arrs: dict, ids):
+    import numpy as np
+    order = np.argsort(ids, kind="stable")
+    return {k: v[order] for k, v in arrs.items()}
+
+
+def precision_report(args) -> dict:
+    """Precision variant: the same workload advanced by the plain FP32 path
+    (absolute FP32 positions), the cell + offset FP32 path and the FP64 path;
+    FP64 totals (mass, momentum, energy) along the run and per-quantity
+    differences against the FP64 run by particle id. (The comparison of one
+    cell-path step with the FP64 oracle on a 64-spacing cube of this workload
+    is a GPU test.)"""
+    import numpy as np
+    import torch
+
+    from paper_1210_1017_amd import cases, sph
+
+    t0 = time.perf_counter()
+    case = cases.case_c4() if args.report_case == "c4" else cases.case_c2()
+    p, n = case.params, case.n
+    print(f"[precision] {case.name}: {n} particles, generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    F = sph.FEATURE_CELL | sph.FEATURE_FP64
+    ctx = sph.Context(p, n, F)
+    t64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    # cell + offset state from the exact lattice positions
+    ca, cb = sph.CellState.empty(n), sph.CellState.empty(n)
+    ctx.cstate_from_positions(t64(case.pos64[:, 0]), t64(case.pos64[:, 1]), t64(case.pos64[:, 2]),
+                              ca, n)
+    for k in ("vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop", "type", "id"):
+        ca.t[k][:n].copy_(torch.from_numpy(np.ascontiguousarray(case.state[k])))
+    # FP64 state from the same positions
+    st64 = {k: case.state[k] for k in sph.SOA_FIELDS}
+    st64["x"], st64["y"], st64["z"] = case.pos64[:, 0], case.pos64[:, 1], case.pos64[:, 2]
+    da, db = sph.F64State.from_numpy(st64, capacity=n), sph.F64State.empty(n)
+    # plain FP32 state (positions rounded to FP32)
+    pa, pb = sph.DeviceState.from_numpy(case.state, capacity=n), sph.DeviceState.empty(n)
+    del st64
+    out = {"workload": case.name, "particles": n, "steps": args.report_steps,
+           "fp64_steps": args.fp64_steps, "series": []}
+
+    def plain_totals(s):
+        st = {k: s.t[k][:n].double() for k in ("x", "y", "z", "vx", "vy", "vz", "rho")}
+        ng = s.t["type"][:n] != cases.GHOST
+        m = p["mass"]
+        rho0, B = p["rho0"], p["c0"] ** 2 * p["rho0"] / 7.0
+        sr = st["rho"] / rho0
+        e = B * ((sr ** 6 - 1.0) / (6 * rho0) + (1.0 / st["rho"] - 1.0 / rho0))
+        tot = [m * ng.sum(), m * st["vx"][ng].sum(), m * st["vy"][ng].sum(), m * st["vz"][ng].sum(),
+               0.5 * m * (st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2)[ng].sum(),
+               m * 9.81 * st["z"][ng].sum(), m * e[ng].sum(), ng.sum()]
+        return [float(v) for v in tot]
+
+    ev = max(1, args.report_steps // 10)
+    tc = td = tp = 0.0
+    for s in range(args.report_steps + 1):
+        if s % ev == 0 or s == args.report_steps:
+            rec = {"step": s, "cell": ctx.ctotals(ca, n).tolist(), "plain": plain_totals(pa)}
+            if s <= args.fp64_steps:
+                rec["fp64"] = ctx.dtotals(da, n).tolist()
+            out["series"].append(rec)
+            print(f"[precision] step {s}: {rec}", file=sys.stderr, flush=True)
+        if s == args.report_steps:
+            break
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ctx.cstep(ca, cb, n, s)
+        ca, cb = cb, ca
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        ctx.step(pa, pb, n, s)
+        pa, pb = pb, pa
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        tc += b - a
+        tp += c - b
+        if s < args.fp64_steps:
+            ctx.dstep(da, db, n, s)
+            da, db = db, da
+            torch.cuda.synchronize()
+            td += time.perf_counter() - c
+    out["ms_per_step"] = {"cell": tc / args.report_steps * 1e3, "plain": tp / args.report_steps * 1e3,
+                          "fp64": td / max(args.fp64_steps, 1) * 1e3}
+    if args.fp64_steps == args.report_steps:
+        ref = _by_id(da.to_numpy(n), da.t["id"][:n].cpu().numpy())
+        x, y, z = ctx.cstate_positions(ca, n)
+        cst = ca.to_numpy(n)
+        cst.update({"x": x.cpu().numpy(), "y": y.cpu().numpy(), "z": z.cpu().numpy()})
+        cel = _by_id(cst, cst["id"])
+        pla = _by_id(pa.to_numpy(n), pa.t["id"][:n].cpu().numpy())
+        fl = ref["type"] == cases.FLUID
+        errs = {}
+        for name, st in (("cell", cel), ("plain", pla)):
+            e = {}
+            for k in ("x", "y", "z", "vx", "vy", "vz", "rho"):
+                d = st[k][fl].astype(np.float64) - ref[k][fl]
+                e[k] = {"rms": float(np.sqrt(np.mean(d * d))), "max": float(np.abs(d).max())}
+            disp = np.sqrt(sum((ref[k][fl] - case.pos64[ref["id"][fl], i]) ** 2
+                               for i, k in enumerate("xyz")))
+            e["rms_displacement_fp64"] = float(np.sqrt(np.mean(disp ** 2)))
+            errs[name] = e
+        out["vs_fp64"] = errs
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +210,15 @@ def main() -> int:
                     help="wall time of the CPU-oracle baseline (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter scaling) and exit")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="run the precision-variant report (cell + offset and FP64 paths) and exit")
+    ap.add_argument("--report-case", default="c4", choices=["c4", "c2"])
+    ap.add_argument("--report-steps", type=int, default=10000)
+    ap.add_argument("--fp64-steps", type=int, default=10000)
     args = ap.parse_args()
+    if args.precision_report:
+        print(json.dumps(precision_report(args)), flush=True)
+        return 0
     if args.copy_probe:
         copy_probe(args.copy_probe, 5)
         return 0

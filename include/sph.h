@@ -82,8 +82,14 @@ typedef struct sph_params {
     int32_t reserved_;  /* must be 0                                            */
     double slab_xlo, slab_xhi;
     uint32_t capacity;  /* maximum particle count of any call, < 2^28           */
-    uint32_t reserved2_;
+    uint32_t features;  /* SPH_F_* bits: extra scratch for the variant paths    */
 } sph_params;
+
+/* Feature bits of sph_params.features. */
+enum {
+    SPH_F_CELL = 1u << 0, /* cell + offset position path (sph_cstate, sph_c*)  */
+    SPH_F_FP64 = 1u << 1  /* FP64 reference path (sph_dstate, sph_d*)          */
+};
 
 /* Structure-of-arrays particle state; every pointer is a device array of
  * at least n elements. v*p / rhop are the Verlet "previous" values. */
@@ -207,6 +213,84 @@ int sph_timing_read(sph_ctx *ctx, float *ms, uint32_t max_steps, uint32_t *count
  * of the cell tables (ncells each) into caller buffers. */
 int sph_copy_keys(sph_ctx *ctx, uint32_t *keys_out, uint32_t n, void *stream);
 int sph_copy_cell_tables(sph_ctx *ctx, uint32_t *begin_out, uint32_t *end_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Precision variant. The same step (sort, interaction, dt, Verlet) on a state
+ * whose positions are an int32 linear cell index (the x-major cell of the sort
+ * key, cells of side cs = 2h, Sec. 3.1) plus an FP32 offset from the cell
+ * centre, |offset| <= h per axis: position = origin + (c + 1/2) cs + offset.
+ * Offsets keep FP32 resolution at the scale of a cell instead of the domain,
+ * so small displacements (dt v) are not rounded away over many steps. Pair
+ * separations are formed as (o_i - o_j) + (c_i - c_j) cs; the Verlet update
+ * moves a particle to the neighbouring cell when an offset leaves [-h, h).
+ * The time-step minimum and the global mass / momentum / energy sums are
+ * FP64 on the GPU. Needs SPH_F_CELL in params.features.
+ * ------------------------------------------------------------------------- */
+typedef struct sph_cstate {
+    int32_t *cell;       /* linear cell (x-major); -1 = outside the grid (excluded) */
+    float *ox, *oy, *oz; /* offset from the cell centre (m)                          */
+    float *vx, *vy, *vz;
+    float *rho;
+    float *vxp, *vyp, *vzp;
+    float *rhop;
+    uint8_t *type;
+    int32_t *id;
+} sph_cstate;
+
+/* Cell and offset of n FP64 device positions (other fields untouched):
+ * c = floor((x - o)/cs) in FP64, offset = (float)((x - o)/cs - c - 1/2) * cs;
+ * a position outside the grid gets cell -1 and offset 0. */
+int sph_cstate_from_positions(sph_ctx *ctx, const double *x, const double *y, const double *z,
+                              sph_cstate *out, uint32_t n, void *stream);
+/* FP64 positions of a cell state: o + (c + 1/2) cs + offset, per axis
+ * (NaN for cell -1). */
+int sph_cstate_positions(sph_ctx *ctx, const sph_cstate *s, double *x, double *y, double *z,
+                         uint32_t n, void *stream);
+/* Sort step (keys from the cells; labels as in sph_sort), reorder into out,
+ * cell tables, counts. */
+int sph_csort(sph_ctx *ctx, const sph_cstate *in, sph_cstate *out, uint32_t n, void *stream);
+/* Interaction on the state of the last sph_csort (rates as in sph_interact);
+ * the dt limits are reduced in FP64 (sph_get_dt64). */
+int sph_cinteract(sph_ctx *ctx, const sph_cstate *sorted, uint32_t n, const sph_rates *out,
+                  void *stream);
+/* Whole step on cell states: csort(cur -> next), interaction, FP64 dt,
+ * Verlet update with re-celling of next. */
+int sph_cstep(sph_ctx *ctx, const sph_cstate *cur, sph_cstate *next, uint32_t n, uint64_t step,
+              void *stream);
+/* FP64 totals over the in-domain non-ghost particles of a cell state:
+ * out[0] mass, out[1..3] momentum, out[4] kinetic energy, out[5] potential
+ * energy -m g.r, out[6] internal energy m e(rho) with
+ * e(rho) = B[(rho^(g-1) - rho0^(g-1))/((g-1) rho0^g) + 1/rho - 1/rho0]
+ * (the work of the Tait pressure), out[7] particle count. Synchronises. */
+int sph_ctotals(sph_ctx *ctx, const sph_cstate *s, uint32_t n, double *out, void *stream);
+
+/* FP64 reference path: the same step with every state array, the
+ * interaction and the update in FP64 (cell keys from the positions rounded to
+ * FP32, which only bins the particles). Needs SPH_F_FP64. */
+typedef struct sph_dstate {
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *rho;
+    double *vxp, *vyp, *vzp;
+    double *rhop;
+    uint8_t *type;
+    int32_t *id;
+} sph_dstate;
+
+typedef struct sph_drates {
+    double *ax, *ay, *az, *arho; /* as sph_rates, FP64 */
+} sph_drates;
+
+int sph_dsort(sph_ctx *ctx, const sph_dstate *in, sph_dstate *out, uint32_t n, void *stream);
+int sph_dinteract(sph_ctx *ctx, const sph_dstate *sorted, uint32_t n, const sph_drates *out,
+                  void *stream);
+int sph_dstep(sph_ctx *ctx, const sph_dstate *cur, sph_dstate *next, uint32_t n, uint64_t step,
+              void *stream);
+int sph_dtotals(sph_ctx *ctx, const sph_dstate *s, uint32_t n, double *out, void *stream);
+
+/* dt of the last sph_cinteract / sph_cstep / sph_dinteract / sph_dstep in
+ * FP64 (CFL times the FP64 minimum of the per-particle limits). */
+int sph_get_dt64(sph_ctx *ctx, double *dt, void *stream);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,9 @@ def lib():
         L.orc_dt.restype = C.c_double
         L.orc_verlet.argtypes = [pp, C.c_int64, C.c_int64, C.c_double, u8] + [d] * 15
         L.orc_threads.restype = C.c_int
+        L.orc_internal_energy.argtypes = [pp, C.c_double]
+        L.orc_internal_energy.restype = C.c_double
+        L.orc_totals.argtypes = [pp, C.c_int64, d, d, d, d, d, d, d, u8, d]
         _lib = L
     return _lib
 
@@ -211,6 +214,20 @@ def eos(p: dict, rho: float):
     pr, c = C.c_double(), C.c_double()
     lib().orc_eos(C.byref(make_params(p)), float(rho), C.byref(pr), C.byref(c))
     return pr.value, c.value
+
+
+def internal_energy(p: dict, rho: float) -> float:
+    return float(lib().orc_internal_energy(C.byref(make_params(p)), float(rho)))
+
+
+def totals(p: dict, st: dict) -> np.ndarray:
+    """[mass, px, py, pz, E_kin, E_pot, E_int, count] over non-ghost particles."""
+    s = to_f64(st) if st["x"].dtype != np.float64 else st
+    out = np.zeros(8)
+    lib().orc_totals(C.byref(make_params(p)), s["x"].shape[0], _d(s["x"]), _d(s["y"]), _d(s["z"]),
+                     _d(s["vx"]), _d(s["vy"]), _d(s["vz"]), _d(s["rho"]),
+                     _ptr(s["type"], C.c_uint8), _d(out))
+    return out
 
 
 def interact(p: dict, srt: dict, sel: np.ndarray | None = None) -> dict:

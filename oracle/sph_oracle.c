@@ -525,3 +525,38 @@ void orc_verlet(const orc_params *p, int64_t n0, int64_t step, double dt,
         vx[i] = vn[0]; vy[i] = vn[1]; vz[i] = vn[2];
     }
 }
+
+/* ------------------------------------------------------ global totals */
+
+/* Internal energy per unit mass of the barotropic Tait fluid, the work of
+ * the pressure from rho0: e(rho) = int_{rho0}^{rho} p(r)/r^2 dr
+ *   = B [ (rho^(g-1) - rho0^(g-1)) / ((g-1) rho0^g) + 1/rho - 1/rho0 ]. */
+double orc_internal_energy(const orc_params *p, double rho)
+{
+    const double B = p->c0 * p->c0 * p->rho0 / p->gamma;
+    const double g = p->gamma;
+    return B * ((pow(rho, g - 1.0) - pow(p->rho0, g - 1.0)) / ((g - 1.0) * pow(p->rho0, g)) +
+                1.0 / rho - 1.0 / p->rho0);
+}
+
+/* Totals over the non-ghost particles with finite positions: out[0] mass,
+ * out[1..3] momentum, out[4] kinetic energy, out[5] potential energy
+ * -m g.r, out[6] internal energy m e(rho), out[7] count. */
+void orc_totals(const orc_params *p, int64_t n, const double *x, const double *y,
+                const double *z, const double *vx, const double *vy, const double *vz,
+                const double *rho, const uint8_t *type, double *out)
+{
+    for (int q = 0; q < 8; q++) out[q] = 0.0;
+    const double m = p->mass;
+    for (int64_t i = 0; i < n; i++) {
+        if (type[i] == T_GHOST || !isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i])) continue;
+        out[0] += m;
+        out[1] += m * vx[i];
+        out[2] += m * vy[i];
+        out[3] += m * vz[i];
+        out[4] += 0.5 * m * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+        out[5] += -m * (p->g[0] * x[i] + p->g[1] * y[i] + p->g[2] * z[i]);
+        out[6] += m * orc_internal_energy(p, rho[i]);
+        out[7] += 1.0;
+    }
+}

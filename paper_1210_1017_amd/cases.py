@@ -115,6 +115,7 @@ class Case:
     name: str
     params: dict
     state: dict
+    pos64: np.ndarray | None = None  # the exact (FP64) positions the FP32 state rounds
 
     @property
     def n(self) -> int:
@@ -179,7 +180,7 @@ def dam_break(dp: float, nx: int, ny: int, nz: int, nfx: int, nfz: int, *,
     rho = np.concatenate([np.full(len(bpos), params["rho0"]), frho])
     Lx, Ly, Lz = nx * dp, ny * dp, nz * dp
     set_grid(params, (-cs, -cs, -cs), (Lx + cs, Ly + cs, 1.5 * Lz))
-    return Case(name, params, _make_state(pos, typ, rho))
+    return Case(name, params, _make_state(pos, typ, rho), pos)
 
 
 def case_c1(seed: int = 1) -> Case:
@@ -194,6 +195,25 @@ def case_c2(jitter_seed: int = 3, obstacle_seed: int = 2) -> Case:
     return dam_break(0.004, 400, 168, 100, 100, 75, jitter_seed=jitter_seed,
                      obstacles=3, obstacle_seed=obstacle_seed, obstacle_side=30,
                      obstacle_height=100, name="dam_break_3obst_dp0.004")
+
+
+def case_c4(seed: int = 7, obstacle_seed: int = 2) -> Case:
+    """Dam break with three obstacles at dp = 0.0013 m: 308 x 514 x 231 = 36,570,072
+    fluid particles (the nominal "32M" case) plus walls and obstacles (~38.5M)."""
+    return dam_break(0.0013, 1231, 515, 308, 308, 231, jitter_seed=seed, obstacles=3,
+                     obstacle_seed=obstacle_seed, obstacle_side=92, obstacle_height=308,
+                     name="dam_break_3obst_dp0.0013")
+
+
+def sub_block(case: Case, lo, side: float, margin: float) -> tuple[np.ndarray, np.ndarray]:
+    """Indices of the particles inside the cube [lo, lo + side)^3 and of those
+    inside the same cube grown by ``margin`` (the block and its halo)."""
+    p = case.pos64 if case.pos64 is not None else np.stack(
+        [case.state["x"], case.state["y"], case.state["z"]], 1).astype(np.float64)
+    lo = np.asarray(lo, dtype=np.float64)
+    inner = np.all((p >= lo) & (p < lo + side), axis=1)
+    outer = np.all((p >= lo - margin) & (p < lo + side + margin), axis=1)
+    return np.nonzero(inner)[0], np.nonzero(outer)[0]
 
 
 def small_tank(dp: float = 0.02, nx: int = 24, ny: int = 10, nz: int = 12, nfx: int = 8,
@@ -267,7 +287,7 @@ def slab_c3(*, dp: float = 0.0013, width_cells: int = 25, ny_fluid: int = 515,
     set_grid(params, (xlo - cs, -cs, -cs), (xhi + cs, nyw * dp + cs, 1.5 * nz_wall * dp))
     params["slab_mode"] = 1
     params["slab_xlo"], params["slab_xhi"] = xlo, xhi
-    return Case(name, params, _make_state(pos, typ, rho, vel))
+    return Case(name, params, _make_state(pos, typ, rho, vel), pos)
 
 
 def small_slab(seed: int = 21) -> Case:
@@ -290,14 +310,15 @@ def perturb(case: Case, seed: int, vamp: float = 0.5, rho_rel: float = 0.005,
     st["rho"][sel] = (st["rho"][sel] * (1.0 + rng.uniform(-rho_rel, rho_rel, size=n))).astype(np.float32)
     for a, b in (("vxp", "vx"), ("vyp", "vy"), ("vzp", "vz"), ("rhop", "rho")):
         st[a] = st[b].copy()
-    return Case(case.name + f"+perturb{seed}", dict(case.params), st)
+    return Case(case.name + f"+perturb{seed}", dict(case.params), st, case.pos64)
 
 
 def shuffle(case: Case, seed: int) -> Case:
     """Same particles in a random storage order."""
     perm = _rng(seed).permutation(case.n)
     st = {k: v[perm].copy() for k, v in case.state.items()}
-    return Case(case.name + f"+shuffle{seed}", dict(case.params), st)
+    return Case(case.name + f"+shuffle{seed}", dict(case.params), st,
+                None if case.pos64 is None else case.pos64[perm].copy())
 
 
 def random_cloud(n: int, dp: float, extent, seed: int, types=(FLUID,)) -> Case:
@@ -311,7 +332,7 @@ def random_cloud(n: int, dp: float, extent, seed: int, types=(FLUID,)) -> Case:
     vel = rng.uniform(-0.5, 0.5, size=(n, 3))
     cs = 2.0 * params["h"]
     set_grid(params, (-cs, -cs, -cs), tuple(ext + cs))
-    return Case("random_cloud", params, _make_state(pos, typ, rho, vel))
+    return Case("random_cloud", params, _make_state(pos, typ, rho, vel), pos)
 
 
 def periodic_block(n_side: int, dp: float, seed: int, jitter: float = 0.15) -> Case:

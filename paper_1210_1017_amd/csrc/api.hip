@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "sph_internal.h"
@@ -61,9 +62,12 @@ void free_events(sph_ctx *c) {
 
 void free_all(sph_ctx *c) {
     free_events(c);
+    void *vptrs[] = {c->p64, c->drate, c->tot_part};
+    for (void *p : vptrs)
+        if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
                     c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->cell_blockmin, c->pos4, c->vel4,
-                    c->rate, c->dt_part, c->pair_part, c->cand_part, c->info};
+                    c->rate, c->info};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -99,8 +103,8 @@ int sph_create(const sph_params *p, sph_ctx **out) {
         return fail(nullptr, SPH_E_INVALID_ARG, "physical parameters must be positive");
     if (p->gamma != 7.0)
         return fail(nullptr, SPH_E_INVALID_ARG, "gamma must be 7 (Tait law of the method)");
-    if (p->reserved_ != 0 || p->reserved2_ != 0)
-        return fail(nullptr, SPH_E_INVALID_ARG, "reserved fields must be zero");
+    if (p->reserved_ != 0 || (p->features & ~(uint32_t)(SPH_F_CELL | SPH_F_FP64)) != 0)
+        return fail(nullptr, SPH_E_INVALID_ARG, "reserved fields and unknown feature bits must be zero");
     for (int a = 0; a < 3; a++)
         if (p->ncell[a] < 1 || !isfinite(p->origin[a]) || !isfinite(p->g[a]))
             return fail(nullptr, SPH_E_INVALID_ARG, "bad grid or gravity on axis %d", a);
@@ -167,7 +171,6 @@ int sph_create(const sph_params *p, sph_ctx **out) {
 
     const size_t cap = p->capacity;
     c->max_tiles = (uint32_t)((cap + kSortTile - 1) / kSortTile);
-    c->max_iblocks = (uint32_t)((cap + kInteractThreads - 1) / kInteractThreads);
     hipError_t e = hipSuccess;
 #define ALLOC(ptr, bytes)                                               \
     do {                                                                \
@@ -187,10 +190,14 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     ALLOC(c->pos4, cap * sizeof(float4));
     ALLOC(c->vel4, cap * sizeof(float4));
     ALLOC(c->rate, cap * 4 * sizeof(float));
-    ALLOC(c->dt_part, (size_t)c->max_iblocks * 4);
-    ALLOC(c->pair_part, (size_t)c->max_iblocks * 4);
-    ALLOC(c->cand_part, (size_t)c->max_iblocks * 4);
     ALLOC(c->info, sizeof(DevInfo));
+    c->features = p->features;
+    c->tot_blocks = (uint32_t)std::min<size_t>(1024, (cap + kTotThreads - 1) / kTotThreads);
+    ALLOC(c->tot_part, (size_t)8 * (c->tot_blocks + 1) * sizeof(double));
+    if (p->features & SPH_F_FP64) {
+        ALLOC(c->p64, cap * sizeof(double));
+        ALLOC(c->drate, 4 * cap * sizeof(double));
+    }
 #undef ALLOC
     if (e == hipSuccess) e = hipMemset(c->info, 0, sizeof(DevInfo));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -241,6 +248,7 @@ static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n
     c->sorted_n = n;
     c->have_sort = true;
     c->have_dt = false;
+    c->last_path = 0;
     return SPH_OK;
 }
 
@@ -259,7 +267,7 @@ int sph_interact(sph_ctx *c, const sph_soa *sorted, uint32_t n, const sph_rates 
     int r = enter(c);
     if (r) return r;
     if (!soa_ok(sorted) || !rates_ok(out)) return fail(c, SPH_E_INVALID_ARG, "null array");
-    if (!c->have_sort || n != c->sorted_n)
+    if (!c->have_sort || n != c->sorted_n || c->last_path != 0)
         return fail(c, SPH_E_STATE, "sph_interact needs a preceding sph_sort of the same n");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_pack(c, *sorted, n, s);
@@ -274,7 +282,7 @@ int sph_update(sph_ctx *c, sph_soa *sorted, const sph_rates *rates, uint32_t n, 
     int r = enter(c);
     if (r) return r;
     if (!soa_ok(sorted) || !rates_ok(rates)) return fail(c, SPH_E_INVALID_ARG, "null array");
-    if (!c->have_dt || n != c->sorted_n)
+    if (!c->have_dt || n != c->sorted_n || c->last_path != 0)
         return fail(c, SPH_E_STATE, "sph_update needs a preceding sph_interact of the same n");
     hipError_t e = launch_update(c, *sorted, rates->ax, rates->ay, rates->az, rates->arho, n, step,
                                  (hipStream_t)stream);
@@ -341,7 +349,17 @@ int sph_get_dt(sph_ctx *c, float *dt, void *stream) {
     DevInfo h;
     int r = read_info(c, &h, stream);
     if (r) return r;
-    *dt = h.dt;
+    if (!c->have_dt) return fail(c, SPH_E_STATE, "no interaction yet");
+    if (c->last_path != 0) {  // variant paths: the FP32 rounding of CFL * FP64 minimum
+        double m64;
+        memcpy(&m64, &h.dtmin64_bits, sizeof m64);
+        *dt = (float)((double)c->kp.cfl * m64);
+        return SPH_OK;
+    }
+    // the same FP32 product as the update kernel forms: CFL * min limit
+    float m;
+    memcpy(&m, &h.dtmin_bits, sizeof m);
+    *dt = c->kp.cfl * m;
     return SPH_OK;
 }
 
@@ -440,6 +458,190 @@ int sph_copy_cell_tables(sph_ctx *c, uint32_t *begin_out, uint32_t *end_out, voi
     if (e == hipSuccess)
         e = hipMemcpyAsync(end_out, c->cell_end, (size_t)c->ncells * 4, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? SPH_OK : hip_fail(c, e, "copy cell tables");
+}
+
+// ------------------------------------------------------------ variants
+
+static bool cstate_ok(const sph_cstate *s) {
+    return s && s->cell && s->ox && s->oy && s->oz && s->vx && s->vy && s->vz && s->rho && s->vxp &&
+           s->vyp && s->vzp && s->rhop && s->type && s->id;
+}
+
+static bool dstate_ok(const sph_dstate *s) {
+    return s && s->x && s->y && s->z && s->vx && s->vy && s->vz && s->rho && s->vxp && s->vyp &&
+           s->vzp && s->rhop && s->type && s->id;
+}
+
+static int need(sph_ctx *c, uint32_t feature, uint32_t n) {
+    int r = enter(c);
+    if (r) return r;
+    if (!(c->features & feature))
+        return fail(c, SPH_E_STATE, "this path needs feature bit %u in sph_params.features", feature);
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    return SPH_OK;
+}
+
+int sph_cstate_from_positions(sph_ctx *c, const double *x, const double *y, const double *z,
+                              sph_cstate *out, uint32_t n, void *stream) {
+    int r = need(c, SPH_F_CELL, n);
+    if (r) return r;
+    if (n && (!x || !y || !z || !out || !out->cell || !out->ox || !out->oy || !out->oz))
+        return fail(c, SPH_E_INVALID_ARG, "null array");
+    hipError_t e = launch_cell_from_pos(c, x, y, z, *out, n, (hipStream_t)stream);
+    return e == hipSuccess ? SPH_OK : hip_fail(c, e, "cells from positions");
+}
+
+int sph_cstate_positions(sph_ctx *c, const sph_cstate *st, double *x, double *y, double *z,
+                         uint32_t n, void *stream) {
+    int r = need(c, SPH_F_CELL, n);
+    if (r) return r;
+    if (n && (!x || !y || !z || !st || !st->cell || !st->ox || !st->oy || !st->oz))
+        return fail(c, SPH_E_INVALID_ARG, "null array");
+    hipError_t e = launch_pos_from_cell(c, *st, x, y, z, n, (hipStream_t)stream);
+    return e == hipSuccess ? SPH_OK : hip_fail(c, e, "positions from cells");
+}
+
+static int do_csort(sph_ctx *c, const sph_cstate *in, const sph_cstate *out, uint32_t n,
+                    hipStream_t s) {
+    hipError_t e = launch_keys_cell(c, *in, n, s);
+    if (e == hipSuccess) e = radix_sort(c, c->keys_a, c->vals_a, c->keys_sorted, c->perm, n,
+                                        c->cell_bits + 2, s);
+    if (e == hipSuccess) e = launch_tables(c, n, s);
+    if (e == hipSuccess) e = launch_gather_cell(c, *in, *out, n, s);
+    if (e != hipSuccess) return hip_fail(c, e, "cell sort step");
+    c->sorted_n = n;
+    c->have_sort = true;
+    c->have_dt = false;
+    c->last_path = 1;
+    return SPH_OK;
+}
+
+int sph_csort(sph_ctx *c, const sph_cstate *in, sph_cstate *out, uint32_t n, void *stream) {
+    int r = need(c, SPH_F_CELL, n);
+    if (r) return r;
+    if (!cstate_ok(in) || !cstate_ok(out)) return fail(c, SPH_E_INVALID_ARG, "null state array");
+    if (in->cell == out->cell || in->ox == out->ox || in->type == out->type)
+        return fail(c, SPH_E_INVALID_ARG, "in and out must not share arrays");
+    return do_csort(c, in, out, n, (hipStream_t)stream);
+}
+
+int sph_cinteract(sph_ctx *c, const sph_cstate *sorted, uint32_t n, const sph_rates *out,
+                  void *stream) {
+    int r = need(c, SPH_F_CELL, n);
+    if (r) return r;
+    if (!cstate_ok(sorted) || !rates_ok(out)) return fail(c, SPH_E_INVALID_ARG, "null array");
+    if (!c->have_sort || n != c->sorted_n || c->last_path != 1)
+        return fail(c, SPH_E_STATE, "sph_cinteract needs a preceding sph_csort of the same n");
+    hipError_t e = launch_interact_cell(c, *sorted, n, *out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "cell interaction");
+    c->have_dt = true;
+    return SPH_OK;
+}
+
+int sph_cstep(sph_ctx *c, const sph_cstate *cur, sph_cstate *next, uint32_t n, uint64_t step,
+              void *stream) {
+    int r = need(c, SPH_F_CELL, n);
+    if (r) return r;
+    if (!cstate_ok(cur) || !cstate_ok(next)) return fail(c, SPH_E_INVALID_ARG, "null state array");
+    if (cur->cell == next->cell || cur->ox == next->ox || cur->type == next->type)
+        return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
+    hipStream_t s = (hipStream_t)stream;
+    r = do_csort(c, cur, next, n, s);
+    if (r) return r;
+    const size_t cap = c->capacity;
+    sph_rates rt = {c->rate, c->rate + cap, c->rate + 2 * cap, c->rate + 3 * cap,
+                    nullptr, nullptr, nullptr};
+    hipError_t e = launch_interact_cell(c, *next, n, rt, s);
+    if (e == hipSuccess) e = launch_update_cell(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, step, s);
+    if (e != hipSuccess) return hip_fail(c, e, "cell step");
+    c->have_dt = true;
+    return SPH_OK;
+}
+
+int sph_ctotals(sph_ctx *c, const sph_cstate *st, uint32_t n, double *out, void *stream) {
+    int r = need(c, SPH_F_CELL, n);
+    if (r) return r;
+    if (!cstate_ok(st) || !out) return fail(c, SPH_E_INVALID_ARG, "null array");
+    hipError_t e = launch_totals_cell(c, *st, n, out, (hipStream_t)stream);
+    return e == hipSuccess ? SPH_OK : hip_fail(c, e, "cell totals");
+}
+
+static int do_dsort(sph_ctx *c, const sph_dstate *in, const sph_dstate *out, uint32_t n,
+                    hipStream_t s) {
+    hipError_t e = launch_keys_d(c, *in, n, s);
+    if (e == hipSuccess) e = radix_sort(c, c->keys_a, c->vals_a, c->keys_sorted, c->perm, n,
+                                        c->cell_bits + 2, s);
+    if (e == hipSuccess) e = launch_tables(c, n, s);
+    if (e == hipSuccess) e = launch_gather_d(c, *in, *out, n, s);
+    if (e != hipSuccess) return hip_fail(c, e, "FP64 sort step");
+    c->sorted_n = n;
+    c->have_sort = true;
+    c->have_dt = false;
+    c->last_path = 2;
+    return SPH_OK;
+}
+
+int sph_dsort(sph_ctx *c, const sph_dstate *in, sph_dstate *out, uint32_t n, void *stream) {
+    int r = need(c, SPH_F_FP64, n);
+    if (r) return r;
+    if (!dstate_ok(in) || !dstate_ok(out)) return fail(c, SPH_E_INVALID_ARG, "null state array");
+    if (in->x == out->x || in->rho == out->rho || in->type == out->type)
+        return fail(c, SPH_E_INVALID_ARG, "in and out must not share arrays");
+    return do_dsort(c, in, out, n, (hipStream_t)stream);
+}
+
+int sph_dinteract(sph_ctx *c, const sph_dstate *sorted, uint32_t n, const sph_drates *out,
+                  void *stream) {
+    int r = need(c, SPH_F_FP64, n);
+    if (r) return r;
+    if (!dstate_ok(sorted) || !out || !out->ax || !out->ay || !out->az || !out->arho)
+        return fail(c, SPH_E_INVALID_ARG, "null array");
+    if (!c->have_sort || n != c->sorted_n || c->last_path != 2)
+        return fail(c, SPH_E_STATE, "sph_dinteract needs a preceding sph_dsort of the same n");
+    hipError_t e = launch_interact_d(c, *sorted, n, *out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "FP64 interaction");
+    c->have_dt = true;
+    return SPH_OK;
+}
+
+int sph_dstep(sph_ctx *c, const sph_dstate *cur, sph_dstate *next, uint32_t n, uint64_t step,
+              void *stream) {
+    int r = need(c, SPH_F_FP64, n);
+    if (r) return r;
+    if (!dstate_ok(cur) || !dstate_ok(next)) return fail(c, SPH_E_INVALID_ARG, "null state array");
+    if (cur->x == next->x || cur->rho == next->rho || cur->type == next->type)
+        return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
+    hipStream_t s = (hipStream_t)stream;
+    r = do_dsort(c, cur, next, n, s);
+    if (r) return r;
+    const size_t cap = c->capacity;
+    sph_drates rt = {c->drate, c->drate + cap, c->drate + 2 * cap, c->drate + 3 * cap};
+    hipError_t e = launch_interact_d(c, *next, n, rt, s);
+    if (e == hipSuccess) e = launch_update_d(c, *next, rt, n, step, s);
+    if (e != hipSuccess) return hip_fail(c, e, "FP64 step");
+    c->have_dt = true;
+    return SPH_OK;
+}
+
+int sph_dtotals(sph_ctx *c, const sph_dstate *st, uint32_t n, double *out, void *stream) {
+    int r = need(c, SPH_F_FP64, n);
+    if (r) return r;
+    if (!dstate_ok(st) || !out) return fail(c, SPH_E_INVALID_ARG, "null array");
+    hipError_t e = launch_totals_d(c, *st, n, out, (hipStream_t)stream);
+    return e == hipSuccess ? SPH_OK : hip_fail(c, e, "FP64 totals");
+}
+
+int sph_get_dt64(sph_ctx *c, double *dt, void *stream) {
+    if (!dt) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    if (!c->have_dt || c->last_path == 0)
+        return fail(c, SPH_E_STATE, "no cell or FP64 interaction yet");
+    double m;
+    memcpy(&m, &h.dtmin64_bits, sizeof m);
+    *dt = c->prm.cfl * m;
+    return SPH_OK;
 }
 
 }  // extern "C"

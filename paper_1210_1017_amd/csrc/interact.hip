@@ -1,7 +1,7 @@
 // Particle interaction of the WCSPH step (Sec. 3.2) with the SPH continuity
 // and momentum equations, artificial viscosity and Tait equation of state of
-// Sec. 2.2 and the dynamic boundaries of Sec. 2.3; plus the per-block parts of
-// the CFL time-step reduction (Sec. 3.3).
+// Sec. 2.2 and the dynamic boundaries of Sec. 2.3; plus the CFL time-step
+// reduction (Sec. 3.3): block-local min, then one atomic min per block.
 #include "sph_device.h"
 
 namespace sph {
@@ -26,13 +26,28 @@ constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9 buffer resource: 32-bit ra
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+#ifndef SPH_XCD_CHUNK
+#define SPH_XCD_CHUNK 0
+#endif
 // Workgroups are handed to the 8 XCDs round-robin; renumber them so that each
-// XCD works on one contiguous share of the sorted particles (neighbour data
-// then stays in that XCD's L2). A bijection of [0, nb).
+// XCD works on contiguous stretches of the sorted particles (neighbour data
+// then stays in that XCD's L2). kXcdChunk = 0: one stretch per XCD; C > 1:
+// stretches of C blocks dealt to the XCDs in turn (load balance across a
+// domain whose cost varies along x). Both are bijections of [0, nb).
+constexpr uint32_t kXcdChunk = SPH_XCD_CHUNK;
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
     constexpr uint32_t X = 8;
-    const uint32_t q = nb / X, r = nb % X, x = b % X, k = b / X;
-    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+    if (kXcdChunk == 1) return b;
+    if (kXcdChunk == 0) {
+        const uint32_t q = nb / X, r = nb % X, x = b % X, k = b / X;
+        return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+    }
+    // full rounds of X*C blocks: XCD x takes the x-th stretch of C in each round
+    const uint32_t round = X * kXcdChunk;
+    const uint32_t full = nb / round * round;
+    if (b >= full) return b;  // the last partial round keeps the hardware order
+    const uint32_t x = b % X, k = b / X;  // k-th block that XCD x receives
+    return (k / kXcdChunk) * round + x * kXcdChunk + k % kXcdChunk;
 }
 
 // One lane per particle i of the label-0 prefix (Sec. 3.2: one thread per
@@ -55,8 +70,7 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
     const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend,
     DevInfo *__restrict__ info, float *__restrict__ oax, float *__restrict__ oay,
     float *__restrict__ oaz, float *__restrict__ orho, float *__restrict__ opress,
-    float *__restrict__ onu, uint32_t *__restrict__ onpair, float *__restrict__ dt_part,
-    uint32_t *__restrict__ pair_part, uint32_t *__restrict__ cand_part) {
+    float *__restrict__ onu, uint32_t *__restrict__ onpair) {
     __shared__ uint16_t s_list[kSlots][kInteractThreads];
     __shared__ uint32_t s_base[9][kInteractThreads];
     __shared__ float s_rdt[kInteractThreads / 64];
@@ -229,49 +243,14 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
             np += s_rnp[k];
             nc += s_rnc[k];
         }
-        dt_part[blockIdx.x] = d;
-        pair_part[blockIdx.x] = np;
-        cand_part[blockIdx.x] = nc;
-    }
-}
-
-// dt = CFL * min over blocks; total neighbour pairs.
-__global__ __launch_bounds__(256) void k_dt_final(KParams kp, const float *__restrict__ dt_part,
-                                                  const uint32_t *__restrict__ pair_part,
-                                                  const uint32_t *__restrict__ cand_part,
-                                                  uint32_t nblocks, DevInfo *__restrict__ info) {
-    __shared__ float s_d[4];
-    __shared__ unsigned long long s_p[4], s_c[4];
-    const int tid = threadIdx.x;
-    float d = INFINITY;
-    unsigned long long np = 0, nc = 0;
-    for (uint32_t b = tid; b < nblocks; b += 256) {
-        d = fminf(d, dt_part[b]);
-        np += pair_part[b];
-        nc += cand_part[b];
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        d = fminf(d, __shfl_xor(d, o, 64));
-        np += __shfl_xor(np, o, 64);
-        nc += __shfl_xor(nc, o, 64);
-    }
-    if ((tid & 63) == 0) {
-        s_d[tid >> 6] = d;
-        s_p[tid >> 6] = np;
-        s_c[tid >> 6] = nc;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        d = fminf(fminf(s_d[0], s_d[1]), fminf(s_d[2], s_d[3]));
-        np = s_p[0] + s_p[1] + s_p[2] + s_p[3];
-        nc = s_c[0] + s_c[1] + s_c[2] + s_c[3];
-        const float dt = kp.cfl * d;
-        info->dt = dt;
-        info->pairs = np;
-        info->pairs_total += np;
-        info->cand_total += nc;
-        if (!(dt > 0.0f) || !(dt < INFINITY)) atomicOr(&info->flags, (uint32_t)SPH_S_DT);
+        // device-wide min and sums; positive floats order like their bits, and
+        // neither min nor integer sums depend on the order of the blocks
+        if (d < INFINITY) atomicMin(&info->dtmin_bits, __float_as_uint(d));
+        if (np) {
+            atomicAdd(&info->pairs, (unsigned long long)np);
+            atomicAdd(&info->pairs_total, (unsigned long long)np);
+        }
+        if (nc) atomicAdd(&info->cand_total, (unsigned long long)nc);
     }
 }
 
@@ -280,11 +259,8 @@ hipError_t launch_interact(sph_ctx *c, const uint8_t *type, uint32_t n, const sp
     const uint32_t nb = n == 0 ? 1 : (n + kInteractThreads - 1) / kInteractThreads;
     hipLaunchKernelGGL(k_interact, dim3(nb), dim3(kInteractThreads), 0, s, c->kp, c->pos4,
                        c->vel4, n, type, c->keys_sorted, c->cell_begin, c->cell_end, c->info,
-                       out.ax, out.ay, out.az, out.arho, out.press, out.nu, out.npair, c->dt_part,
-                       c->pair_part, c->cand_part);
+                       out.ax, out.ay, out.az, out.arho, out.press, out.nu, out.npair);
     if (after_kernel) (void)hipEventRecord(after_kernel, s);
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, c->kp, c->dt_part, c->pair_part,
-                       c->cand_part, nb, c->info);
     return hipGetLastError();
 }
 

@@ -6,37 +6,16 @@
 namespace sph {
 
 // ------------------------------------------------------------------ keys
-// One thread per particle (Sec. 3.1). Cell coordinates in FP32:
-// c = floor((x - o) * (1/cs)); a coordinate outside [0, ncell) on any axis
-// gives label 3 (outside the grid). In slab mode a non-ghost particle left of
-// slab_xlo gets label 1 and one at or right of slab_xhi label 2 (Sec. 4.3).
+// One thread per particle (Sec. 3.1): key = label << Bc | cell (cell_key).
 __global__ __launch_bounds__(256) void k_keys(KParams kp, const float *__restrict__ x,
                                               const float *__restrict__ y,
                                               const float *__restrict__ z,
                                               const uint8_t *__restrict__ type, uint32_t n,
                                               uint32_t *__restrict__ keys,
                                               int32_t *__restrict__ vals) {
-#pragma clang fp contract(off)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float px = x[i], py = y[i], pz = z[i];
-    const float tx = (px - kp.ox) * kp.inv_cs;
-    const float ty = (py - kp.oy) * kp.inv_cs;
-    const float tz = (pz - kp.oz) * kp.inv_cs;
-    const bool inside = (tx >= 0.0f && tx < (float)kp.ncx) && (ty >= 0.0f && ty < (float)kp.ncy) &&
-                        (tz >= 0.0f && tz < (float)kp.ncz);
-    uint32_t key;
-    if (!inside) {
-        key = 3u << kp.cell_bits;
-    } else {
-        const uint32_t cx = (uint32_t)(int)floorf(tx), cy = (uint32_t)(int)floorf(ty),
-                       cz = (uint32_t)(int)floorf(tz);
-        const uint32_t cell = (cx * (uint32_t)kp.ncy + cy) * (uint32_t)kp.ncz + cz;
-        uint32_t label = 0;
-        if (kp.slab_mode && type[i] != kGhost) label = px < kp.slab_xlo ? 1u : (px >= kp.slab_xhi ? 2u : 0u);
-        key = (label << kp.cell_bits) | cell;
-    }
-    keys[i] = key;
+    keys[i] = cell_key(kp, x[i], y[i], z[i], type[i]);
     vals[i] = (int32_t)i;
 }
 
@@ -406,14 +385,22 @@ hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s) {
 }
 
 // ------------------------------------------------------- gather / pack
+// The interaction that follows a reorder (or a pack) reduces into these.
+__device__ __forceinline__ void reset_step_reductions(DevInfo *info) {
+    info->dtmin_bits = 0x7f800000u;  // +inf
+    info->pairs = 0ull;
+}
+
 // Reorder every state array by the sorted permutation (Sec. 3.1: all arrays
 // are ordered according to the sorted IDs) and write the packed interaction
 // inputs (x, y, z, p/rho^2) and (vx, vy, vz, rho).
 __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa out,
                                                 const int32_t *__restrict__ perm, uint32_t n,
                                                 float4 *__restrict__ pos4,
-                                                float4 *__restrict__ vel4) {
+                                                float4 *__restrict__ vel4,
+                                                DevInfo *__restrict__ info) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) reset_step_reductions(info);
     if (k >= n) return;
     const uint32_t s = (uint32_t)perm[k];
     const float x = in.x[s], y = in.y[s], z = in.z[s];
@@ -431,16 +418,17 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
 
 hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
                          hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, c->kp, in, out, c->perm,
-                       n, c->pos4, c->vel4);
+    hipLaunchKernelGGL(k_gather, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, in,
+                       out, c->perm, n, c->pos4, c->vel4, c->info);
     return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_pack(KParams kp, sph_soa in, uint32_t n,
                                               float4 *__restrict__ pos4,
-                                              float4 *__restrict__ vel4) {
+                                              float4 *__restrict__ vel4,
+                                              DevInfo *__restrict__ info) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) reset_step_reductions(info);
     if (k >= n) return;
     const float rho = in.rho[k];
     pos4[k] = make_float4(in.x[k], in.y[k], in.z[k], tait_p_over_rho2(kp, rho));
@@ -448,9 +436,8 @@ __global__ __launch_bounds__(256) void k_pack(KParams kp, sph_soa in, uint32_t n
 }
 
 hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, c->kp, in, n, c->pos4,
-                       c->vel4);
+    hipLaunchKernelGGL(k_pack, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, in, n,
+                       c->pos4, c->vel4, c->info);
     return hipGetLastError();
 }
 

@@ -31,6 +31,28 @@ __device__ __forceinline__ float sound_speed(const KParams &kp, float rho) {
     return kp.c0 * (s * s * s);
 }
 
+// Cell key of one particle (Sec. 3.1 cells of side 2h; Sec. 4.3 migration
+// label): FP32 cell coordinates floor((x - o) * (1/cs)); outside the grid on
+// any axis (or NaN) -> label 3; in slab mode a non-ghost particle left of
+// slab_xlo -> 1, at or right of slab_xhi -> 2. key = label << Bc | cell.
+__device__ __forceinline__ uint32_t cell_key(const KParams &kp, float px, float py, float pz,
+                                             uint8_t type) {
+#pragma clang fp contract(off)
+    const float tx = (px - kp.ox) * kp.inv_cs;
+    const float ty = (py - kp.oy) * kp.inv_cs;
+    const float tz = (pz - kp.oz) * kp.inv_cs;
+    const bool inside = (tx >= 0.0f && tx < (float)kp.ncx) && (ty >= 0.0f && ty < (float)kp.ncy) &&
+                        (tz >= 0.0f && tz < (float)kp.ncz);
+    if (!inside) return 3u << kp.cell_bits;
+    const uint32_t cx = (uint32_t)(int)floorf(tx), cy = (uint32_t)(int)floorf(ty),
+                   cz = (uint32_t)(int)floorf(tz);
+    const uint32_t cell = (cx * (uint32_t)kp.ncy + cy) * (uint32_t)kp.ncz + cz;
+    uint32_t label = 0;
+    if (kp.slab_mode && type != kGhost)
+        label = px < kp.slab_xlo ? 1u : (px >= kp.slab_xhi ? 2u : 0u);
+    return (label << kp.cell_bits) | cell;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = __lane_id();
 #pragma unroll

@@ -44,6 +44,9 @@ struct DevInfo {
     uint32_t ranges[14];  // halo_lo, edge_lo, edge_hi, halo_hi, out_lo, out_hi, excluded
     float dt;
     uint32_t flags;
+    uint32_t dtmin_bits;  // bits of the smallest per-particle dt limit (positive float)
+    uint32_t pad_;
+    unsigned long long dtmin64_bits;  // same in FP64 (variant paths)
     unsigned long long pairs;        // neighbour pairs of the last interaction
     unsigned long long pairs_total;  // summed over every interaction since creation
     unsigned long long cand_total;   // candidates tested, summed likewise
@@ -59,7 +62,6 @@ struct sph_ctx {
     int cell_bits = 0;
     uint32_t ncells = 0;
     uint32_t max_tiles = 0;
-    uint32_t max_iblocks = 0;
     // scratch (device)
     uint32_t *keys_a = nullptr, *keys_b = nullptr, *keys_sorted = nullptr;
     int32_t *vals_a = nullptr, *vals_b = nullptr, *perm = nullptr;
@@ -69,10 +71,15 @@ struct sph_ctx {
     uint32_t *cell_blockmin = nullptr;  // per scan block of cells
     float4 *pos4 = nullptr, *vel4 = nullptr;  // packed (x,y,z,p/rho^2), (vx,vy,vz,rho)
     float *rate = nullptr;                    // 4 * capacity: ax, ay, az, arho
-    float *dt_part = nullptr;
-    uint32_t *pair_part = nullptr;
-    uint32_t *cand_part = nullptr;
     sph::DevInfo *info = nullptr;
+    // variant paths (allocated when params.features asks for them)
+    uint32_t features = 0;
+    double cs64 = 0.0;
+    double *p64 = nullptr;        // p/rho^2 of the sorted FP64 state
+    double *drate = nullptr;      // 4 * capacity FP64 rates of sph_dstep
+    double *tot_part = nullptr;   // 8 doubles per totals block
+    uint32_t tot_blocks = 0;
+    int last_path = 0;            // 0 plain, 1 cell, 2 FP64: which state the tables describe
     // optional per-phase timing of sph_step (events: start, sorted, interacted, updated)
     hipEvent_t *events = nullptr;
     uint32_t ev_slots = 0, ev_used = 0;
@@ -99,6 +106,37 @@ hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s)
 // interact.hip
 hipError_t launch_interact(sph_ctx *c, const uint8_t *type, uint32_t n, const sph_rates &out,
                            hipStream_t s, hipEvent_t after_kernel = nullptr);
+
+// variants.hip (cell + offset and FP64 paths)
+struct GridD {
+    double ox, oy, oz, cs;
+    int32_t ncx, ncy, ncz;
+};
+constexpr int kTotThreads = 256;
+GridD grid_d(const sph_ctx *c);
+hipError_t launch_cell_from_pos(sph_ctx *c, const double *x, const double *y, const double *z,
+                                const sph_cstate &out, uint32_t n, hipStream_t s);
+hipError_t launch_pos_from_cell(sph_ctx *c, const sph_cstate &st, double *x, double *y,
+                                double *z, uint32_t n, hipStream_t s);
+hipError_t launch_keys_cell(sph_ctx *c, const sph_cstate &in, uint32_t n, hipStream_t s);
+hipError_t launch_gather_cell(sph_ctx *c, const sph_cstate &in, const sph_cstate &out,
+                              uint32_t n, hipStream_t s);
+hipError_t launch_interact_cell(sph_ctx *c, const sph_cstate &st, uint32_t n,
+                                const sph_rates &out, hipStream_t s);
+hipError_t launch_update_cell(sph_ctx *c, const sph_cstate &st, const float *ax, const float *ay,
+                              const float *az, const float *arho, uint32_t n, uint64_t step,
+                              hipStream_t s);
+hipError_t launch_totals_cell(sph_ctx *c, const sph_cstate &st, uint32_t n, double *out_host,
+                              hipStream_t s);
+hipError_t launch_keys_d(sph_ctx *c, const sph_dstate &in, uint32_t n, hipStream_t s);
+hipError_t launch_gather_d(sph_ctx *c, const sph_dstate &in, const sph_dstate &out, uint32_t n,
+                           hipStream_t s);
+hipError_t launch_interact_d(sph_ctx *c, const sph_dstate &st, uint32_t n, const sph_drates &out,
+                             hipStream_t s);
+hipError_t launch_update_d(sph_ctx *c, const sph_dstate &st, const sph_drates &r, uint32_t n,
+                           uint64_t step, hipStream_t s);
+hipError_t launch_totals_d(sph_ctx *c, const sph_dstate &st, uint32_t n, double *out_host,
+                           hipStream_t s);
 
 // update.hip
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,

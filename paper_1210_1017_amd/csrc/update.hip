@@ -17,10 +17,15 @@ __global__ __launch_bounds__(256) void k_verlet(KParams kp, sph_soa st,
                                                 const float *__restrict__ arho,
                                                 DevInfo *__restrict__ info, int euler) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    // dt = CFL * (smallest per-particle limit of the interaction), Sec. 3.3
+    const float dt = kp.cfl * __uint_as_float(info->dtmin_bits);
+    if (k == 0) {
+        info->dt = dt;
+        if (!(dt > 0.0f) || !(dt < INFINITY)) atomicOr(&info->flags, (uint32_t)SPH_S_DT);
+    }
     if (k >= info->n_label[0]) return;
     const uint8_t t = st.type[k];
     if (t == kGhost) return;
-    const float dt = info->dt;
     const float rho = st.rho[k];
     const float rn = euler ? fmaf(dt, arho[k], rho) : fmaf(2.0f * dt, arho[k], st.rhop[k]);
     st.rhop[k] = rho;
@@ -49,11 +54,10 @@ __global__ __launch_bounds__(256) void k_verlet(KParams kp, sph_soa st,
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
                          const float *az, const float *arho, uint32_t n, uint64_t step,
                          hipStream_t s) {
-    if (n == 0) return hipSuccess;
     const int E = c->kp.euler_every;
     const int euler = E > 0 ? (step % (uint64_t)E == 0) : (step == 0);
-    hipLaunchKernelGGL(k_verlet, dim3((n + 255) / 256), dim3(256), 0, s, c->kp, st, ax, ay, az,
-                       arho, c->info, euler);
+    hipLaunchKernelGGL(k_verlet, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, st,
+                       ax, ay, az, arho, c->info, euler);
     return hipGetLastError();
 }
 

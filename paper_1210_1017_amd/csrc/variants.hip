@@ -1,0 +1,803 @@
+// Variant paths of the WCSPH step:
+//  * cell + offset positions (int32 cell, FP32 offset from the cell centre),
+//    FP32 interaction on separations formed from offsets and cell
+//    differences, FP64 dt minimum and FP64 global totals;
+//  * an FP64 reference path (every state array, the interaction and the
+//    update in FP64).
+// The sort machinery (radix sort, cell tables, counts) is shared with the
+// plain path; only the key, reorder, interaction and update kernels differ.
+#include "sph_device.h"
+
+namespace sph {
+
+constexpr uint64_t kInf64Bits = 0x7ff0000000000000ull;  // +inf as FP64 bits
+constexpr uint32_t kRsrc3 = 0x00020000u;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+GridD grid_d(const sph_ctx *c) {
+    GridD g;
+    g.ox = c->prm.origin[0];
+    g.oy = c->prm.origin[1];
+    g.oz = c->prm.origin[2];
+    g.cs = 2.0 * c->prm.h;
+    g.ncx = c->prm.ncell[0];
+    g.ncy = c->prm.ncell[1];
+    g.ncz = c->prm.ncell[2];
+    return g;
+}
+
+__device__ __forceinline__ void reset_variant_reductions(DevInfo *info) {
+    info->dtmin_bits = 0x7f800000u;
+    info->dtmin64_bits = kInf64Bits;
+    info->pairs = 0ull;
+}
+
+// positive doubles order like their bits
+__device__ __forceinline__ void atomic_min_pos_double(unsigned long long *a, double v) {
+    atomicMin(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// ------------------------------------------------------------- conversions
+__global__ __launch_bounds__(256) void k_cell_from_pos(GridD g, const double *__restrict__ x,
+                                                       const double *__restrict__ y,
+                                                       const double *__restrict__ z, uint32_t n,
+                                                       sph_cstate out) {
+#pragma clang fp contract(off)
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double t[3] = {(x[i] - g.ox) / g.cs, (y[i] - g.oy) / g.cs, (z[i] - g.oz) / g.cs};
+    const int nc[3] = {g.ncx, g.ncy, g.ncz};
+    int c[3];
+    float o[3];
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (!(t[a] >= 0.0 && t[a] < (double)nc[a])) {
+            inside = false;
+            c[a] = 0;
+            o[a] = 0.0f;
+        } else {
+            const double f = floor(t[a]);
+            c[a] = (int)f;
+            o[a] = (float)((t[a] - f - 0.5) * g.cs);
+        }
+    }
+    out.cell[i] = inside ? (c[0] * g.ncy + c[1]) * g.ncz + c[2] : -1;
+    out.ox[i] = inside ? o[0] : 0.0f;
+    out.oy[i] = inside ? o[1] : 0.0f;
+    out.oz[i] = inside ? o[2] : 0.0f;
+}
+
+__device__ __forceinline__ void cell_coords(int32_t cell, int32_t ncy, int32_t ncz, int *cx,
+                                            int *cy, int *cz) {
+    *cz = cell % ncz;
+    *cy = (cell / ncz) % ncy;
+    *cx = cell / (ncz * ncy);
+}
+
+__device__ __forceinline__ void pos_of(const GridD &g, int32_t cell, float ox, float oy, float oz,
+                                       double *x, double *y, double *z) {
+#pragma clang fp contract(off)
+    int cx, cy, cz;
+    cell_coords(cell, g.ncy, g.ncz, &cx, &cy, &cz);
+    *x = g.ox + ((double)cx + 0.5) * g.cs + (double)ox;
+    *y = g.oy + ((double)cy + 0.5) * g.cs + (double)oy;
+    *z = g.oz + ((double)cz + 0.5) * g.cs + (double)oz;
+}
+
+__global__ __launch_bounds__(256) void k_pos_from_cell(GridD g, sph_cstate st, uint32_t n,
+                                                       double *__restrict__ x,
+                                                       double *__restrict__ y,
+                                                       double *__restrict__ z) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = st.cell[i];
+    if (c < 0) {
+        x[i] = y[i] = z[i] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    pos_of(g, c, st.ox[i], st.oy[i], st.oz[i], &x[i], &y[i], &z[i]);
+}
+
+hipError_t launch_cell_from_pos(sph_ctx *c, const double *x, const double *y, const double *z,
+                                const sph_cstate &out, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_from_pos, dim3((n + 255) / 256), dim3(256), 0, s, grid_d(c), x, y, z,
+                       n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pos_from_cell(sph_ctx *c, const sph_cstate &st, double *x, double *y,
+                                double *z, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pos_from_cell, dim3((n + 255) / 256), dim3(256), 0, s, grid_d(c), st, n,
+                       x, y, z);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ cell path
+// Keys straight from the stored cells: label 3 for cell -1; in slab mode the
+// halo layers x = 0 and x = ncx-1 are exactly "left of slab_xlo" and "at or
+// right of slab_xhi" (the slab faces are cell faces), so non-ghosts there get
+// labels 1 and 2.
+__global__ __launch_bounds__(256) void k_keys_cell(KParams kp, const int32_t *__restrict__ cell,
+                                                   const uint8_t *__restrict__ type, uint32_t n,
+                                                   uint32_t *__restrict__ keys,
+                                                   int32_t *__restrict__ vals) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = cell[i];
+    uint32_t key;
+    if (c < 0 || (uint32_t)c >= kp.ncells) {
+        key = 3u << kp.cell_bits;
+    } else {
+        uint32_t label = 0;
+        if (kp.slab_mode && type[i] != kGhost) {
+            const int cx = c / (kp.ncy * kp.ncz);
+            label = cx == 0 ? 1u : (cx == kp.ncx - 1 ? 2u : 0u);
+        }
+        key = (label << kp.cell_bits) | (uint32_t)c;
+    }
+    keys[i] = key;
+    vals[i] = (int32_t)i;
+}
+
+hipError_t launch_keys_cell(sph_ctx *c, const sph_cstate &in, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys_cell, dim3((n + 255) / 256), dim3(256), 0, s, c->kp, in.cell,
+                       in.type, n, c->keys_a, c->vals_a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_gather_cell(KParams kp, sph_cstate in, sph_cstate out,
+                                                     const int32_t *__restrict__ perm, uint32_t n,
+                                                     float4 *__restrict__ pos4,
+                                                     float4 *__restrict__ vel4,
+                                                     DevInfo *__restrict__ info) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) reset_variant_reductions(info);
+    if (k >= n) return;
+    const uint32_t s = (uint32_t)perm[k];
+    const float ox = in.ox[s], oy = in.oy[s], oz = in.oz[s];
+    const float vx = in.vx[s], vy = in.vy[s], vz = in.vz[s], rho = in.rho[s];
+    out.cell[k] = in.cell[s];
+    out.ox[k] = ox; out.oy[k] = oy; out.oz[k] = oz;
+    out.vx[k] = vx; out.vy[k] = vy; out.vz[k] = vz;
+    out.rho[k] = rho;
+    out.vxp[k] = in.vxp[s]; out.vyp[k] = in.vyp[s]; out.vzp[k] = in.vzp[s];
+    out.rhop[k] = in.rhop[s];
+    out.type[k] = in.type[s];
+    out.id[k] = in.id[s];
+    pos4[k] = make_float4(ox, oy, oz, tait_p_over_rho2(kp, rho));
+    vel4[k] = make_float4(vx, vy, vz, rho);
+}
+
+hipError_t launch_gather_cell(sph_ctx *c, const sph_cstate &in, const sph_cstate &out,
+                              uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_cell, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp,
+                       in, out, c->perm, n, c->pos4, c->vel4, c->info);
+    return hipGetLastError();
+}
+
+// Interaction on cell + offset positions. The structure is that of the plain
+// kernel (lane per particle, 9 contiguous z-runs, support test into a
+// per-lane LDS list, pair terms for the listed neighbours); what differs is
+// the separation: r_ij = (o_i + s) - o_j with s = (c_i - c_j) cs, the cell
+// difference being the run's (x, y) column offset and, along z, which of the
+// run's three cells j lies in (from the run's cell boundaries). The list is
+// flushed by the whole wave at run boundaries once any lane passes
+// kCCap - kCSlack entries.
+constexpr int kCCap = 64;
+constexpr int kCSlack = 24;
+constexpr int kCUnroll = 8;
+constexpr int kCSlots = kCCap + kCUnroll;
+
+__global__ __launch_bounds__(kInteractThreads, 2) void k_interact_cell(
+    KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4, uint32_t n,
+    const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
+    const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend,
+    DevInfo *__restrict__ info, float *__restrict__ oax, float *__restrict__ oay,
+    float *__restrict__ oaz, float *__restrict__ orho, float *__restrict__ opress,
+    float *__restrict__ onu, uint32_t *__restrict__ onpair) {
+    __shared__ uint16_t s_list[kCSlots][kInteractThreads];
+    __shared__ uint32_t s_base[9][kInteractThreads];
+    __shared__ uint32_t s_zb[9][kInteractThreads];  // run-relative starts of cells z and z+1
+    __shared__ double s_rdt[kInteractThreads / 64];
+    __shared__ uint32_t s_rnp[kInteractThreads / 64];
+    __shared__ uint32_t s_rnc[kInteractThreads / 64];
+
+    const int tid = threadIdx.x;
+    const uint32_t n0 = info->n_label[0];
+    const uint32_t i = blockIdx.x * kInteractThreads + tid;
+    const bool inrange = i < n0;
+    const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;
+    double dtmin = INFINITY;
+    uint32_t npair = 0, ncand = 0;
+    const float cs = 2.0f * kp.h;
+
+    if (inrange) {
+        const float4 pi = pos4[i], vi = vel4[i];
+        const float rhoi = vi.w, Pi = pi.w;
+        const float si = rhoi * kp.inv_rho0;
+        const float si3 = si * si * si;
+        float axs = 0.f, ays = 0.f, azs = 0.f, drho = 0.f, nu = 0.f;
+        if (ti != kGhost) {
+            const __amdgpu_buffer_rsrc_t rp =
+                __builtin_amdgcn_make_buffer_rsrc((void *)pos4, 0, (int)(n * 16u), kRsrc3);
+            const __amdgpu_buffer_rsrc_t rv =
+                __builtin_amdgcn_make_buffer_rsrc((void *)vel4, 0, (int)(n * 16u), kRsrc3);
+            const uint32_t cell = sk[i] & kp.cell_mask;
+            const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
+            const int cz = (int)(cell % ncz);
+            const int cy = (int)((cell / ncz) % ncy);
+            const int cx = (int)(cell / (ncz * ncy));
+            const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
+            const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
+            const float hinv2 = -0.5f * kp.inv_h;
+            const float eta2 = kp.eta2, h = kp.h;
+            const float kvis = -kp.alpha * kp.h * kp.c0;
+            const float zm = pi.z + cs, zp = pi.z - cs;  // i's z relative to cells z-1, z+1
+
+            auto flush = [&](int cnt) {
+#pragma unroll 2
+                for (int k = 0; k < cnt; k++) {
+                    const uint32_t e = s_list[k][tid];
+                    const uint32_t col = e >> kRunBits, kk = e & kRunMax;
+                    const uint32_t j = s_base[col][tid] + kk;
+                    const uint32_t zb = s_zb[col][tid];
+                    const float shx = (float)(1 - (int)(col / 3)) * cs;
+                    const float shy = (float)(1 - (int)(col % 3)) * cs;
+                    const float ziz = kk < (zb & 0xffffu) ? zm : (kk < (zb >> 16) ? pi.z : zp);
+                    const v4f pj = __builtin_amdgcn_raw_buffer_load_b128(rp, j * 16u, 0, 0);
+                    const v4f vj = __builtin_amdgcn_raw_buffer_load_b128(rv, j * 16u, 0, 0);
+                    const float dx = (pi.x + shx) - pj.x, dy = (pi.y + shy) - pj.y, dz = ziz - pj.z;
+                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);
+                    const float F = t * t * t;
+                    const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+                    const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
+                    drho = fmaf(F, vr, drho);
+                    const float rs = rhoi + vj.w;
+                    const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
+                    const float vR = vr * R;
+                    const float mu = (h * rs) * vR;
+                    nu = fmaxf(nu, fabsf(mu));
+                    const float sj = vj.w * kp.inv_rho0;
+                    const float visc = vr < 0.0f ? kvis * fmaf(sj * sj, sj, si3) * vR : 0.0f;
+                    const float f = (Pi + pj.w + visc) * F;
+                    axs = fmaf(f, dx, axs);
+                    ays = fmaf(f, dy, ays);
+                    azs = fmaf(f, dz, azs);
+                }
+            };
+
+            uint16_t *const lp0 = &s_list[0][tid];
+            uint16_t *const lpcap = &s_list[kCCap][tid];
+            uint16_t *lp = lp0;
+            uint32_t listed = 0;
+            for (int col = 0; col < 9; col++) {
+                if (__any(lp > lpcap - (size_t)kCSlack * kInteractThreads)) {
+                    const int cnt = (int)((lp - lp0) / kInteractThreads);
+                    flush(cnt);
+                    listed += cnt;
+                    lp = lp0;
+                }
+                const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
+                uint32_t jb = 0, je = 0, b1 = 0, b2 = 0;
+                if (X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
+                    const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
+                    jb = cbeg[c0 + zlo];
+                    je = cend[c0 + zhi];
+                    b1 = cbeg[c0 + (uint32_t)cz];
+                    b2 = (uint32_t)cz + 1 < ncz ? cbeg[c0 + (uint32_t)cz + 1] : je;
+                }
+                if (je - jb > kRunMax + 1u) {
+                    atomicOr(&info->flags, (uint32_t)SPH_S_RUN_OVERFLOW);
+                    je = jb + kRunMax + 1u;
+                }
+                const uint32_t len = je - jb;
+                const uint32_t kb1 = min(b1 - jb, len), kb2 = min(b2 - jb, len);
+                s_base[col][tid] = jb;
+                s_zb[col][tid] = kb1 | (kb2 << 16);
+                ncand += len;
+                const float pix = pi.x + (float)(1 - col / 3) * cs;
+                const float piy = pi.y + (float)(1 - col % 3) * cs;
+                const uint32_t voff = jb * 16u;
+                for (uint32_t k0 = 0; k0 < len; k0 += kCUnroll) {
+                    v4f q[kCUnroll];
+#pragma unroll
+                    for (int u = 0; u < kCUnroll; u++)
+                        q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
+#pragma unroll
+                    for (int u = 0; u < kCUnroll; u++) {
+                        const uint32_t kk = k0 + u;
+                        const float ziz = kk < kb1 ? zm : (kk < kb2 ? pi.z : zp);
+                        const float dx = pix - q[u].x, dy = piy - q[u].y, dz = ziz - q[u].z;
+                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        if (kk < len && r2 < kp.r2max) {
+                            *lp = (uint16_t)(((uint32_t)col << kRunBits) + kk);
+                            lp += kInteractThreads;
+                        }
+                    }
+                    if (lp >= lpcap) {
+                        const int cnt = (int)((lp - lp0) / kInteractThreads);
+                        flush(cnt);
+                        listed += cnt;
+                        lp = lp0;
+                    }
+                }
+            }
+            const int cnt = (int)((lp - lp0) / kInteractThreads);
+            flush(cnt);
+            npair = listed + cnt - 1u;  // minus the self entry
+        }
+        const float mk = kp.mass * kp.kgrad;
+        float ax = 0.f, ay = 0.f, az = 0.f, ar = 0.f;
+        if (ti == kFluid) {
+            ax = fmaf(-mk, axs, kp.gx);
+            ay = fmaf(-mk, ays, kp.gy);
+            az = fmaf(-mk, azs, kp.gz);
+        }
+        if (ti != kGhost) {
+            ar = mk * drho;
+            // CFL limits (Sec. 3.3) in FP64
+            const double s = (double)rhoi / (double)kp.rho0;
+            const double c = (double)kp.c0 * s * s * s;
+            dtmin = (double)kp.h / (c + (double)nu);
+            if (ti == kFluid) {
+                const double a2 = (double)ax * ax + (double)ay * ay + (double)az * az;
+                if (a2 > 0.0) dtmin = fmin(dtmin, sqrt((double)kp.h / sqrt(a2)));
+            }
+        }
+        oax[i] = ax;
+        oay[i] = ay;
+        oaz[i] = az;
+        orho[i] = ar;
+        if (opress) opress[i] = tait_p(kp, rhoi);
+        if (onu) onu[i] = nu;
+        if (onpair) onpair[i] = npair;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dtmin = fmin(dtmin, __shfl_xor(dtmin, o, 64));
+        npair += __shfl_xor(npair, o, 64);
+        ncand += __shfl_xor(ncand, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        s_rdt[tid >> 6] = dtmin;
+        s_rnp[tid >> 6] = npair;
+        s_rnc[tid >> 6] = ncand;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double d = s_rdt[0];
+        uint32_t np = s_rnp[0], nc = s_rnc[0];
+        for (int k = 1; k < kInteractThreads / 64; k++) {
+            d = fmin(d, s_rdt[k]);
+            np += s_rnp[k];
+            nc += s_rnc[k];
+        }
+        if (d < INFINITY) atomic_min_pos_double(&info->dtmin64_bits, d);
+        if (np) {
+            atomicAdd(&info->pairs, (unsigned long long)np);
+            atomicAdd(&info->pairs_total, (unsigned long long)np);
+        }
+        if (nc) atomicAdd(&info->cand_total, (unsigned long long)nc);
+    }
+}
+
+hipError_t launch_interact_cell(sph_ctx *c, const sph_cstate &st, uint32_t n,
+                                const sph_rates &out, hipStream_t s) {
+    const uint32_t nb = n == 0 ? 1 : (n + kInteractThreads - 1) / kInteractThreads;
+    hipLaunchKernelGGL(k_interact_cell, dim3(nb), dim3(kInteractThreads), 0, s, c->kp, c->pos4,
+                       c->vel4, n, st.type, c->keys_sorted, c->cell_begin, c->cell_end, c->info,
+                       out.ax, out.ay, out.az, out.arho, out.press, out.nu, out.npair);
+    return hipGetLastError();
+}
+
+// Verlet update on cell + offset positions (same scheme as the plain path);
+// dt = (float)(CFL * FP64 minimum). After the move an offset outside [-h, h)
+// hands the particle to the neighbouring cell (offset -/+ cs, exact in FP32
+// for |offset| < 3h); leaving the grid gives cell -1.
+__global__ __launch_bounds__(256) void k_verlet_cell(KParams kp, sph_cstate st,
+                                                     const float *__restrict__ ax,
+                                                     const float *__restrict__ ay,
+                                                     const float *__restrict__ az,
+                                                     const float *__restrict__ arho,
+                                                     DevInfo *__restrict__ info, int euler) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const double dt64 = (double)kp.cfl * __longlong_as_double((long long)info->dtmin64_bits);
+    const float dt = (float)dt64;
+    if (k == 0) {
+        info->dt = dt;
+        if (!(dt > 0.0f) || !(dt < INFINITY)) atomicOr(&info->flags, (uint32_t)SPH_S_DT);
+    }
+    if (k >= info->n_label[0]) return;
+    const uint8_t t = st.type[k];
+    if (t == kGhost) return;
+    const float rho = st.rho[k];
+    const float rn = euler ? fmaf(dt, arho[k], rho) : fmaf(2.0f * dt, arho[k], st.rhop[k]);
+    st.rhop[k] = rho;
+    st.rho[k] = rn;
+    bool ok = isfinite(rn);
+    if (t == kFluid) {
+        const float cs = 2.0f * kp.h, hh = kp.h;
+        const float a[3] = {ax[k], ay[k], az[k]};
+        float *off[3] = {st.ox, st.oy, st.oz};
+        float *vel[3] = {st.vx, st.vy, st.vz};
+        float *velp[3] = {st.vxp, st.vyp, st.vzp};
+        const float hdt2 = 0.5f * dt * dt;
+        int32_t cell = st.cell[k];
+        int cc[3];
+        cell_coords(cell, kp.ncy, kp.ncz, &cc[0], &cc[1], &cc[2]);
+        const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
+        bool inside = cell >= 0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const float v = vel[d][k];
+            const float vn = euler ? fmaf(dt, a[d], v) : fmaf(2.0f * dt, a[d], velp[d][k]);
+            float o = off[d][k] + fmaf(hdt2, a[d], dt * v);
+            for (int it = 0; it < 4 && o >= hh; it++) { o -= cs; cc[d]++; }
+            for (int it = 0; it < 4 && o < -hh; it++) { o += cs; cc[d]--; }
+            ok = ok && isfinite(vn) && isfinite(o) && o >= -hh && o < hh;
+            off[d][k] = o;
+            velp[d][k] = v;
+            vel[d][k] = vn;
+            inside = inside && cc[d] >= 0 && cc[d] < nc[d];
+        }
+        st.cell[k] = inside ? (cc[0] * kp.ncy + cc[1]) * kp.ncz + cc[2] : -1;
+    }
+    if (!ok) atomicOr(&info->flags, (uint32_t)SPH_S_NONFINITE);
+}
+
+hipError_t launch_update_cell(sph_ctx *c, const sph_cstate &st, const float *ax, const float *ay,
+                              const float *az, const float *arho, uint32_t n, uint64_t step,
+                              hipStream_t s) {
+    const int E = c->kp.euler_every;
+    const int euler = E > 0 ? (step % (uint64_t)E == 0) : (step == 0);
+    hipLaunchKernelGGL(k_verlet_cell, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp,
+                       st, ax, ay, az, arho, c->info, euler);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- FP64 totals
+// Per-particle: mass, momentum, kinetic energy, potential energy -m g.r and
+// internal energy m e(rho), e = B[(s^6 - 1)/(6 rho0) + 1/rho - 1/rho0],
+// s = rho/rho0 (gamma = 7); block sums in a fixed tree order, then one block
+// adds the block sums in index order: the totals are reproducible.
+struct TotParams {
+    GridD g;
+    double mass, B, rho0, gx, gy, gz;
+};
+
+__device__ __forceinline__ void add_particle(const TotParams &tp, double x, double y, double z,
+                                             double vx, double vy, double vz, double rho,
+                                             double acc[8]) {
+    const double m = tp.mass;
+    const double s = rho / tp.rho0;
+    const double s2 = s * s, s6 = s2 * s2 * s2;
+    const double e = tp.B * ((s6 - 1.0) / (6.0 * tp.rho0) + (1.0 / rho - 1.0 / tp.rho0));
+    acc[0] += m;
+    acc[1] += m * vx;
+    acc[2] += m * vy;
+    acc[3] += m * vz;
+    acc[4] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    acc[5] += -m * (tp.gx * x + tp.gy * y + tp.gz * z);
+    acc[6] += m * e;
+    acc[7] += 1.0;
+}
+
+__device__ __forceinline__ void block_sum8(double acc[8], double *part) {
+    __shared__ double s_acc[kTotThreads][8];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 8; q++) s_acc[tid][q] = acc[q];
+    __syncthreads();
+    for (int w = kTotThreads / 2; w > 0; w >>= 1) {
+        if (tid < w)
+#pragma unroll
+            for (int q = 0; q < 8; q++) s_acc[tid][q] += s_acc[tid + w][q];
+        __syncthreads();
+    }
+    if (tid < 8) part[blockIdx.x * 8 + tid] = s_acc[0][tid];
+}
+
+__global__ __launch_bounds__(kTotThreads) void k_totals_cell(TotParams tp, sph_cstate st,
+                                                             uint32_t n,
+                                                             double *__restrict__ part) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t k = blockIdx.x * kTotThreads + threadIdx.x; k < n; k += gridDim.x * kTotThreads) {
+        const int32_t c = st.cell[k];
+        if (c < 0 || st.type[k] == kGhost) continue;
+        double x, y, z;
+        pos_of(tp.g, c, st.ox[k], st.oy[k], st.oz[k], &x, &y, &z);
+        add_particle(tp, x, y, z, st.vx[k], st.vy[k], st.vz[k], st.rho[k], acc);
+    }
+    block_sum8(acc, part);
+}
+
+__global__ __launch_bounds__(kTotThreads) void k_totals_d(TotParams tp, sph_dstate st, uint32_t n,
+                                                          double *__restrict__ part) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t k = blockIdx.x * kTotThreads + threadIdx.x; k < n; k += gridDim.x * kTotThreads) {
+        if (st.type[k] == kGhost || !(st.x[k] == st.x[k])) continue;
+        add_particle(tp, st.x[k], st.y[k], st.z[k], st.vx[k], st.vy[k], st.vz[k], st.rho[k], acc);
+    }
+    block_sum8(acc, part);
+}
+
+__global__ __launch_bounds__(kTotThreads) void k_totals_final(const double *__restrict__ part,
+                                                              uint32_t nb,
+                                                              double *__restrict__ out) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t b = threadIdx.x; b < nb; b += kTotThreads)
+#pragma unroll
+        for (int q = 0; q < 8; q++) acc[q] += part[b * 8 + q];
+    block_sum8(acc, out);  // gridDim.x == 1: writes out[0..7]
+}
+
+static TotParams tot_params(const sph_ctx *c) {
+    TotParams tp;
+    tp.g = grid_d(c);
+    tp.mass = c->prm.mass;
+    tp.B = c->prm.c0 * c->prm.c0 * c->prm.rho0 / c->prm.gamma;
+    tp.rho0 = c->prm.rho0;
+    tp.gx = c->prm.g[0];
+    tp.gy = c->prm.g[1];
+    tp.gz = c->prm.g[2];
+    return tp;
+}
+
+static hipError_t finish_totals(sph_ctx *c, double *out_host, hipStream_t s) {
+    double *res = c->tot_part + 8 * c->tot_blocks;
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kTotThreads), 0, s, c->tot_part,
+                       c->tot_blocks, res);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out_host, res, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
+hipError_t launch_totals_cell(sph_ctx *c, const sph_cstate &st, uint32_t n, double *out_host,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_totals_cell, dim3(c->tot_blocks), dim3(kTotThreads), 0, s, tot_params(c),
+                       st, n, c->tot_part);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? finish_totals(c, out_host, s) : e;
+}
+
+hipError_t launch_totals_d(sph_ctx *c, const sph_dstate &st, uint32_t n, double *out_host,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_totals_d, dim3(c->tot_blocks), dim3(kTotThreads), 0, s, tot_params(c), st,
+                       n, c->tot_part);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? finish_totals(c, out_host, s) : e;
+}
+
+// ------------------------------------------------------------ FP64 path
+__global__ __launch_bounds__(256) void k_keys_d(KParams kp, const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ z,
+                                                const uint8_t *__restrict__ type, uint32_t n,
+                                                uint32_t *__restrict__ keys,
+                                                int32_t *__restrict__ vals) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = cell_key(kp, (float)x[i], (float)y[i], (float)z[i], type[i]);
+    vals[i] = (int32_t)i;
+}
+
+hipError_t launch_keys_d(sph_ctx *c, const sph_dstate &in, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys_d, dim3((n + 255) / 256), dim3(256), 0, s, c->kp, in.x, in.y, in.z,
+                       in.type, n, c->keys_a, c->vals_a);
+    return hipGetLastError();
+}
+
+struct DParams {
+    double h, r2max, eta2, mass, alpha, rho0, B, c0, gx, gy, gz, kgrad, cfl;
+};
+
+static DParams dparams(const sph_ctx *c) {
+    const sph_params &p = c->prm;
+    DParams d;
+    d.h = p.h;
+    d.r2max = 4.0 * p.h * p.h;
+    const double eta = p.eta_over_h * p.h;
+    d.eta2 = eta * eta;
+    d.mass = p.mass;
+    d.alpha = p.alpha;
+    d.rho0 = p.rho0;
+    d.B = p.c0 * p.c0 * p.rho0 / p.gamma;
+    d.c0 = p.c0;
+    d.gx = p.g[0];
+    d.gy = p.g[1];
+    d.gz = p.g[2];
+    d.kgrad = -5.0 * (21.0 / (16.0 * M_PI * p.h * p.h * p.h)) / (p.h * p.h);
+    d.cfl = p.cfl;
+    return d;
+}
+
+__device__ __forceinline__ double tait_p64(const DParams &d, double rho) {
+    const double s = rho / d.rho0, e = (rho - d.rho0) / d.rho0;
+    double q = s + 1.0;
+    for (int k = 0; k < 5; k++) q = q * s + 1.0;  // 1 + s + ... + s^6
+    return d.B * e * q;
+}
+
+__global__ __launch_bounds__(256) void k_gather_d(DParams dp, sph_dstate in, sph_dstate out,
+                                                  const int32_t *__restrict__ perm, uint32_t n,
+                                                  double *__restrict__ p64,
+                                                  DevInfo *__restrict__ info) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) reset_variant_reductions(info);
+    if (k >= n) return;
+    const uint32_t s = (uint32_t)perm[k];
+    const double rho = in.rho[s];
+    out.x[k] = in.x[s]; out.y[k] = in.y[s]; out.z[k] = in.z[s];
+    out.vx[k] = in.vx[s]; out.vy[k] = in.vy[s]; out.vz[k] = in.vz[s];
+    out.rho[k] = rho;
+    out.vxp[k] = in.vxp[s]; out.vyp[k] = in.vyp[s]; out.vzp[k] = in.vzp[s];
+    out.rhop[k] = in.rhop[s];
+    out.type[k] = in.type[s];
+    out.id[k] = in.id[s];
+    p64[k] = tait_p64(dp, rho) / (rho * rho);
+}
+
+hipError_t launch_gather_d(sph_ctx *c, const sph_dstate &in, const sph_dstate &out, uint32_t n,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_d, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, dparams(c),
+                       in, out, c->perm, n, c->p64, c->info);
+    return hipGetLastError();
+}
+
+// Reference interaction in FP64: lane per particle, direct loop over the 9
+// z-runs, support test |r_ij|^2 < 4h^2 in FP64, the pair terms of Sec. 2.2.
+__global__ __launch_bounds__(256) void k_interact_d(
+    DParams dp, KParams kp, sph_dstate st, const double *__restrict__ p64,
+    const uint32_t *__restrict__ sk, const uint32_t *__restrict__ cbeg,
+    const uint32_t *__restrict__ cend, DevInfo *__restrict__ info, sph_drates out) {
+    __shared__ double s_rdt[4];
+    __shared__ uint32_t s_rnp[4];
+    const int tid = threadIdx.x;
+    const uint32_t n0 = info->n_label[0];
+    const uint32_t i = blockIdx.x * 256 + tid;
+    double dtmin = INFINITY;
+    uint32_t npair = 0;
+    if (i < n0) {
+        const uint8_t ti = st.type[i];
+        double axs = 0, ays = 0, azs = 0, drho = 0, nu = 0;
+        const double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+        const double vxi = st.vx[i], vyi = st.vy[i], vzi = st.vz[i], rhoi = st.rho[i];
+        const double Pi = p64[i];
+        const double ci = dp.c0 * (rhoi / dp.rho0) * (rhoi / dp.rho0) * (rhoi / dp.rho0);
+        if (ti != kGhost) {
+            const uint32_t cell = sk[i] & kp.cell_mask;
+            const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
+            const int cz = (int)(cell % ncz);
+            const int cy = (int)((cell / ncz) % ncy);
+            const int cx = (int)(cell / (ncz * ncy));
+            const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
+            const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
+            for (int col = 0; col < 9; col++) {
+                const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
+                if (X < 0 || X >= kp.ncx || Y < 0 || Y >= kp.ncy) continue;
+                const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
+                const uint32_t jb = cbeg[c0 + zlo], je = cend[c0 + zhi];
+                for (uint32_t j = jb; j < je; j++) {
+                    if (j == i) continue;
+                    const double dx = xi - st.x[j], dy = yi - st.y[j], dz = zi - st.z[j];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (!(r2 < dp.r2max)) continue;
+                    const double rhoj = st.rho[j];
+                    const double t = 1.0 - 0.5 * sqrt(r2) / dp.h;
+                    const double F = t * t * t;
+                    const double ux = vxi - st.vx[j], uy = vyi - st.vy[j], uz = vzi - st.vz[j];
+                    const double vr = ux * dx + uy * dy + uz * dz;
+                    drho += F * vr;
+                    const double mu = dp.h * vr / (r2 + dp.eta2);
+                    nu = fmax(nu, fabs(mu));
+                    const double sj = rhoj / dp.rho0;
+                    const double cj = dp.c0 * sj * sj * sj;
+                    const double visc = vr < 0.0 ? -dp.alpha * 0.5 * (ci + cj) * mu / (0.5 * (rhoi + rhoj)) : 0.0;
+                    const double f = (Pi + p64[j] + visc) * F;
+                    axs += f * dx;
+                    ays += f * dy;
+                    azs += f * dz;
+                    npair++;
+                }
+            }
+        }
+        const double mk = dp.mass * dp.kgrad;
+        double ax = 0, ay = 0, az = 0, ar = 0;
+        if (ti == kFluid) {
+            ax = -mk * axs + dp.gx;
+            ay = -mk * ays + dp.gy;
+            az = -mk * azs + dp.gz;
+        }
+        if (ti != kGhost) {
+            ar = mk * drho;
+            dtmin = dp.h / (ci + nu);
+            if (ti == kFluid) {
+                const double amag = sqrt(ax * ax + ay * ay + az * az);
+                if (amag > 0.0) dtmin = fmin(dtmin, sqrt(dp.h / amag));
+            }
+        }
+        out.ax[i] = ax;
+        out.ay[i] = ay;
+        out.az[i] = az;
+        out.arho[i] = ar;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dtmin = fmin(dtmin, __shfl_xor(dtmin, o, 64));
+        npair += __shfl_xor(npair, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        s_rdt[tid >> 6] = dtmin;
+        s_rnp[tid >> 6] = npair;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double d = fmin(fmin(s_rdt[0], s_rdt[1]), fmin(s_rdt[2], s_rdt[3]));
+        const uint32_t np = s_rnp[0] + s_rnp[1] + s_rnp[2] + s_rnp[3];
+        if (d < INFINITY) atomic_min_pos_double(&info->dtmin64_bits, d);
+        if (np) {
+            atomicAdd(&info->pairs, (unsigned long long)np);
+            atomicAdd(&info->pairs_total, (unsigned long long)np);
+        }
+    }
+}
+
+hipError_t launch_interact_d(sph_ctx *c, const sph_dstate &st, uint32_t n, const sph_drates &out,
+                             hipStream_t s) {
+    const uint32_t nb = n == 0 ? 1 : (n + 255) / 256;
+    hipLaunchKernelGGL(k_interact_d, dim3(nb), dim3(256), 0, s, dparams(c), c->kp, st, c->p64,
+                       c->keys_sorted, c->cell_begin, c->cell_end, c->info, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_verlet_d(DParams dp, sph_dstate st, sph_drates r,
+                                                  DevInfo *__restrict__ info, int euler) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const double dt = dp.cfl * __longlong_as_double((long long)info->dtmin64_bits);
+    if (k == 0) {
+        info->dt = (float)dt;
+        if (!(dt > 0.0) || !(dt < INFINITY)) atomicOr(&info->flags, (uint32_t)SPH_S_DT);
+    }
+    if (k >= info->n_label[0]) return;
+    const uint8_t t = st.type[k];
+    if (t == kGhost) return;
+    const double rho = st.rho[k];
+    const double rn = euler ? rho + dt * r.arho[k] : st.rhop[k] + 2.0 * dt * r.arho[k];
+    st.rhop[k] = rho;
+    st.rho[k] = rn;
+    bool ok = isfinite(rn);
+    if (t == kFluid) {
+        const double a[3] = {r.ax[k], r.ay[k], r.az[k]};
+        double *pos[3] = {st.x, st.y, st.z};
+        double *vel[3] = {st.vx, st.vy, st.vz};
+        double *velp[3] = {st.vxp, st.vyp, st.vzp};
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const double v = vel[d][k];
+            const double vn = euler ? v + dt * a[d] : velp[d][k] + 2.0 * dt * a[d];
+            pos[d][k] += dt * v + 0.5 * dt * dt * a[d];
+            velp[d][k] = v;
+            vel[d][k] = vn;
+            ok = ok && isfinite(vn) && isfinite(pos[d][k]);
+        }
+    }
+    if (!ok) atomicOr(&info->flags, (uint32_t)SPH_S_NONFINITE);
+}
+
+hipError_t launch_update_d(sph_ctx *c, const sph_dstate &st, const sph_drates &r, uint32_t n,
+                           uint64_t step, hipStream_t s) {
+    const int E = c->kp.euler_every;
+    const int euler = E > 0 ? (step % (uint64_t)E == 0) : (step == 0);
+    hipLaunchKernelGGL(k_verlet_d, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, dparams(c),
+                       st, r, c->info, euler);
+    return hipGetLastError();
+}
+
+}  // namespace sph

@@ -36,7 +36,12 @@ class Params(C.Structure):
                 ("g", C.c_double * 3), ("origin", C.c_double * 3), ("ncell", C.c_int32 * 3),
                 ("euler_every", C.c_int32), ("slab_mode", C.c_int32), ("reserved_", C.c_int32),
                 ("slab_xlo", C.c_double), ("slab_xhi", C.c_double),
-                ("capacity", C.c_uint32), ("reserved2_", C.c_uint32)]
+                ("capacity", C.c_uint32), ("features", C.c_uint32)]
+
+FEATURE_CELL, FEATURE_FP64 = 1, 2
+CSTATE_FIELDS = ("cell", "ox", "oy", "oz", "vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop",
+                 "type", "id")
+DSTATE_F64 = ("x", "y", "z", "vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop")
 
 
 class SoA(C.Structure):
@@ -48,6 +53,18 @@ RATE_FIELDS = ("ax", "ay", "az", "arho", "press", "nu", "npair")
 
 class Rates(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in RATE_FIELDS]
+
+
+class CState(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in CSTATE_FIELDS]
+
+
+class DState(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in DSTATE_F64 + ("type", "id")]
+
+
+class DRates(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ax", "ay", "az", "arho")]
 
 
 class Counts(C.Structure):
@@ -96,6 +113,17 @@ def lib() -> C.CDLL:
         L.sph_timing_begin.argtypes = [vp, u32]
         L.sph_timing_read.argtypes = [vp, P(C.c_float), u32, P(C.c_uint32)]
         L.sph_copy_keys.argtypes = [vp, vp, u32, vp]
+        L.sph_cstate_from_positions.argtypes = [vp, vp, vp, vp, P(CState), u32, vp]
+        L.sph_cstate_positions.argtypes = [vp, P(CState), vp, vp, vp, u32, vp]
+        L.sph_csort.argtypes = [vp, P(CState), P(CState), u32, vp]
+        L.sph_cinteract.argtypes = [vp, P(CState), u32, P(Rates), vp]
+        L.sph_cstep.argtypes = [vp, P(CState), P(CState), u32, u64, vp]
+        L.sph_ctotals.argtypes = [vp, P(CState), u32, P(C.c_double), vp]
+        L.sph_dsort.argtypes = [vp, P(DState), P(DState), u32, vp]
+        L.sph_dinteract.argtypes = [vp, P(DState), u32, P(DRates), vp]
+        L.sph_dstep.argtypes = [vp, P(DState), P(DState), u32, u64, vp]
+        L.sph_dtotals.argtypes = [vp, P(DState), u32, P(C.c_double), vp]
+        L.sph_get_dt64.argtypes = [vp, P(C.c_double), vp]
         L.sph_copy_cell_tables.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
@@ -108,7 +136,7 @@ def header_functions() -> list[str]:
     return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", txt)))
 
 
-def make_params(p: dict, capacity: int) -> Params:
+def make_params(p: dict, capacity: int, features: int = 0) -> Params:
     s = Params()
     for k in ("dp", "h", "rho0", "gamma", "c0", "alpha", "eta_over_h", "cfl", "mass"):
         setattr(s, k, float(p[k]))
@@ -121,6 +149,7 @@ def make_params(p: dict, capacity: int) -> Params:
     s.slab_xlo = float(p.get("slab_xlo", 0.0))
     s.slab_xhi = float(p.get("slab_xhi", 0.0))
     s.capacity = int(capacity)
+    s.features = int(features)
     return s
 
 
@@ -166,6 +195,61 @@ class DeviceState:
         return SoA(*[self.t[k].data_ptr() for k in SOA_FIELDS])
 
 
+class CellState:
+    """Cell + offset particle state on the GPU (int32 cell, FP32 offsets)."""
+
+    def __init__(self, tensors: dict):
+        self.t = tensors
+
+    @classmethod
+    def empty(cls, capacity: int, device="cuda") -> "CellState":
+        import torch
+        t = {k: torch.empty(capacity, dtype=torch.float32, device=device)
+             for k in CSTATE_FIELDS if k not in ("cell", "type", "id")}
+        t["cell"] = torch.empty(capacity, dtype=torch.int32, device=device)
+        t["type"] = torch.empty(capacity, dtype=torch.uint8, device=device)
+        t["id"] = torch.empty(capacity, dtype=torch.int32, device=device)
+        return cls(t)
+
+    def soa(self) -> CState:
+        return CState(*[self.t[k].data_ptr() for k in CSTATE_FIELDS])
+
+    def to_numpy(self, n: int) -> dict:
+        return {k: self.t[k][:n].cpu().numpy().copy() for k in CSTATE_FIELDS}
+
+
+class F64State:
+    """FP64 particle state on the GPU (SoA)."""
+
+    def __init__(self, tensors: dict):
+        self.t = tensors
+
+    @classmethod
+    def empty(cls, capacity: int, device="cuda") -> "F64State":
+        import torch
+        t = {k: torch.empty(capacity, dtype=torch.float64, device=device) for k in DSTATE_F64}
+        t["type"] = torch.empty(capacity, dtype=torch.uint8, device=device)
+        t["id"] = torch.empty(capacity, dtype=torch.int32, device=device)
+        return cls(t)
+
+    @classmethod
+    def from_numpy(cls, st: dict, capacity: int | None = None, device="cuda") -> "F64State":
+        import torch
+        n = st["x"].shape[0]
+        ds = cls.empty(max(n if capacity is None else capacity, 1), device)
+        for k in DSTATE_F64:
+            ds.t[k][:n].copy_(torch.from_numpy(np.ascontiguousarray(st[k], dtype=np.float64)))
+        ds.t["type"][:n].copy_(torch.from_numpy(np.ascontiguousarray(st["type"])))
+        ds.t["id"][:n].copy_(torch.from_numpy(np.ascontiguousarray(st["id"])))
+        return ds
+
+    def soa(self) -> DState:
+        return DState(*[self.t[k].data_ptr() for k in DSTATE_F64 + ("type", "id")])
+
+    def to_numpy(self, n: int) -> dict:
+        return {k: self.t[k][:n].cpu().numpy().copy() for k in DSTATE_F64 + ("type", "id")}
+
+
 def make_rates(capacity: int, with_aux: bool = True, device="cuda") -> dict:
     import torch
     keys = ("ax", "ay", "az", "arho") + (("press", "nu") if with_aux else ())
@@ -183,11 +267,11 @@ def _rates_struct(r: dict) -> Rates:
 class Context:
     """One libsph context (scratch for ``capacity`` particles on the current GPU)."""
 
-    def __init__(self, params: dict, capacity: int):
+    def __init__(self, params: dict, capacity: int, features: int = 0):
         self.L = lib()
         self.params = dict(params)
         self.capacity = int(capacity)
-        self._p = make_params(params, capacity)
+        self._p = make_params(params, capacity, features)
         h = C.c_void_p()
         rc = self.L.sph_create(C.byref(self._p), C.byref(h))
         if rc != SPH_OK:
@@ -233,6 +317,63 @@ class Context:
     def step(self, cur: DeviceState, nxt: DeviceState, n: int, step: int, stream=None):
         a, b = cur.soa(), nxt.soa()
         self._check(self.L.sph_step(self.h, C.byref(a), C.byref(b), n, step, _stream_ptr(stream)))
+
+    # ---- cell + offset path
+    def cstate_from_positions(self, x, y, z, out: CellState, n: int, stream=None):
+        o = out.soa()
+        self._check(self.L.sph_cstate_from_positions(self.h, _addr(x), _addr(y), _addr(z),
+                                                     C.byref(o), n, _stream_ptr(stream)))
+
+    def cstate_positions(self, st: CellState, n: int, stream=None):
+        import torch
+        out = [torch.empty(max(n, 1), dtype=torch.float64, device="cuda") for _ in range(3)]
+        a = st.soa()
+        self._check(self.L.sph_cstate_positions(self.h, C.byref(a), *[_addr(t) for t in out], n,
+                                                _stream_ptr(stream)))
+        return [t[:n] for t in out]
+
+    def csort(self, cur: CellState, out: CellState, n: int, stream=None):
+        a, b = cur.soa(), out.soa()
+        self._check(self.L.sph_csort(self.h, C.byref(a), C.byref(b), n, _stream_ptr(stream)))
+
+    def cinteract(self, srt: CellState, n: int, rates: dict, stream=None):
+        a, r = srt.soa(), _rates_struct(rates)
+        self._check(self.L.sph_cinteract(self.h, C.byref(a), n, C.byref(r), _stream_ptr(stream)))
+
+    def cstep(self, cur: CellState, nxt: CellState, n: int, step: int, stream=None):
+        a, b = cur.soa(), nxt.soa()
+        self._check(self.L.sph_cstep(self.h, C.byref(a), C.byref(b), n, step, _stream_ptr(stream)))
+
+    def ctotals(self, st: CellState, n: int, stream=None) -> np.ndarray:
+        out = (C.c_double * 8)()
+        a = st.soa()
+        self._check(self.L.sph_ctotals(self.h, C.byref(a), n, out, _stream_ptr(stream)))
+        return np.array(out[:])
+
+    # ---- FP64 reference path
+    def dsort(self, cur: F64State, out: F64State, n: int, stream=None):
+        a, b = cur.soa(), out.soa()
+        self._check(self.L.sph_dsort(self.h, C.byref(a), C.byref(b), n, _stream_ptr(stream)))
+
+    def dinteract(self, srt: F64State, n: int, rates: dict, stream=None):
+        a = srt.soa()
+        r = DRates(*[rates[k].data_ptr() for k in ("ax", "ay", "az", "arho")])
+        self._check(self.L.sph_dinteract(self.h, C.byref(a), n, C.byref(r), _stream_ptr(stream)))
+
+    def dstep(self, cur: F64State, nxt: F64State, n: int, step: int, stream=None):
+        a, b = cur.soa(), nxt.soa()
+        self._check(self.L.sph_dstep(self.h, C.byref(a), C.byref(b), n, step, _stream_ptr(stream)))
+
+    def dtotals(self, st: F64State, n: int, stream=None) -> np.ndarray:
+        out = (C.c_double * 8)()
+        a = st.soa()
+        self._check(self.L.sph_dtotals(self.h, C.byref(a), n, out, _stream_ptr(stream)))
+        return np.array(out[:])
+
+    def dt64(self, stream=None) -> float:
+        v = C.c_double()
+        self._check(self.L.sph_get_dt64(self.h, C.byref(v), _stream_ptr(stream)))
+        return float(v.value)
 
     def counts(self, stream=None) -> dict:
         c = Counts()

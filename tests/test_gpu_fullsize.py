@@ -14,7 +14,8 @@ import pytest
 
 import oracle
 from paper_1210_1017_amd import cases, sph
-from parity_util import TOL, announce, assert_sorted_equal, gpu_sort, interact_compare, ulp32
+from parity_util import (TOL, announce, assert_sorted_equal, gpu_sort, interact_compare,
+                         relnorm, ulp32)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
@@ -129,3 +130,59 @@ def test_c3_sort_state_ranges_and_sampled_interaction(c3):
     print("c3", err, flush=True)
     for k, v in err.items():
         assert v <= TOL, (k, v)
+
+
+def test_c4_cell_step_subblock_vs_oracle():
+    """The 38.5M-particle precision-variant workload: one cell + offset
+    interaction on the whole state, compared with the FP64 oracle on a cube of
+    64 lattice spacings (its particles, with a halo of 4h as neighbours)."""
+    case = cases.case_c4()
+    p, n = case.params, case.n
+    announce(f"c4 cell interaction + oracle sub-block n={n}")
+    F = sph.FEATURE_CELL
+    ctx = sph.Context(p, n, F)
+    t64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    ca, cb = sph.CellState.empty(n), sph.CellState.empty(n)
+    ctx.cstate_from_positions(t64(case.pos64[:, 0]), t64(case.pos64[:, 1]), t64(case.pos64[:, 2]),
+                              ca, n)
+    for k in ("vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop", "type", "id"):
+        ca.t[k][:n].copy_(torch.from_numpy(np.ascontiguousarray(case.state[k])))
+    ctx.csort(ca, cb, n)
+    rates = sph.make_rates(n)
+    ctx.cinteract(cb, n, rates)
+    torch.cuda.synchronize()
+    x, y, z = ctx.cstate_positions(cb, n)
+    ids_sorted = cb.t["id"][:n].cpu().numpy()
+    pos_by_id = np.empty((n, 3))
+    pos_by_id[ids_sorted] = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+    dp = p["dp"]
+    lo = np.array([60 * dp, 200 * dp, 60 * dp])
+    inner, outer = cases.sub_block(case, lo, 64 * dp, 4.0 * p["h"])
+    assert len(inner) > 250000
+    sub = {k: case.state[k][outer] for k in sph.SOA_FIELDS}
+    sub64 = oracle.to_f64(sub)
+    for a, k in enumerate("xyz"):
+        sub64[k] = np.ascontiguousarray(pos_by_id[outer, a])
+    subp = dict(p)
+    cs = 2.0 * p["h"]
+    cases.set_grid(subp, tuple(lo - 3 * cs), tuple(lo + 64 * dp + 3 * cs))
+    srt = oracle.sort_state(subp, sub64)
+    want = np.isin(srt["state"]["id"], case.state["id"][inner])
+    sel = np.nonzero(want[: int(srt["counts"][0])])[0]
+    acc = oracle.interact(subp, srt, sel=sel)
+    ids = srt["state"]["id"][sel]
+    where = np.empty(n, dtype=np.int64)
+    where[ids_sorted] = np.arange(n)
+    gi = where[ids]
+    g = {k: v[:n].cpu().numpy()[gi] for k, v in rates.items()}
+    t = srt["state"]["type"][sel]
+    fl = t == cases.FLUID
+    gv = np.array(p["g"])
+    a_ref = np.stack([acc["ax"], acc["ay"], acc["az"]], 1)[fl] - gv
+    a_gpu = np.stack([g["ax"], g["ay"], g["az"]], 1)[fl].astype(np.float64) - gv
+    errs = {"a_minus_g": relnorm(a_gpu, a_ref), "drho": relnorm(g["arho"], acc["drho"]),
+            "p": relnorm(g["press"], acc["p"]), "nu": relnorm(g["nu"], acc["nu"])}
+    print("c4 sub-block", len(sel), errs, int(g["npair"].sum()), int(acc["npair"].sum()), flush=True)
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+    assert abs(int(g["npair"].sum()) - int(acc["npair"].sum())) <= 1e-4 * acc["npair"].sum() + 2

@@ -1,0 +1,283 @@
+"""GPU variant paths against the FP64 oracle, through the C ABI.
+
+Cell + offset path: positions round-trip at FP32 resolution of the offset;
+interaction and one step agree with the oracle run on the exact FP64
+positions the cells describe (1e-4 normwise on the rates; positions within a
+few FP32 ulps of the offset scale); re-celling moves particles across faces
+exactly; FP64 totals equal the oracle's sums.
+
+FP64 path: the sort is bit-exact with the oracle (keys from the positions
+rounded to FP32 on both sides); rates, a step and totals agree with the
+oracle to FP64 rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1210_1017_amd import cases, sph
+from parity_util import TOL, announce, relnorm, ulp32
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+F = sph.FEATURE_CELL | sph.FEATURE_FP64
+
+
+def _t64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _cell_state(ctx, case, cap):
+    n = case.n
+    cs = sph.CellState.empty(cap)
+    ctx.cstate_from_positions(_t64(case.pos64[:, 0]), _t64(case.pos64[:, 1]),
+                              _t64(case.pos64[:, 2]), cs, n)
+    for k in ("vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop", "type", "id"):
+        cs.t[k][:n].copy_(torch.from_numpy(np.ascontiguousarray(case.state[k])))
+    return cs
+
+
+def _oracle_state(ctx, cst, n):
+    """The FP64 state a cell state describes (positions reconstructed on the GPU
+    in FP64, everything else the FP32 values upcast exactly)."""
+    x, y, z = ctx.cstate_positions(cst, n)
+    st = cst.to_numpy(n)
+    out = {"x": x.cpu().numpy(), "y": y.cpu().numpy(), "z": z.cpu().numpy()}
+    for k in ("vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop"):
+        out[k] = st[k].astype(np.float64)
+    out["type"] = st["type"]
+    out["id"] = st["id"]
+    return out
+
+
+def _by_id(a: dict, ids):
+    order = np.argsort(ids)
+    return {k: v[order] for k, v in a.items()}
+
+
+def _cases():
+    return {
+        "tank": lambda: cases.perturb(cases.small_tank(), 13),
+        "slab": lambda: cases.perturb(cases.small_slab(), 14),
+        "c1": lambda: cases.perturb(cases.case_c1(), 15),
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_cell_roundtrip(name):
+    case = _cases()[name]()
+    p, n = case.params, case.n
+    announce(f"cell roundtrip {name} n={n}")
+    ctx = sph.Context(p, n, F)
+    cst = _cell_state(ctx, case, n)
+    x, y, z = ctx.cstate_positions(cst, n)
+    got = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+    err = np.abs(got - case.pos64)
+    assert err.max() <= ulp32(p["h"]) * 0.5 + 1e-15
+    o = cst.to_numpy(n)
+    assert np.all(np.abs(o["ox"]) <= p["h"]) and np.all(np.abs(o["oz"]) <= p["h"])
+    cs = 2.0 * p["h"]
+    c = np.floor((case.pos64 - np.array(p["origin"])) / cs).astype(np.int64)
+    lin = (c[:, 0] * p["ncell"][1] + c[:, 1]) * p["ncell"][2] + c[:, 2]
+    assert np.array_equal(o["cell"], lin)
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_cell_interaction_parity(name):
+    case = _cases()[name]()
+    p, n = case.params, case.n
+    announce(f"cell interact {name} n={n}")
+    ctx = sph.Context(p, n, F)
+    cur = _cell_state(ctx, case, n)
+    srt = sph.CellState.empty(n)
+    ctx.csort(cur, srt, n)
+    rates = sph.make_rates(n)
+    ctx.cinteract(srt, n, rates)
+    torch.cuda.synchronize()
+    n0 = ctx.counts()["n_label"][0]
+    ost = _oracle_state(ctx, srt, n)
+    osr = oracle.sort_state(p, ost)
+    acc = oracle.interact(p, osr)
+    ids_ref = osr["state"]["id"][: len(acc["ax"])]
+    ref = _by_id({**acc, "type": osr["state"]["type"][: len(acc["ax"])]}, ids_ref)
+    g = {k: v.cpu().numpy()[:n0] for k, v in rates.items()}
+    g = _by_id(g, ost["id"][:n0])
+    assert np.array_equal(np.sort(ids_ref), np.sort(ost["id"][:n0]))
+    fl = ref["type"] == cases.FLUID
+    ng = ref["type"] != cases.GHOST
+    gv = np.array(p["g"])
+    a_ref = np.stack([ref["ax"], ref["ay"], ref["az"]], 1)[fl] - gv
+    a_gpu = np.stack([g["ax"], g["ay"], g["az"]], 1)[fl].astype(np.float64) - gv
+    errs = {"a_minus_g": relnorm(a_gpu, a_ref), "drho": relnorm(g["arho"][ng], ref["drho"][ng]),
+            "p": relnorm(g["press"][ng], ref["p"][ng]), "nu": relnorm(g["nu"][ng], ref["nu"][ng])}
+    print(name, errs, flush=True)
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+    # the support test is taken on different (more precise) separations than the
+    # oracle's FP32 absolute positions: counts may differ only at |r| = 2h
+    dpair = np.abs(g["npair"][ng].astype(np.int64) - ref["npair"][ng])
+    assert dpair.sum() <= 1e-4 * ref["npair"].sum() + 2
+    assert abs(ctx.dt64() - oracle.dt(p, osr, acc)) <= 1e-5 * oracle.dt(p, osr, acc)
+
+
+def test_cell_step_parity():
+    case = cases.perturb(cases.case_c1(), 15)
+    p, n = case.params, case.n
+    announce(f"cell step c1 n={n}")
+    ctx = sph.Context(p, n, F)
+    cur = _cell_state(ctx, case, n)
+    ost0 = _oracle_state(ctx, cur, n)
+    nxt = sph.CellState.empty(n)
+    ctx.cstep(cur, nxt, n, 0)
+    torch.cuda.synchronize()
+    dt = float(np.float32(ctx.dt()))
+    got = _oracle_state(ctx, nxt, n)
+    r = oracle.step(p, ost0, 0, dt_override=dt)
+    ref = r["state"]
+    g = _by_id(got, got["id"])
+    f = _by_id(ref, ref["id"])
+    s0 = _by_id(r["srt"]["state"], r["srt"]["state"]["id"])
+    fl = f["type"] == cases.FLUID
+    for k in ("x", "y", "z"):
+        inc = np.abs(f[k] - s0[k])
+        bound = 2.0 * ulp32(p["h"]) + 1e-3 * inc
+        assert np.all(np.abs(g[k] - f[k]) <= bound), k
+    for k in ("vx", "vy", "vz", "rho"):
+        inc_ref = f[k] - s0[k]
+        inc_gpu = g[k] - s0[k]
+        excess = np.maximum(np.abs(inc_gpu - inc_ref) - ulp32(f[k]), 0.0)
+        assert np.linalg.norm(excess) <= 1e-3 * np.linalg.norm(inc_ref), k
+    assert fl.sum() > 9000
+    assert ctx.status() & (sph.STATUS_NONFINITE | sph.STATUS_DT) == 0
+
+
+def test_cell_recell_across_faces_and_out_of_grid():
+    """Isolated particles just below a cell face moving across it (and one
+    leaving the grid): after a step the cell index advances and the FP64
+    position is x0 + dt v (+ dt^2 g / 2 along z), within FP32 offset ulps."""
+    p = cases.base_params(0.02)
+    cases.set_grid(p, (0.0, 0.0, 0.0), (1.04, 1.04, 1.04))  # 10 cells of 0.104? no: cs = 0.052
+    cs = 2.0 * p["h"]
+    eps = 2e-6
+    pos = []
+    vel = []
+    for k in range(6):
+        base = np.array([0.2 + 0.3 * (k % 3), 0.2 + 0.3 * (k // 3), 0.5])
+        c = np.floor(base / cs)
+        if k % 2 == 0:
+            x = (c + 1) * cs - eps  # just below the upper face in x, moving +x
+            pos.append([x[0], base[1], base[2]])
+            vel.append([0.5, 0.0, 0.0])
+        else:
+            x = c * cs + eps  # just above the lower face in y, moving -y
+            pos.append([base[0], x[1], base[2]])
+            vel.append([0.0, -0.5, 0.0])
+    pos.append([1.04 - eps, 0.5, 0.5])  # leaves the grid through x = 1.04
+    vel.append([0.5, 0.0, 0.0])
+    pos = np.array(pos)
+    vel = np.array(vel)
+    n = len(pos)
+    st = cases._make_state(pos, np.zeros(n), np.full(n, 1000.0), vel)
+    case = cases.Case("recell", p, st, pos)
+    announce(f"cell recell n={n}")
+    ctx = sph.Context(p, n, F)
+    cur = _cell_state(ctx, case, n)
+    c0 = cur.to_numpy(n)["cell"].copy()
+    nxt = sph.CellState.empty(n)
+    ctx.cstep(cur, nxt, n, 0)
+    torch.cuda.synchronize()
+    dt = float(np.float32(ctx.dt()))
+    got = nxt.to_numpy(n)
+    order = np.argsort(got["id"])
+    cell1 = got["cell"][order]
+    x, y, z = ctx.cstate_positions(nxt, n)
+    P = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)[order]
+    v32 = vel.astype(np.float32).astype(np.float64)
+    want = pos.astype(np.float64) + dt * v32 + 0.5 * dt * dt * np.array([0, 0, -9.81])
+    stride = np.array([p["ncell"][1] * p["ncell"][2], p["ncell"][2], 1])
+    for k in range(6):
+        d = stride[0] if k % 2 == 0 else -stride[1]
+        assert cell1[k] == c0[k] + d, k
+        assert np.all(np.abs(P[k] - want[k]) <= 4 * ulp32(p["h"]) + 1e-12), (k, P[k] - want[k])
+    assert cell1[6] == -1 and np.all(np.isnan(P[6]))
+    ctx.csort(nxt, cur, n)
+    assert ctx.counts()["n_label"][3] == 1
+
+
+@pytest.mark.parametrize("name", ["tank", "c1"])
+def test_cell_totals(name):
+    case = _cases()[name]()
+    p, n = case.params, case.n
+    announce(f"cell totals {name} n={n}")
+    ctx = sph.Context(p, n, F)
+    cst = _cell_state(ctx, case, n)
+    got = ctx.ctotals(cst, n)
+    ref = oracle.totals(p, _oracle_state(ctx, cst, n))
+    for q in range(8):
+        assert abs(got[q] - ref[q]) <= 1e-11 * max(abs(ref[q]), 1e-30) + 1e-300, (q, got[q], ref[q])
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_fp64_path_parity(name):
+    case = _cases()[name]()
+    p, n = case.params, case.n
+    announce(f"fp64 sort+interact {name} n={n}")
+    ctx = sph.Context(p, n, F)
+    st = {k: case.state[k] for k in sph.SOA_FIELDS}
+    st["x"], st["y"], st["z"] = case.pos64[:, 0], case.pos64[:, 1], case.pos64[:, 2]
+    cur = sph.F64State.from_numpy(st, capacity=n)
+    srt = sph.F64State.empty(n)
+    ctx.dsort(cur, srt, n)
+    r64 = {k: torch.zeros(n, dtype=torch.float64, device="cuda") for k in ("ax", "ay", "az", "arho")}
+    ctx.dinteract(srt, n, r64)
+    torch.cuda.synchronize()
+    ost = oracle.to_f64(st)
+    for k in ("x", "y", "z"):
+        ost[k] = np.ascontiguousarray(case.pos64[:, "xyz".index(k)])
+    osr = oracle.sort_state(p, ost)
+    got = srt.to_numpy(n)
+    for k in sph.DSTATE_F64 + ("type", "id"):
+        assert np.array_equal(got[k], osr["state"][k]), k
+    acc = oracle.interact(p, osr)
+    n0 = len(acc["ax"])
+    t = osr["state"]["type"][:n0]
+    fl, ng = t == cases.FLUID, t != cases.GHOST
+    gv = np.array(p["g"])
+    a_ref = np.stack([acc["ax"], acc["ay"], acc["az"]], 1)[fl] - gv
+    a_gpu = np.stack([r64[k].cpu().numpy()[:n0] for k in ("ax", "ay", "az")], 1)[fl] - gv
+    ea = relnorm(a_gpu, a_ref)
+    ed = relnorm(r64["arho"].cpu().numpy()[:n0][ng], acc["drho"][ng])
+    print(name, ea, ed, flush=True)
+    assert ea <= 1e-10 and ed <= 1e-10
+    assert ctx.pairs() == int(acc["npair"].sum())
+    assert abs(ctx.dt64() - oracle.dt(p, osr, acc)) <= 1e-12 * oracle.dt(p, osr, acc)
+
+
+def test_fp64_step_and_totals():
+    case = cases.perturb(cases.case_c1(), 16)
+    p, n = case.params, case.n
+    announce(f"fp64 step c1 n={n}")
+    ctx = sph.Context(p, n, F)
+    st = {k: case.state[k] for k in sph.SOA_FIELDS}
+    st["x"], st["y"], st["z"] = case.pos64[:, 0], case.pos64[:, 1], case.pos64[:, 2]
+    cur = sph.F64State.from_numpy(st, capacity=n)
+    nxt = sph.F64State.empty(n)
+    ctx.dstep(cur, nxt, n, 0)
+    torch.cuda.synchronize()
+    dt = ctx.dt64()
+    ost = oracle.to_f64(st)
+    for k in ("x", "y", "z"):
+        ost[k] = np.ascontiguousarray(case.pos64[:, "xyz".index(k)])
+    r = oracle.step(p, ost, 0)
+    assert abs(dt - r["dt"]) <= 1e-12 * r["dt"]
+    got = nxt.to_numpy(n)
+    ref = r["state"]
+    assert np.array_equal(got["id"], ref["id"])
+    s0 = r["srt"]["state"]
+    for k in ("x", "y", "z", "vx", "vy", "vz", "rho"):
+        inc_ref = ref[k] - s0[k]
+        assert np.linalg.norm(got[k] - ref[k]) <= 1e-9 * np.linalg.norm(inc_ref) + 1e-15, k
+    tot = ctx.dtotals(nxt, n)
+    tref = oracle.totals(p, ref)
+    for q in range(8):
+        assert abs(tot[q] - tref[q]) <= 1e-11 * max(abs(tref[q]), 1e-30), q

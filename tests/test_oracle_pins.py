@@ -467,3 +467,27 @@ def test_boundaries_fixed_and_counts_conserved(orc):
         ref = v[np.argsort(case.state["id"][case.state["type"] == cases.BOUNDARY])]
         assert np.array_equal(cur, ref), k
     assert not np.array_equal(s["rho"][s["type"] == cases.BOUNDARY], 1000.0)
+
+
+def test_internal_energy_is_work_of_pressure(orc):
+    """e(rho) = int_rho0^rho p(r)/r^2 dr (barotropic fluid): quadrature of the
+    oracle's own equation of state against the closed form."""
+    p = cases.base_params(0.01)
+    assert orc.internal_energy(p, p["rho0"]) == 0.0
+    for rho in (985.0, 999.0, 1001.5, 1020.0, 1060.0):
+        val, _ = quad(lambda r: orc.eos(p, r)[0] / (r * r), p["rho0"], rho, epsabs=0, epsrel=1e-13)
+        e = orc.internal_energy(p, rho)
+        assert abs(e - val) <= 1e-9 * abs(val) + 1e-15
+        assert e > 0.0  # p/rho^2 changes sign with rho - rho0: e >= 0 on both sides
+
+
+def test_totals_simple_sums(orc):
+    case = cases.perturb(cases.small_tank(), 5)
+    st = orc.to_f64(case.state)
+    p = case.params
+    t = orc.totals(p, st)
+    ng = st["type"] != cases.GHOST
+    m = p["mass"]
+    assert t[7] == ng.sum() and abs(t[0] - m * ng.sum()) <= 1e-12 * t[0]
+    assert abs(t[3] - m * st["vz"][ng].sum()) <= 1e-12 * m * np.abs(st["vz"][ng]).sum()
+    assert abs(t[5] - m * 9.81 * st["z"][ng].sum()) <= 1e-12 * abs(t[5])
