@@ -83,6 +83,8 @@ def lib():
         L.orc_internal_energy.argtypes = [pp, C.c_double]
         L.orc_internal_energy.restype = C.c_double
         L.orc_totals.argtypes = [pp, C.c_int64, d, d, d, d, d, d, d, u8, d]
+        L.orc_nearest.argtypes = [pp, C.c_int64, d, d, d, u32, u32, u32, C.c_int64, i64,
+                                  C.c_int32, i32, i32]
         _lib = L
     return _lib
 
@@ -288,6 +290,23 @@ def neighbours_cells(p: dict, srt: dict, cap: int = 1 << 24):
                                    _ptr(row, C.c_int64), _ptr(cols, C.c_int32), cap)
     assert m <= cap
     return row, cols[:m].copy()
+
+
+def nearest(p: dict, srt: dict, sel, k: int = 64):
+    """The k nearest neighbours (by FP32 squared distance, then index) of the
+    sorted particles ``sel``: (nbr [len(sel), k] int32 with -1 padding, total
+    neighbour count per particle)."""
+    s = srt["state"]
+    n0 = int(srt["counts"][0])
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    m = sel.shape[0]
+    nbr = np.full((m, k), -1, dtype=np.int32)
+    cnt = np.zeros(m, dtype=np.int32)
+    lib().orc_nearest(C.byref(make_params(p)), n0, _d(s["x"]), _d(s["y"]), _d(s["z"]),
+                      _ptr(srt["keys"], C.c_uint32), _ptr(srt["begin"], C.c_uint32),
+                      _ptr(srt["end"], C.c_uint32), m, _ptr(sel, C.c_int64), k,
+                      _ptr(nbr, C.c_int32), _ptr(cnt, C.c_int32))
+    return nbr, cnt
 
 
 def dt(p: dict, srt: dict, acc: dict) -> float:
