@@ -58,7 +58,12 @@ enum {
     SPH_S_DT = 1u << 1,           /* dt not finite or not positive                        */
     SPH_S_RUN_OVERFLOW = 1u << 2, /* a 3-cell neighbour run held > 4095 particles: the
                                      excess was skipped, results invalid                  */
-    SPH_S_EXCLUDED = 1u << 3      /* some particles lie outside the cell grid (label 3)   */
+    SPH_S_EXCLUDED = 1u << 3,     /* some particles lie outside the cell grid (label 3)   */
+    SPH_S_NN_RANGE = 1u << 4,     /* surrogate: a result was non-finite or its density
+                                     left the allowed band (sph_nn_apply, sph_nn_advance) */
+    SPH_S_NN_LIST = 1u << 5       /* surrogate: a particle had more than 128 neighbours in
+                                     support; its row used the nearest 64 of the first
+                                     128 found                                             */
 };
 
 /* Run parameters. */
@@ -291,6 +296,132 @@ int sph_dtotals(sph_ctx *ctx, const sph_dstate *s, uint32_t n, double *out, void
 /* dt of the last sph_cinteract / sph_cstep / sph_dinteract / sph_dstep in
  * FP64 (CFL times the FP64 minimum of the per-particle limits). */
 int sph_get_dt64(sph_ctx *ctx, double *dt, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned surrogate. An addition to the paper's method: a multilayer
+ * perceptron that advances fluid and boundary particles by four time steps
+ * at once from their neighbourhoods. Its input row for particle i is built
+ * from the cell list of Sec. 3.1 and the compact-support test of Sec. 2.2:
+ * the 64 nearest neighbours j within 2h (FP32 squared distance
+ * fmaf(dz,dz,fmaf(dy,dy,dx*dx)), ties by sorted index), 8 bfloat16 features
+ * per neighbour slot and 32 for the particle itself (SPH_NN_IN = 544):
+ *   slot s:  (x_j - x_i) inv_len, (y_j - y_i) inv_len, (z_j - z_i) inv_len,
+ *            (u_j - u_i) inv_vel (3), (rho_j - rho_ref) inv_rho, kind_j,
+ *            zeros for an empty slot;
+ *   own:     (rho_i - rho_ref) inv_rho, u_i inv_vel (3), count_i / 64,
+ *            kind_i, 26 zeros;
+ * kind = -1 for boundary particles, +1 otherwise; count_i = neighbours in
+ * support before truncation; each feature is an FP32 difference times an
+ * FP32 scale rounded to bfloat16 (nearest, ties to even). Ghost rows are zero.
+ * Network: 544 -> w -> w -> w -> 4, SiLU after each hidden layer, bfloat16
+ * weights and activations with FP32 accumulation on the matrix cores, FP32
+ * master weights with Adam. Outputs, scaled: (du_x, du_y, du_z, drho) over
+ * the four steps.
+ * ------------------------------------------------------------------------- */
+#define SPH_NN_SLOTS 64
+#define SPH_NN_IN 544
+#define SPH_NN_OUT 4
+#define SPH_NN_LAYERS 4
+
+typedef struct sph_nn_scales {
+    float inv_len; /* 1 / length scale (1/h)            */
+    float inv_vel; /* 1 / velocity scale                */
+    float rho_ref; /* reference density (rho0)          */
+    float inv_rho; /* 1 / density scale                 */
+} sph_nn_scales;
+
+/* Network and training workspace; every buffer is caller-owned device
+ * memory (FP32 unless noted). Layer l maps in_l -> out_l with
+ * (in, out) = (544, w), (w, w), (w, w), (w, 4); W[l] is row-major out x in.
+ * The kernels read the bfloat16 copies wb[l]; sph_mlp_sync and
+ * sph_mlp_adam refresh them from the FP32 masters w[l]. */
+typedef struct sph_mlp {
+    int32_t width;      /* hidden width: multiple of 16, 16..256             */
+    uint32_t capacity;  /* rows of the workspace (training batch, <= 2^20)    */
+    float *w[4], *b[4]; /* master weights [out][in] and biases [out]          */
+    void *wb[4];        /* bfloat16 copies of w[l]                            */
+    float *gw[4], *gb[4];                 /* gradients of the last backward   */
+    float *mw[4], *vw[4], *mb[4], *vb[4]; /* Adam moments                     */
+    float *z[4];        /* pre-activations [capacity][out_l]                 */
+    void *a[3];         /* bfloat16 hidden activations [capacity][width]      */
+    float *da;          /* [capacity][width]                                  */
+    void *dz;           /* bfloat16 [capacity][width]                         */
+    float *dy;          /* [capacity][4]                                      */
+    float *work;        /* sph_mlp_work_floats(width, capacity) floats        */
+    float *loss;        /* [1]: loss of the last sph_mlp_backward             */
+} sph_mlp;
+
+/* Size of sph_mlp.work (split-K partial products of the weight gradients
+ * and loss partials), in floats. */
+uint64_t sph_mlp_work_floats(int32_t width, uint32_t capacity);
+
+/* Refresh the bfloat16 weight copies from the FP32 masters. */
+int sph_mlp_sync(sph_ctx *ctx, sph_mlp *net, void *stream);
+
+/* Input rows for particles of the sorted state of the last sph_sort (same
+ * n): row r describes sorted particle rows[r] (rows == NULL: particle r).
+ * x: bfloat16 [nrows][SPH_NN_IN], device. A row index outside the label-0
+ * prefix gives a zero row. Re-packs the sorted arrays first, so the state
+ * may have been changed in place since the sort (not reordered). */
+int sph_nn_features(sph_ctx *ctx, const sph_soa *sorted, const int32_t *rows, uint32_t nrows,
+                    const sph_nn_scales *scales, void *x, void *stream);
+
+/* where[id[k]] = k for k < n (ids must be a permutation of 0..n-1). */
+int sph_nn_index(sph_ctx *ctx, const int32_t *id, uint32_t n, int32_t *where, void *stream);
+
+/* Training targets: for r < nrows, particle k = rows[r] (or r) of state a
+ * and the particle with the same id in state b (index where_b[id]):
+ * t[4r..4r+3] = ((u_b - u_a) inv_dv (3 components), (rho_b - rho_a) inv_dr),
+ * FP32. */
+int sph_nn_targets(sph_ctx *ctx, const sph_soa *a, const sph_soa *b, const int32_t *where_b,
+                   const int32_t *rows, uint32_t nrows, float inv_dv, float inv_dr, float *t,
+                   void *stream);
+
+/* Forward pass of rows x (bfloat16 [rows][SPH_NN_IN]) into y (FP32
+ * [rows][4]); keeps the activations in net for sph_mlp_backward.
+ * rows <= net->capacity. */
+int sph_mlp_forward(sph_ctx *ctx, sph_mlp *net, const void *x, uint32_t rows, float *y,
+                    void *stream);
+
+/* Loss L = sum_{r,c} wcol[c] (y - t)^2 / (4 rows) of the last forward pass
+ * (same x and rows) into net->loss, and its gradients into gw, gb.
+ * wcol: 4 host floats. */
+int sph_mlp_backward(sph_ctx *ctx, sph_mlp *net, const void *x, uint32_t rows, const float *t,
+                     const float *wcol, void *stream);
+
+/* One Adam step (step number t >= 1, bias-corrected) on every weight and
+ * bias from gw, gb; refreshes the bfloat16 copies. */
+int sph_mlp_adam(sph_ctx *ctx, sph_mlp *net, float lr, float beta1, float beta2, float eps,
+                 uint32_t t, void *stream);
+
+/* Apply network outputs y (FP32 [nrows][4], row r = sorted particle r) to
+ * the sorted state over a span dt4 of four steps: fluid u += y[0..2]
+ * dv_scale, x += dt4 (u_old + u_new)/2; fluid and boundary rho += y[3]
+ * dr_scale; ghosts untouched. The previous-step arrays are set to one step
+ * back along the same change (new - change/4), so a following Verlet step
+ * continues the leapfrog. A non-finite result or |rho/rho0 - 1| > rho_tol
+ * sets SPH_S_NN_RANGE. */
+int sph_nn_apply(sph_ctx *ctx, sph_soa *sorted, const float *y, uint32_t nrows, float dv_scale,
+                 float dr_scale, float dt4, float rho_tol, void *stream);
+
+/* One surrogate advance: sort cur into next (as sph_sort), then one fused
+ * kernel builds each particle's input row, runs the network (width 128) and
+ * applies the result to next as sph_nn_apply does. */
+int sph_nn_advance(sph_ctx *ctx, const sph_mlp *net, const sph_soa *cur, sph_soa *next,
+                   uint32_t n, const sph_nn_scales *scales, float dv_scale, float dr_scale,
+                   float dt4, float rho_tol, void *stream);
+
+/* Error of a surrogate state s against a reference state r reached from the
+ * same base state b by plain SPH steps, over the fluid particles of s
+ * (matched by id through where_r and where_b, built by sph_nn_index):
+ * out[0] max |rho_s - rho_r| / rho_r, out[1] sum (rho_s - rho_r)^2,
+ * out[2] sum (rho_r - rho_b)^2, out[3] sum |u_s - u_r|^2,
+ * out[4] sum |u_r - u_b|^2, out[5] sum |x_s - x_r|^2,
+ * out[6] sum |x_r - x_b|^2, out[7] fluid count. 8 host doubles;
+ * synchronises. */
+int sph_nn_judge(sph_ctx *ctx, const sph_soa *s, const sph_soa *r, const sph_soa *b,
+                 const int32_t *where_r, const int32_t *where_b, uint32_t n, double *out,
+                 void *stream);
 
 #ifdef __cplusplus
 }

@@ -128,10 +128,13 @@ class Case:
 
 
 def tank_walls(nx: int, ny: int, nz: int) -> np.ndarray:
-    """Lattice indices (i,j,k) of one wall layer on x=0, x=nx, y=0, y=ny, z=0."""
-    I, J, K = _lattice(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1))
-    on = (I == 0) | (I == nx) | (J == 0) | (J == ny) | (K == 0)
-    return np.stack([I[on], J[on], K[on]], axis=1)
+    """Lattice indices (i,j,k) of one wall layer on x=0, x=nx, y=0, y=ny, z=0,
+    each point once, in lexicographic order."""
+    ii, jj, kk = np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1)
+    faces = [np.stack(_lattice([0], jj, kk), 1), np.stack(_lattice([nx], jj, kk), 1),
+             np.stack(_lattice(ii, [0], kk), 1), np.stack(_lattice(ii, [ny], kk), 1),
+             np.stack(_lattice(ii, jj, [0]), 1)]
+    return np.unique(np.concatenate(faces, axis=0), axis=0)
 
 
 def obstacle_surface(i0: int, j0: int, side: int, height: int) -> np.ndarray:
@@ -203,6 +206,39 @@ def case_c4(seed: int = 7, obstacle_seed: int = 2) -> Case:
     return dam_break(0.0013, 1231, 515, 308, 308, 231, jitter_seed=seed, obstacles=3,
                      obstacle_seed=obstacle_seed, obstacle_side=92, obstacle_height=308,
                      name="dam_break_3obst_dp0.0013")
+
+
+def obstacle_tank(seed: int, *, dp: float = 0.004, nx: int = 200, ny: int = 84, nz: int = 100,
+                  nfx: int = 50, nfz: int = 75, n_obstacles: int = 2, side: int = 30) -> Case:
+    """Training layout for the learned surrogate: a 0.8 x 0.34 x 0.4 m tank at
+    dp = 0.004 m with a 0.2 m long, 0.3 m high water column (the height of the
+    1.47M-particle workload, so the same hydrostatic density range) and
+    ``n_obstacles`` hollow square obstacles whose positions in front of the
+    column are drawn from ``seed`` (non-overlapping, inside the tank)."""
+    params = base_params(dp)
+    cs = 2.0 * params["h"]
+    rng = _rng(1000 + seed)
+    placed, bnd = [], [tank_walls(nx, ny, nz)]
+    while len(placed) < n_obstacles:
+        i0 = int(rng.integers(nfx + 10, nx - side - 5))
+        j0 = int(rng.integers(3, ny - side - 3))
+        box = (i0 - 2, i0 + side + 2, j0 - 2, j0 + side + 2)
+        if any(not (box[1] < b[0] or b[1] < box[0] or box[3] < b[2] or b[3] < box[2])
+               for b in placed):
+            continue
+        placed.append(box)
+        bnd.append(obstacle_surface(i0, j0, side, nz))
+    bidx = np.unique(np.concatenate(bnd, axis=0), axis=0)
+    I, J, K = _lattice(np.arange(1, nfx + 1), np.arange(1, ny), np.arange(1, nfz + 1))
+    fidx = np.stack([I, J, K], axis=1)
+    fpos = fidx * dp + 1e-4 * dp * _rng(seed).uniform(-1.0, 1.0, size=fidx.shape)
+    bpos = bidx.astype(np.float64) * dp
+    frho = hydrostatic_rho(params, nfz * dp - fpos[:, 2])
+    pos = np.concatenate([bpos, fpos], axis=0)
+    typ = np.concatenate([np.full(len(bpos), BOUNDARY), np.full(len(fpos), FLUID)])
+    rho = np.concatenate([np.full(len(bpos), params["rho0"]), frho])
+    set_grid(params, (-cs, -cs, -cs), (nx * dp + cs, ny * dp + cs, 1.5 * nz * dp))
+    return Case(f"obstacle_tank{seed}", params, _make_state(pos, typ, rho), pos)
 
 
 def sub_block(case: Case, lo, side: float, margin: float) -> tuple[np.ndarray, np.ndarray]:

@@ -62,7 +62,7 @@ void free_events(sph_ctx *c) {
 
 void free_all(sph_ctx *c) {
     free_events(c);
-    void *vptrs[] = {c->p64, c->drate, c->tot_part};
+    void *vptrs[] = {c->p64, c->drate, c->tot_part, c->nn_part, c->nn_out};
     for (void *p : vptrs)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
@@ -194,6 +194,8 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     c->features = p->features;
     c->tot_blocks = (uint32_t)std::min<size_t>(1024, (cap + kTotThreads - 1) / kTotThreads);
     ALLOC(c->tot_part, (size_t)8 * (c->tot_blocks + 1) * sizeof(double));
+    ALLOC(c->nn_part, (size_t)8 * (cap / 256 + 2) * sizeof(double));
+    ALLOC(c->nn_out, 8 * sizeof(double));
     if (p->features & SPH_F_FP64) {
         ALLOC(c->p64, cap * sizeof(double));
         ALLOC(c->drate, 4 * cap * sizeof(double));
@@ -645,3 +647,230 @@ int sph_get_dt64(sph_ctx *c, double *dt, void *stream) {
 }
 
 }  // extern "C"
+
+/* ------------------------------------------------------------ surrogate */
+
+static void layer_dims(int width, int l, int *in, int *out) {
+    *in = l == 0 ? SPH_NN_IN : width;
+    *out = l == SPH_NN_LAYERS - 1 ? SPH_NN_OUT : width;
+}
+
+static uint64_t split_floats(int32_t width) {
+    return (uint64_t)kMlpSplits * (uint64_t)width * SPH_NN_IN;
+}
+
+uint64_t sph_mlp_work_floats(int32_t width, uint32_t capacity) {
+    if (width <= 0) return 0;
+    return split_floats(width) + ((uint64_t)capacity * SPH_NN_OUT + 255) / 256 + 64;
+}
+
+static int mlp_check(sph_ctx *c, const sph_mlp *m, bool train) {
+    if (!m) return fail(c, SPH_E_INVALID_ARG, "null network");
+    if (m->width < 16 || m->width > 256 || m->width % 16)
+        return fail(c, SPH_E_INVALID_ARG, "width %d: must be a multiple of 16 in [16, 256]",
+                    (int)m->width);
+    for (int l = 0; l < SPH_NN_LAYERS; l++)
+        if (!m->w[l] || !m->b[l] || !m->wb[l])
+            return fail(c, SPH_E_INVALID_ARG, "null weight array of layer %d", l);
+    if (!train) return SPH_OK;
+    if (m->capacity == 0 || m->capacity > (1u << 20))
+        return fail(c, SPH_E_INVALID_ARG, "workspace capacity %u not in [1, 2^20]", m->capacity);
+    for (int l = 0; l < SPH_NN_LAYERS; l++)
+        if (!m->gw[l] || !m->gb[l] || !m->mw[l] || !m->vw[l] || !m->mb[l] || !m->vb[l] ||
+            !m->z[l])
+            return fail(c, SPH_E_INVALID_ARG, "null training array of layer %d", l);
+    for (int l = 0; l < SPH_NN_LAYERS - 1; l++)
+        if (!m->a[l]) return fail(c, SPH_E_INVALID_ARG, "null activation array %d", l);
+    if (!m->da || !m->dz || !m->dy || !m->work || !m->loss)
+        return fail(c, SPH_E_INVALID_ARG, "null training workspace");
+    return SPH_OK;
+}
+
+int sph_mlp_sync(sph_ctx *c, sph_mlp *m, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if ((r = mlp_check(c, m, false))) return r;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < SPH_NN_LAYERS && e == hipSuccess; l++) {
+        int in, out;
+        layer_dims(m->width, l, &in, &out);
+        e = launch_f32_to_bf16(m->w[l], m->wb[l], (long long)in * out, (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "mlp sync");
+    return SPH_OK;
+}
+
+int sph_nn_features(sph_ctx *c, const sph_soa *sorted, const int32_t *rows, uint32_t nrows,
+                    const sph_nn_scales *scales, void *x, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!soa_ok(sorted) || !scales || (nrows && !x))
+        return fail(c, SPH_E_INVALID_ARG, "null argument");
+    if (!c->have_sort || c->last_path != 0)
+        return fail(c, SPH_E_STATE, "sph_nn_features needs a preceding sph_sort");
+    if (!rows && nrows > c->sorted_n)
+        return fail(c, SPH_E_INVALID_ARG, "nrows = %u > n = %u of the sort", nrows, c->sorted_n);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_pack(c, *sorted, c->sorted_n, s);
+    if (e == hipSuccess) e = launch_nn_features(c, sorted->type, rows, nrows, *scales, x, s);
+    if (e != hipSuccess) return hip_fail(c, e, "features");
+    return SPH_OK;
+}
+
+int sph_nn_index(sph_ctx *c, const int32_t *id, uint32_t n, int32_t *where, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (n && (!id || !where)) return fail(c, SPH_E_INVALID_ARG, "null argument");
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    hipError_t e = launch_id_scatter(id, n, where, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "index");
+    return SPH_OK;
+}
+
+int sph_nn_targets(sph_ctx *c, const sph_soa *a, const sph_soa *b, const int32_t *where_b,
+                   const int32_t *rows, uint32_t nrows, float inv_dv, float inv_dr, float *t,
+                   void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!soa_ok(a) || !soa_ok(b) || (nrows && (!where_b || !t)))
+        return fail(c, SPH_E_INVALID_ARG, "null argument");
+    hipError_t e = launch_nn_targets(*a, *b, where_b, rows, nrows, inv_dv, inv_dr, t,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "targets");
+    return SPH_OK;
+}
+
+int sph_mlp_forward(sph_ctx *c, sph_mlp *m, const void *x, uint32_t rows, float *y,
+                    void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if ((r = mlp_check(c, m, true))) return r;
+    if (rows > m->capacity)
+        return fail(c, SPH_E_CAPACITY, "rows = %u > workspace capacity %u", rows, m->capacity);
+    if (rows == 0) return SPH_OK;
+    if (!x || !y) return fail(c, SPH_E_INVALID_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    const void *A = x;
+    for (int l = 0; l < SPH_NN_LAYERS && e == hipSuccess; l++) {
+        int in, out;
+        layer_dims(m->width, l, &in, &out);
+        // Z = A W^T: B[k][n] = W[n][k]
+        e = launch_gemm(A, m->wb[l], m->z[l], (int)rows, out, in, in, 1, 1, in, out, 1, 0,
+                        nullptr, s);
+        if (e != hipSuccess) break;
+        if (l < SPH_NN_LAYERS - 1) {
+            e = launch_bias_act(m->z[l], m->b[l], m->a[l], nullptr, rows, out, 1, s);
+            A = m->a[l];
+        } else {
+            e = launch_bias_act(m->z[l], m->b[l], nullptr, y, rows, out, 0, s);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "mlp forward");
+    return SPH_OK;
+}
+
+int sph_mlp_backward(sph_ctx *c, sph_mlp *m, const void *x, uint32_t rows, const float *t,
+                     const float *wcol, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if ((r = mlp_check(c, m, true))) return r;
+    if (rows == 0 || rows > m->capacity)
+        return fail(c, SPH_E_CAPACITY, "rows = %u not in [1, %u]", rows, m->capacity);
+    if (!x || !t || !wcol) return fail(c, SPH_E_INVALID_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    float *part = m->work, *lpart = m->work + split_floats(m->width);
+    hipError_t e = launch_mse(m->z[SPH_NN_LAYERS - 1], t, wcol, m->dy, rows, SPH_NN_OUT, lpart,
+                              m->loss, s);
+    if (e == hipSuccess) e = launch_act_back(m->dy, nullptr, m->dz, (long long)rows * SPH_NN_OUT, 0, s);
+    for (int l = SPH_NN_LAYERS - 1; l >= 0 && e == hipSuccess; l--) {
+        int in, out;
+        layer_dims(m->width, l, &in, &out);
+        const void *Ap = l == 0 ? x : m->a[l - 1];
+        // dW (out x in) = dZ^T (out x rows) . A_prev (rows x in)
+        e = launch_gemm(m->dz, Ap, m->gw[l], out, in, (int)rows, 1, out, in, 1, in, 1, 0, part, s);
+        if (e == hipSuccess) e = launch_colsum(m->dz, rows, out, m->gb[l], s);
+        if (l == 0 || e != hipSuccess) continue;
+        // dA (rows x in) = dZ (rows x out) . W (out x in); dZ_prev = dA * SiLU'(Z_prev)
+        e = launch_gemm(m->dz, m->wb[l], m->da, (int)rows, in, out, out, 1, in, 1, in, 1, 0,
+                        nullptr, s);
+        if (e == hipSuccess)
+            e = launch_act_back(m->da, m->z[l - 1], m->dz, (long long)rows * in, 1, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "mlp backward");
+    return SPH_OK;
+}
+
+int sph_mlp_adam(sph_ctx *c, sph_mlp *m, float lr, float beta1, float beta2, float eps,
+                 uint32_t t, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if ((r = mlp_check(c, m, true))) return r;
+    if (t == 0 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(c, SPH_E_INVALID_ARG, "Adam: t >= 1 and betas in [0, 1) required");
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < SPH_NN_LAYERS && e == hipSuccess; l++) {
+        int in, out;
+        layer_dims(m->width, l, &in, &out);
+        e = launch_adam(m->w[l], m->mw[l], m->vw[l], m->gw[l], m->wb[l], (long long)in * out, lr,
+                        beta1, beta2, eps, c1, c2, s);
+        if (e == hipSuccess)
+            e = launch_adam(m->b[l], m->mb[l], m->vb[l], m->gb[l], nullptr, out, lr, beta1, beta2,
+                            eps, c1, c2, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "adam");
+    return SPH_OK;
+}
+
+int sph_nn_apply(sph_ctx *c, sph_soa *sorted, const float *y, uint32_t nrows, float dv_scale,
+                 float dr_scale, float dt4, float rho_tol, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!soa_ok(sorted) || (nrows && !y)) return fail(c, SPH_E_INVALID_ARG, "null argument");
+    if (!c->have_sort || c->last_path != 0 || nrows > c->sorted_n)
+        return fail(c, SPH_E_STATE, "sph_nn_apply needs a preceding sph_sort of >= nrows");
+    hipError_t e = launch_nn_apply(c, *sorted, y, nrows, dv_scale, dr_scale, dt4, rho_tol,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "apply");
+    c->have_dt = false;
+    return SPH_OK;
+}
+
+int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *next, uint32_t n,
+                   const sph_nn_scales *scales, float dv_scale, float dr_scale, float dt4,
+                   float rho_tol, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if ((r = mlp_check(c, m, false))) return r;
+    if (m->width != 128) return fail(c, SPH_E_INVALID_ARG, "the fused advance needs width 128");
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    if (!soa_ok(cur) || !soa_ok(next) || !scales)
+        return fail(c, SPH_E_INVALID_ARG, "null argument");
+    if (cur->x == next->x || cur->rho == next->rho || cur->type == next->type || cur->id == next->id)
+        return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
+    hipStream_t s = (hipStream_t)stream;
+    if ((r = do_sort(c, cur, next, n, s))) return r;
+    hipError_t e = launch_nn_fused(c, *m, *next, n, *scales, dv_scale, dr_scale, dt4, rho_tol, s);
+    if (e != hipSuccess) return hip_fail(c, e, "surrogate advance");
+    c->have_dt = false;
+    return SPH_OK;
+}
+
+int sph_nn_judge(sph_ctx *c, const sph_soa *sv, const sph_soa *rv, const sph_soa *bv,
+                 const int32_t *where_r, const int32_t *where_b, uint32_t n, double *out,
+                 void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!soa_ok(sv) || !soa_ok(rv) || !soa_ok(bv) || !out || (n && (!where_r || !where_b)))
+        return fail(c, SPH_E_INVALID_ARG, "null argument");
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_nn_judge(*sv, *rv, *bv, where_r, where_b, n, c->nn_part, c->nn_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, c->nn_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "judge");
+    return SPH_OK;
+}

@@ -7,13 +7,13 @@
 namespace sph {
 
 #ifndef SPH_INTERACT_CAP
-#define SPH_INTERACT_CAP 128
+#define SPH_INTERACT_CAP 64
 #endif
 #ifndef SPH_TEST_UNROLL
 #define SPH_TEST_UNROLL 8
 #endif
 #ifndef SPH_COL_SLACK
-#define SPH_COL_SLACK 0
+#define SPH_COL_SLACK 24
 #endif
 constexpr int kCap = SPH_INTERACT_CAP;   // neighbour entries buffered per lane before a flush
 // At each run boundary the whole wave flushes together if any lane has more
@@ -25,30 +25,6 @@ constexpr int kSlots = kCap + kUnroll;   // list slots (a group of candidates ma
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9 buffer resource: 32-bit raw dwords
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-
-#ifndef SPH_XCD_CHUNK
-#define SPH_XCD_CHUNK 0
-#endif
-// Workgroups are handed to the 8 XCDs round-robin; renumber them so that each
-// XCD works on contiguous stretches of the sorted particles (neighbour data
-// then stays in that XCD's L2). kXcdChunk = 0: one stretch per XCD; C > 1:
-// stretches of C blocks dealt to the XCDs in turn (load balance across a
-// domain whose cost varies along x). Both are bijections of [0, nb).
-constexpr uint32_t kXcdChunk = SPH_XCD_CHUNK;
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
-    constexpr uint32_t X = 8;
-    if (kXcdChunk == 1) return b;
-    if (kXcdChunk == 0) {
-        const uint32_t q = nb / X, r = nb % X, x = b % X, k = b / X;
-        return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-    }
-    // full rounds of X*C blocks: XCD x takes the x-th stretch of C in each round
-    const uint32_t round = X * kXcdChunk;
-    const uint32_t full = nb / round * round;
-    if (b >= full) return b;  // the last partial round keeps the hardware order
-    const uint32_t x = b % X, k = b / X;  // k-th block that XCD x receives
-    return (k / kXcdChunk) * round + x * kXcdChunk + k % kXcdChunk;
-}
 
 // One lane per particle i of the label-0 prefix (Sec. 3.2: one thread per
 // particle, neighbours in its own cell and the 26 adjacent ones). With an

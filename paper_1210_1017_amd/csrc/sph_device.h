@@ -53,6 +53,25 @@ __device__ __forceinline__ uint32_t cell_key(const KParams &kp, float px, float 
     return (label << kp.cell_bits) | cell;
 }
 
+// Workgroups are handed to the 8 XCDs of the chip round-robin. Renumber them
+// so that each XCD receives stretches of kXcdChunk consecutive blocks (the
+// neighbour data of a stretch then stays in one XCD's L2) dealt out in turn
+// over the whole domain (the cost per particle varies along x: dealing
+// stretches keeps the XCDs evenly loaded). A bijection of [0, nb); the last
+// partial round keeps the hardware order.
+#ifndef SPH_XCD_CHUNK
+#define SPH_XCD_CHUNK 16
+#endif
+constexpr uint32_t kXcdChunk = SPH_XCD_CHUNK;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    constexpr uint32_t X = 8;
+    const uint32_t round = X * kXcdChunk;
+    const uint32_t full = nb / round * round;
+    if (kXcdChunk <= 1 || b >= full) return b;
+    const uint32_t x = b % X, k = b / X;  // k-th block that XCD x receives
+    return (k / kXcdChunk) * round + x * kXcdChunk + k % kXcdChunk;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = __lane_id();
 #pragma unroll

@@ -78,6 +78,8 @@ struct sph_ctx {
     double *p64 = nullptr;        // p/rho^2 of the sorted FP64 state
     double *drate = nullptr;      // 4 * capacity FP64 rates of sph_dstep
     double *tot_part = nullptr;   // 8 doubles per totals block
+    double *nn_part = nullptr;    // 8 doubles per surrogate-judge block
+    double *nn_out = nullptr;     // 8 doubles: judge result
     uint32_t tot_blocks = 0;
     int last_path = 0;            // 0 plain, 1 cell, 2 FP64: which state the tables describe
     // optional per-phase timing of sph_step (events: start, sorted, interacted, updated)
@@ -137,6 +139,38 @@ hipError_t launch_update_d(sph_ctx *c, const sph_dstate &st, const sph_drates &r
                            uint64_t step, hipStream_t s);
 hipError_t launch_totals_d(sph_ctx *c, const sph_dstate &st, uint32_t n, double *out_host,
                            hipStream_t s);
+
+// mlp.hip (learned surrogate)
+constexpr int kMlpSplits = 32;  // split-K slices of a weight-gradient GEMM, at most
+hipError_t launch_nn_features(sph_ctx *c, const uint8_t *type, const int32_t *rows,
+                              uint32_t nrows, const sph_nn_scales &s, void *X, hipStream_t st);
+hipError_t launch_gemm(const void *A, const void *B, float *C, int M, int N, int K,
+                       long long sam, long long sak, long long sbk, long long sbn, long long scm,
+                       long long scn, int accumulate, float *part, hipStream_t s);
+hipError_t launch_bias_act(float *Z, const float *b, void *Aout, float *Fout, long long rows,
+                           int cols, int act, hipStream_t s);
+hipError_t launch_act_back(const float *dA, const float *Z, void *dZ, long long n, int act,
+                           hipStream_t s);
+hipError_t launch_mse(const float *Y, const float *T, const float *wcol, float *dY,
+                      long long rows, int cols, float *part, float *loss, hipStream_t s);
+hipError_t launch_colsum(const void *dZ, long long rows, int cols, float *db, hipStream_t s);
+hipError_t launch_adam(float *w, float *m, float *v, const float *g, void *wb, long long n,
+                       float lr, float b1, float b2, float eps, float c1, float c2,
+                       hipStream_t s);
+hipError_t launch_f32_to_bf16(const float *a, void *b, long long n, hipStream_t s);
+hipError_t launch_id_scatter(const int32_t *id, uint32_t n, int32_t *where, hipStream_t s);
+hipError_t launch_nn_targets(const sph_soa &a, const sph_soa &b, const int32_t *where_b,
+                             const int32_t *rows, uint32_t nrows, float inv_dv, float inv_dr,
+                             float *T, hipStream_t s);
+hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, uint32_t nrows,
+                           float dv_scale, float dr_scale, float dt4, float rho_tol,
+                           hipStream_t s);
+hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
+                           const int32_t *where_r, const int32_t *where_b, uint32_t n,
+                           double *part, double *out, hipStream_t s);
+hipError_t launch_nn_fused(sph_ctx *c, const sph_mlp &m, const sph_soa &st, uint32_t n,
+                           const sph_nn_scales &s, float dv_scale, float dr_scale, float dt4,
+                           float rho_tol, hipStream_t stream);
 
 // update.hip
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,

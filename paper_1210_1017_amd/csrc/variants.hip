@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact_cell(
 
     const int tid = threadIdx.x;
     const uint32_t n0 = info->n_label[0];
-    const uint32_t i = blockIdx.x * kInteractThreads + tid;
+    const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kInteractThreads + tid;
     const bool inrange = i < n0;
     const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;
     double dtmin = INFINITY;

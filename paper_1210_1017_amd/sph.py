@@ -21,6 +21,8 @@ SOA_FIELDS = F32_FIELDS + ("type", "id")
 
 SPH_OK = 0
 STATUS_NONFINITE, STATUS_DT, STATUS_RUN_OVERFLOW, STATUS_EXCLUDED = 1, 2, 4, 8
+STATUS_NN_RANGE, STATUS_NN_LIST = 16, 32
+NN_SLOTS, NN_IN, NN_OUT, NN_LAYERS = 64, 544, 4, 4
 
 
 class SphError(RuntimeError):
@@ -77,6 +79,22 @@ class Counts(C.Structure):
         return {k: list(getattr(self, k)) for k, _ in self._fields_}
 
 
+class NnScales(C.Structure):
+    _fields_ = [("inv_len", C.c_float), ("inv_vel", C.c_float), ("rho_ref", C.c_float),
+                ("inv_rho", C.c_float)]
+
+
+_P4 = C.c_void_p * 4
+
+
+class MlpStruct(C.Structure):
+    _fields_ = [("width", C.c_int32), ("capacity", C.c_uint32),
+                ("w", _P4), ("b", _P4), ("wb", _P4), ("gw", _P4), ("gb", _P4),
+                ("mw", _P4), ("vw", _P4), ("mb", _P4), ("vb", _P4), ("z", _P4),
+                ("a", C.c_void_p * 3), ("da", C.c_void_p), ("dz", C.c_void_p),
+                ("dy", C.c_void_p), ("work", C.c_void_p), ("loss", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -125,6 +143,20 @@ def lib() -> C.CDLL:
         L.sph_dtotals.argtypes = [vp, P(DState), u32, P(C.c_double), vp]
         L.sph_get_dt64.argtypes = [vp, P(C.c_double), vp]
         L.sph_copy_cell_tables.argtypes = [vp, vp, vp, vp]
+        f32 = C.c_float
+        L.sph_mlp_work_floats.argtypes = [C.c_int32, u32]
+        L.sph_mlp_work_floats.restype = u64
+        L.sph_mlp_sync.argtypes = [vp, P(MlpStruct), vp]
+        L.sph_nn_features.argtypes = [vp, P(SoA), vp, u32, P(NnScales), vp, vp]
+        L.sph_nn_index.argtypes = [vp, vp, u32, vp, vp]
+        L.sph_nn_targets.argtypes = [vp, P(SoA), P(SoA), vp, vp, u32, f32, f32, vp, vp]
+        L.sph_mlp_forward.argtypes = [vp, P(MlpStruct), vp, u32, vp, vp]
+        L.sph_mlp_backward.argtypes = [vp, P(MlpStruct), vp, u32, vp, P(f32), vp]
+        L.sph_mlp_adam.argtypes = [vp, P(MlpStruct), f32, f32, f32, f32, u32, vp]
+        L.sph_nn_apply.argtypes = [vp, P(SoA), vp, u32, f32, f32, f32, f32, vp]
+        L.sph_nn_advance.argtypes = [vp, P(MlpStruct), P(SoA), P(SoA), u32, P(NnScales), f32,
+                                     f32, f32, f32, vp]
+        L.sph_nn_judge.argtypes = [vp, P(SoA), P(SoA), P(SoA), vp, vp, u32, P(C.c_double), vp]
         _lib = L
     return _lib
 
@@ -133,7 +165,7 @@ def header_functions() -> list[str]:
     """Names of the functions that include/sph.h declares."""
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(sph_[a-z0-9_]+)\s*\(", txt)))
 
 
 def make_params(p: dict, capacity: int, features: int = 0) -> Params:
@@ -428,6 +460,148 @@ class Context:
         e = torch.empty(nc, dtype=torch.int32, device="cuda")
         self._check(self.L.sph_copy_cell_tables(self.h, _addr(b), _addr(e), _stream_ptr(stream)))
         return b, e
+
+
+    # ------------------------------------------------------------ surrogate
+    def mlp_sync(self, net: "Mlp", stream=None):
+        self._check(self.L.sph_mlp_sync(self.h, C.byref(net.struct()), _stream_ptr(stream)))
+
+    def nn_features(self, srt: DeviceState, rows, nrows: int, scales, X, stream=None):
+        sc = NnScales(*[float(v) for v in scales])
+        self._check(self.L.sph_nn_features(self.h, C.byref(srt.soa()),
+                                           None if rows is None else _addr(rows), nrows,
+                                           C.byref(sc), _addr(X), _stream_ptr(stream)))
+
+    def nn_index(self, ids, n: int, where, stream=None):
+        self._check(self.L.sph_nn_index(self.h, _addr(ids), n, _addr(where), _stream_ptr(stream)))
+
+    def nn_targets(self, a: DeviceState, b: DeviceState, where_b, rows, nrows: int,
+                   inv_dv: float, inv_dr: float, T, stream=None):
+        self._check(self.L.sph_nn_targets(self.h, C.byref(a.soa()), C.byref(b.soa()),
+                                          _addr(where_b), None if rows is None else _addr(rows),
+                                          nrows, inv_dv, inv_dr, _addr(T), _stream_ptr(stream)))
+
+    def mlp_forward(self, net: "Mlp", X, rows: int, Y, stream=None):
+        self._check(self.L.sph_mlp_forward(self.h, C.byref(net.struct()), _addr(X), rows,
+                                           _addr(Y), _stream_ptr(stream)))
+
+    def mlp_backward(self, net: "Mlp", X, rows: int, T, wcol, stream=None):
+        w = (C.c_float * 4)(*[float(v) for v in wcol])
+        self._check(self.L.sph_mlp_backward(self.h, C.byref(net.struct()), _addr(X), rows,
+                                            _addr(T), w, _stream_ptr(stream)))
+
+    def mlp_adam(self, net: "Mlp", lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, t: int | None = None, stream=None):
+        if t is None:
+            net.t += 1
+            t = net.t
+        self._check(self.L.sph_mlp_adam(self.h, C.byref(net.struct()), lr, beta1, beta2, eps,
+                                        int(t), _stream_ptr(stream)))
+
+    def nn_apply(self, srt: DeviceState, Y, nrows: int, dv_scale: float, dr_scale: float,
+                 dt4: float, rho_tol: float, stream=None):
+        self._check(self.L.sph_nn_apply(self.h, C.byref(srt.soa()), _addr(Y), nrows, dv_scale,
+                                        dr_scale, dt4, rho_tol, _stream_ptr(stream)))
+
+    def nn_advance(self, net: "Mlp", cur: DeviceState, nxt: DeviceState, n: int, scales,
+                   dv_scale: float, dr_scale: float, dt4: float, rho_tol: float, stream=None):
+        sc = NnScales(*[float(v) for v in scales])
+        self._check(self.L.sph_nn_advance(self.h, C.byref(net.struct()), C.byref(cur.soa()),
+                                          C.byref(nxt.soa()), n, C.byref(sc), dv_scale, dr_scale,
+                                          dt4, rho_tol, _stream_ptr(stream)))
+
+    def nn_judge(self, s: DeviceState, r: DeviceState, b: DeviceState, where_r, where_b, n: int,
+                 stream=None) -> np.ndarray:
+        out = (C.c_double * 8)()
+        self._check(self.L.sph_nn_judge(self.h, C.byref(s.soa()), C.byref(r.soa()),
+                                        C.byref(b.soa()), _addr(where_r), _addr(where_b), n, out,
+                                        _stream_ptr(stream)))
+        return np.array(list(out))
+
+
+def layer_dims(width: int) -> list[tuple[int, int]]:
+    """(in, out) of the four layers of the surrogate network."""
+    return [(NN_IN, width), (width, width), (width, width), (width, NN_OUT)]
+
+
+class Mlp:
+    """The surrogate network and its training workspace as device tensors
+    (the buffers of ``sph_mlp``). ``train=False`` allocates the weights only
+    (enough for ``nn_advance``)."""
+
+    def __init__(self, width: int = 128, capacity: int = 32768, train: bool = True,
+                 device="cuda"):
+        import torch
+        f32, bf = torch.float32, torch.bfloat16
+        self.width, self.capacity, self.train_mode = int(width), int(capacity), train
+        dims = layer_dims(self.width)
+        z = lambda *s, dt=f32: torch.zeros(*s, dtype=dt, device=device)
+        self.w = [z(o, i) for i, o in dims]
+        self.b = [z(o) for _, o in dims]
+        self.wb = [z(o, i, dt=bf) for i, o in dims]
+        self.t = 0
+        if train:
+            cap = self.capacity
+            self.gw = [z(o, i) for i, o in dims]
+            self.gb = [z(o) for _, o in dims]
+            self.mw = [z(o, i) for i, o in dims]
+            self.vw = [z(o, i) for i, o in dims]
+            self.mb = [z(o) for _, o in dims]
+            self.vb = [z(o) for _, o in dims]
+            self.z = [z(cap, o) for _, o in dims]
+            self.a = [z(cap, self.width, dt=bf) for _ in range(3)]
+            self.da = z(cap, self.width)
+            self.dz = z(cap, self.width, dt=bf)
+            self.dy = z(cap, NN_OUT)
+            self.work = z(int(lib().sph_mlp_work_floats(self.width, cap)))
+            self.loss = z(1)
+
+    def struct(self) -> MlpStruct:
+        s = MlpStruct()
+        s.width, s.capacity = self.width, (self.capacity if self.train_mode else 0)
+        for l in range(NN_LAYERS):
+            s.w[l], s.b[l], s.wb[l] = (self.w[l].data_ptr(), self.b[l].data_ptr(),
+                                       self.wb[l].data_ptr())
+            if self.train_mode:
+                for name in ("gw", "gb", "mw", "vw", "mb", "vb", "z"):
+                    getattr(s, name)[l] = getattr(self, name)[l].data_ptr()
+        if self.train_mode:
+            for l in range(3):
+                s.a[l] = self.a[l].data_ptr()
+            s.da, s.dz, s.dy = self.da.data_ptr(), self.dz.data_ptr(), self.dy.data_ptr()
+            s.work, s.loss = self.work.data_ptr(), self.loss.data_ptr()
+        return s
+
+    def init(self, seed: int):
+        """Seeded initial weights: N(0, 1/in) for the hidden layers (variance
+        preserving for unit-scale inputs), N(0, 0.01^2/in) for the output
+        layer (start near the zero prediction), zero biases."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        arrays = {}
+        for l, (i, o) in enumerate(layer_dims(self.width)):
+            sd = (1.0 if l < NN_LAYERS - 1 else 0.01) / np.sqrt(i)
+            arrays[f"w{l}"] = (rng.standard_normal((o, i)) * sd).astype(np.float32)
+            arrays[f"b{l}"] = np.zeros(o, dtype=np.float32)
+        self.load(arrays)
+
+    def load(self, arrays: dict):
+        """Set the FP32 masters (w0..w3, b0..b3) and zero the Adam state;
+        the caller then runs Context.mlp_sync for the bfloat16 copies."""
+        import torch
+        for l in range(NN_LAYERS):
+            self.w[l].copy_(torch.from_numpy(np.ascontiguousarray(arrays[f"w{l}"], np.float32)))
+            self.b[l].copy_(torch.from_numpy(np.ascontiguousarray(arrays[f"b{l}"], np.float32)))
+            if self.train_mode:
+                for name in ("mw", "vw", "mb", "vb"):
+                    getattr(self, name)[l].zero_()
+        self.t = 0
+
+    def arrays(self) -> dict:
+        out = {}
+        for l in range(NN_LAYERS):
+            out[f"w{l}"] = self.w[l].cpu().numpy().copy()
+            out[f"b{l}"] = self.b[l].cpu().numpy().copy()
+        return out
 
 
 def u32(t) -> np.ndarray:

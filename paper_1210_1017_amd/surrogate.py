@@ -1,0 +1,351 @@
+"""Runtime of the learned surrogate: online training on trajectories that the
+GPU SPH generates, and the advance loop in which plain SPH is the judge of the
+surrogate's error and its fallback.
+
+Every kernel runs in libsph.so (``sph.Context``): the neighbour rows, the
+bfloat16 MFMA forward and backward passes, Adam, the training targets, the
+fused advance and the judge. This module only schedules those calls, draws the
+training rows (a seeded torch generator on the device) and keeps the books.
+
+The network predicts, for each fluid or boundary particle, the mean rates
+du/dt (3 components, in units of ``acc_scale``) and drho/dt (in units of
+``drho_scale``) over the next k = 4 time steps; an advance applies them over
+4 dt with the dt of the latest plain step (the CFL dt is dominated by the
+nearly constant sound speed).
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import asdict, dataclass, field
+
+import numpy as np
+
+from . import cases, sph
+
+K_STEPS = 4
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+@dataclass
+class NnConfig:
+    width: int = 128
+    vel_scale: float = 1.0        # m/s: velocity features are u / vel_scale
+    rho_feat: float = 0.01        # density features are (rho - rho0) / (rho0 rho_feat)
+    acc_scale: float = 1.0        # m/s^2: velocity targets are (du/dt) / acc_scale
+    drho_scale: float = 1.0       # kg/m^3/s: density targets are (drho/dt) / drho_scale
+    rho_band: float = 0.02        # |rho/rho0 - 1| allowed after an advance (training range)
+    judge_every: int = 8          # advances between two judge checks
+    judge_tol: float = 0.01       # max |rho_sur - rho_sph| / rho_sph before fallback
+    meta: dict = field(default_factory=dict)
+
+    def scales(self, params: dict) -> tuple:
+        """(inv_len, inv_vel, rho_ref, inv_rho) of the input rows."""
+        rho0 = float(params["rho0"])
+        return (1.0 / float(params["h"]), 1.0 / self.vel_scale, rho0, 1.0 / (rho0 * self.rho_feat))
+
+
+def save(path: str, net: sph.Mlp, cfg: NnConfig):
+    arrays = net.arrays()
+    arrays["config"] = np.frombuffer(json.dumps(asdict(cfg)).encode(), dtype=np.uint8)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **arrays)
+    os.replace(tmp, path)
+
+
+def load(path: str, ctx: sph.Context, train: bool = False, capacity: int = 32768):
+    with np.load(path, allow_pickle=False) as f:
+        arrays = {k: f[k] for k in f.files}
+    cfg = NnConfig(**json.loads(bytes(arrays.pop("config")).decode()))
+    net = sph.Mlp(cfg.width, capacity, train=train)
+    net.load(arrays)
+    ctx.mlp_sync(net)
+    return net, cfg
+
+
+def _plain_steps(ctx, cur, pair, n, step, count):
+    """count plain steps from cur, alternating between the two states of
+    ``pair`` (cur itself is never written); returns (final state, step index
+    after, dts)."""
+    dts = []
+    a = cur
+    for q in range(count):
+        b = pair[q % 2]
+        ctx.step(a, b, n, step + q)
+        dts.append(ctx.dt())
+        a = b
+    return a, step + count, dts
+
+
+def _others(bufs, *used):
+    return [x for x in bufs if all(x is not u for u in used)]
+
+
+# ------------------------------------------------------------------ training
+
+def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
+          rows: int = 32768, lr: float = 1e-3, lr_final: float = 1e-4, seed: int = 0,
+          width: int = 128, case_fn=cases.obstacle_tank, log=print,
+          time_budget_s: float | None = None):
+    """Online training: for each of n_traj seeded layouts, run plain SPH for
+    steps_per_traj steps; every window_every steps, take the sorted state A,
+    build the input rows of `rows` randomly drawn particles, run 4 more plain
+    steps to B, and take one Adam step on the targets (B - A) / (4 dt).
+    Returns (net, cfg, history)."""
+    import torch
+    cfg = NnConfig(width=width)
+    net = None
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    hist = {"loss": [], "traj": [], "window": [], "seconds": []}
+    t0 = time.time()
+    total_windows = n_traj * (steps_per_traj // window_every)
+    wi = 0
+    rho_dev_max = 0.0
+    for tr in range(n_traj):
+        case = case_fn(seed * 100003 + tr)
+        n, p = case.n, case.params
+        ctx = sph.Context(p, n)
+        if net is None:
+            net = sph.Mlp(width, rows, train=True)
+            net.init(seed)
+            ctx.mlp_sync(net)
+            X = torch.empty(rows, sph.NN_IN, dtype=torch.bfloat16, device="cuda")
+            T = torch.empty(rows, sph.NN_OUT, dtype=torch.float32, device="cuda")
+            Y = torch.empty(rows, sph.NN_OUT, dtype=torch.float32, device="cuda")
+            where = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        if where.numel() < n:
+            where = torch.empty(n, dtype=torch.int32, device="cuda")
+        scales = cfg.scales(p)
+        cur = sph.DeviceState.from_numpy(case.state)
+        bufs = [sph.DeviceState.empty(n) for _ in range(4)]
+        step = 0
+        while step + window_every <= steps_per_traj:
+            # free-running part of the trajectory between windows
+            for _ in range(window_every - K_STEPS):
+                nxt = _others(bufs, cur)[0]
+                ctx.step(cur, nxt, n, step)
+                cur, step = nxt, step + 1
+            # window: sorted copy A, input rows, 4 plain steps to B
+            A = _others(bufs, cur)[0]
+            ctx.sort(cur, A, n)
+            n0 = ctx.counts()["n_label"][0]
+            r = torch.randint(0, n0, (rows,), generator=gen, device="cuda", dtype=torch.int32)
+            ctx.nn_features(A, r, rows, scales, X)
+            B, step, dts = _plain_steps(ctx, A, _others(bufs, A)[:2], n, step, K_STEPS)
+            span = float(sum(dts))
+            ctx.nn_index(B.t["id"], n, where)
+            if cfg.meta.get("scaled") is None:
+                # unit scales on the first window: set them from the data
+                ctx.nn_targets(A, B, where, r, rows, 1.0 / span, 1.0 / span, T)
+                t_host = T.cpu().numpy().astype(np.float64)
+                cfg.acc_scale = float(max(np.sqrt(np.mean(t_host[:, :3] ** 2)), 1e-3))
+                cfg.drho_scale = float(max(np.sqrt(np.mean(t_host[:, 3] ** 2)), 1e-3))
+                cfg.meta["scaled"] = True
+            ctx.nn_targets(A, B, where, r, rows, 1.0 / (span * cfg.acc_scale),
+                           1.0 / (span * cfg.drho_scale), T)
+            frac = wi / max(total_windows - 1, 1)
+            lr_t = lr * (lr_final / lr) ** frac
+            ctx.mlp_forward(net, X, rows, Y)
+            ctx.mlp_backward(net, X, rows, T, (1.0, 1.0, 1.0, 1.0))
+            ctx.mlp_adam(net, lr_t)
+            if wi % 50 == 0:
+                loss = float(net.loss.item())
+                hist["loss"].append(loss)
+                hist["traj"].append(tr)
+                hist["window"].append(wi)
+                hist["seconds"].append(time.time() - t0)
+                rho = B.t["rho"][:n0].float()
+                rho_dev_max = max(rho_dev_max, float((rho / p["rho0"] - 1.0).abs().max()))
+                log(f"[train] traj {tr} window {wi}/{total_windows} step {step} loss {loss:.4e} "
+                    f"lr {lr_t:.2e} {time.time() - t0:.0f}s")
+            wi += 1
+            cur = B
+            if time_budget_s is not None and time.time() - t0 > time_budget_s:
+                break
+        st = ctx.status()
+        if st & (sph.STATUS_NONFINITE | sph.STATUS_NN_LIST):
+            log(f"[train] trajectory {tr}: status {st:#x}")
+        del ctx
+        if time_budget_s is not None and time.time() - t0 > time_budget_s:
+            log(f"[train] time budget reached after trajectory {tr}")
+            break
+    cfg.rho_band = float(max(0.02, 1.5 * rho_dev_max))
+    cfg.meta.update({"trajectories": tr + 1, "windows": wi, "rows": rows,
+                     "steps_per_traj": steps_per_traj, "window_every": window_every,
+                     "train_seconds": time.time() - t0, "seed": seed,
+                     "final_loss": hist["loss"][-1] if hist["loss"] else None})
+    return net, cfg, hist
+
+
+# ------------------------------------------------------------------ running
+
+def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig | None = None,
+        ctx: sph.Context | None = None, judge: bool = True, log=None) -> dict:
+    """Advance ``case`` by ``steps`` time steps. With ``net`` (and its cfg),
+    k = 4 steps per surrogate advance; every cfg.judge_every-th advance the
+    same 4 steps also run as plain SPH from the same state and
+    sph_nn_judge compares the two; an error above cfg.judge_tol, a
+    non-finite value or a density outside cfg.rho_band switches to plain SPH
+    for the rest of the run (the judged plain result is kept). Without a net:
+    plain SPH. Returns the final device state, wall time and books."""
+    import torch
+    n, p = case.n, case.params
+    ctx = ctx or sph.Context(p, n)
+    cur = sph.DeviceState.from_numpy(case.state)
+    bufs = [sph.DeviceState.empty(n) for _ in range(4)]
+    torch.cuda.synchronize()
+    books = {"advances": 0, "plain_steps": 0, "judged": 0, "fallback_at": None, "judge": []}
+    t0 = time.perf_counter()
+    step = 0
+    if net is None:
+        a = cur
+        for q in range(steps):
+            b = bufs[q % 2]
+            ctx.step(a, b, n, q)
+            a = b
+        torch.cuda.synchronize()
+        books["plain_steps"] = steps
+        return {"state": a, "seconds": time.perf_counter() - t0, "books": books, "ctx": ctx}
+    scales = cfg.scales(p)
+    where_r = torch.empty(n, dtype=torch.int32, device="cuda")
+    where_b = torch.empty(n, dtype=torch.int32, device="cuda")
+    fallback = False
+    dt = None
+
+    def others(*used):
+        return _others(bufs, *used)
+
+    while step < steps:
+        if fallback or dt is None or steps - step < K_STEPS:
+            nxt = others(cur)[0]
+            ctx.step(cur, nxt, n, step)
+            dt = ctx.dt()
+            cur, step = nxt, step + 1
+            books["plain_steps"] += 1
+            continue
+        S = others(cur)[0]
+        span = K_STEPS * dt
+        ctx.nn_advance(net, cur, S, n, scales, span * cfg.acc_scale, span * cfg.drho_scale, span,
+                       cfg.rho_band)
+        bad = ctx.status() & (sph.STATUS_NN_RANGE | sph.STATUS_NONFINITE)
+        do_judge = judge and (books["advances"] % cfg.judge_every == 0)
+        if do_judge or bad:
+            R, _, dts = _plain_steps(ctx, cur, others(cur, S)[:2], n, step, K_STEPS)
+            books["plain_steps"] += K_STEPS
+            dt = dts[-1]
+            if not bad:
+                ctx.nn_index(R.t["id"], n, where_r)
+                ctx.nn_index(cur.t["id"], n, where_b)
+                m = ctx.nn_judge(S, R, cur, where_r, where_b, n)
+                books["judged"] += 1
+                books["judge"].append({"step": step, "max_rel_rho": m[0],
+                                       "rel_drho": float(np.sqrt(m[1] / max(m[2], 1e-300))),
+                                       "rel_du": float(np.sqrt(m[3] / max(m[4], 1e-300))),
+                                       "rel_dx": float(np.sqrt(m[5] / max(m[6], 1e-300)))})
+                bad = m[0] > cfg.judge_tol
+            if bad:
+                fallback = True
+                books["fallback_at"] = step
+                if log:
+                    log(f"[surrogate] fallback to plain SPH at step {step}")
+                cur, step = R, step + K_STEPS
+                continue
+        cur, step = S, step + K_STEPS
+        books["advances"] += 1
+    torch.cuda.synchronize()
+    return {"state": cur, "seconds": time.perf_counter() - t0, "books": books, "ctx": ctx}
+
+
+def compare_by_id(ctx: sph.Context, s: sph.DeviceState, r: sph.DeviceState, b: sph.DeviceState,
+                  n: int) -> dict:
+    """Judge metrics of state s against r, both reached from b (any orders)."""
+    import torch
+    wr = torch.empty(n, dtype=torch.int32, device="cuda")
+    wb = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.nn_index(r.t["id"], n, wr)
+    ctx.nn_index(b.t["id"], n, wb)
+    m = ctx.nn_judge(s, r, b, wr, wb, n)
+    return {"max_rel_rho": float(m[0]),
+            "rel_drho": float(np.sqrt(m[1] / max(m[2], 1e-300))),
+            "rel_du": float(np.sqrt(m[3] / max(m[4], 1e-300))),
+            "rel_dx": float(np.sqrt(m[5] / max(m[6], 1e-300))),
+            "fluid": int(m[7])}
+
+
+def default_weights() -> str:
+    return os.path.join(WEIGHTS_DIR, "surrogate_w128.npz")
+
+
+def report(steps: int = 1000, weights: str | None = None, judge_every: int | None = None,
+           obstacle_seed: int = 9, log=print) -> dict:
+    """Surrogate against plain FP32 SPH on the 1.47M-particle obstacle dam
+    break with a layout that training never saw: steps/s of both loops, and
+    the surrogate state after ``steps`` steps against the plain state by id;
+    the same for persistence (a network that predicts no change), which shows
+    what the trained network adds."""
+    import torch
+    case = cases.case_c2(obstacle_seed=obstacle_seed)
+    n = case.n
+    ctx = sph.Context(case.params, n)
+    net, cfg = load(weights or default_weights(), ctx)
+    if judge_every:
+        cfg.judge_every = judge_every
+    # warm-up of both loops (first launches, allocator)
+    run(case, 8, None, ctx=ctx)
+    run(case, 8, net, cfg, ctx=ctx)
+    plain = run(case, steps, None, ctx=ctx)
+    sur = run(case, steps, net, cfg, ctx=ctx, log=log)
+    zero = sph.Mlp(cfg.width, 64, train=False)
+    ctx.mlp_sync(zero)
+    pers = run(case, steps, zero, cfg, ctx=ctx)
+    base = sph.DeviceState.from_numpy(case.state)
+    out = {"workload": case.name + f"_obstacle_seed{obstacle_seed}", "n": n, "steps": steps,
+           "plain_steps_per_s": steps / plain["seconds"],
+           "surrogate_steps_per_s": steps / sur["seconds"],
+           "speedup": plain["seconds"] / sur["seconds"],
+           "surrogate_books": {k: v for k, v in sur["books"].items() if k != "judge"},
+           "judge": sur["books"]["judge"],
+           "final_vs_plain": compare_by_id(ctx, sur["state"], plain["state"], base, n),
+           "persistence_final_vs_plain": compare_by_id(ctx, pers["state"], plain["state"], base, n),
+           "persistence_books": {k: v for k, v in pers["books"].items() if k != "judge"},
+           "persistence_judge": pers["books"]["judge"],
+           "config": asdict(cfg)}
+    torch.cuda.synchronize()
+    return out
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="Train or evaluate the learned surrogate on the GPU")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--trajectories", type=int, default=200)
+    t.add_argument("--steps", type=int, default=2000)
+    t.add_argument("--window-every", type=int, default=16)
+    t.add_argument("--rows", type=int, default=32768)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--time-budget", type=float, default=None)
+    t.add_argument("--out", default=default_weights())
+    r = sub.add_parser("report")
+    r.add_argument("--steps", type=int, default=1000)
+    r.add_argument("--weights", default=None)
+    r.add_argument("--judge-every", type=int, default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "train":
+        net, cfg, hist = train(a.trajectories, a.steps, a.window_every, a.rows, a.lr, seed=a.seed,
+                               time_budget_s=a.time_budget,
+                               log=lambda *m: print(*m, flush=True))
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        save(a.out, net, cfg)
+        print(json.dumps({"weights": a.out, "config": asdict(cfg), "loss": hist["loss"]},
+                         default=float), flush=True)
+    else:
+        print(json.dumps(report(a.steps, a.weights, a.judge_every,
+                                log=lambda *m: print(*m, flush=True)), default=float), flush=True)
+
+
+if __name__ == "__main__":
+    main()
