@@ -152,6 +152,28 @@ def precision_report(args) -> dict:
                m * 9.81 * st["z"][ng].sum(), m * e[ng].sum(), ng.sum()]
         return [float(v) for v in tot]
 
+    def compare(step):
+        """Per-quantity differences of the cell and plain FP32 runs against
+        the FP64 run, by particle id, at the current step."""
+        ref = _by_id(da.to_numpy(n), da.t["id"][:n].cpu().numpy())
+        x, y, z = ctx.cstate_positions(ca, n)
+        cst = ca.to_numpy(n)
+        cst.update({"x": x.cpu().numpy(), "y": y.cpu().numpy(), "z": z.cpu().numpy()})
+        cel = _by_id(cst, cst["id"])
+        pla = _by_id(pa.to_numpy(n), pa.t["id"][:n].cpu().numpy())
+        fl = ref["type"] == cases.FLUID
+        errs = {"step": step}
+        for name, st in (("cell", cel), ("plain", pla)):
+            e = {}
+            for k in ("x", "y", "z", "vx", "vy", "vz", "rho"):
+                d = st[k][fl].astype(np.float64) - ref[k][fl]
+                e[k] = {"rms": float(np.sqrt(np.mean(d * d))), "max": float(np.abs(d).max())}
+            disp = np.sqrt(sum((ref[k][fl] - case.pos64[ref["id"][fl], i]) ** 2
+                               for i, k in enumerate("xyz")))
+            e["rms_displacement_fp64"] = float(np.sqrt(np.mean(disp ** 2)))
+            errs[name] = e
+        return errs
+
     ev = max(1, args.report_steps // 10)
     tc = td = tp = 0.0
     for s in range(args.report_steps + 1):
@@ -161,6 +183,9 @@ def precision_report(args) -> dict:
                 rec["fp64"] = ctx.dtotals(da, n).tolist()
             out["series"].append(rec)
             print(f"[precision] step {s}: {rec}", file=sys.stderr, flush=True)
+        if s == args.fp64_steps:
+            out["vs_fp64"] = compare(s)
+            print(f"[precision] vs FP64 at step {s}: {out['vs_fp64']}", file=sys.stderr, flush=True)
         if s == args.report_steps:
             break
         torch.cuda.synchronize()
@@ -182,25 +207,6 @@ def precision_report(args) -> dict:
             td += time.perf_counter() - c
     out["ms_per_step"] = {"cell": tc / args.report_steps * 1e3, "plain": tp / args.report_steps * 1e3,
                           "fp64": td / max(args.fp64_steps, 1) * 1e3}
-    if args.fp64_steps == args.report_steps:
-        ref = _by_id(da.to_numpy(n), da.t["id"][:n].cpu().numpy())
-        x, y, z = ctx.cstate_positions(ca, n)
-        cst = ca.to_numpy(n)
-        cst.update({"x": x.cpu().numpy(), "y": y.cpu().numpy(), "z": z.cpu().numpy()})
-        cel = _by_id(cst, cst["id"])
-        pla = _by_id(pa.to_numpy(n), pa.t["id"][:n].cpu().numpy())
-        fl = ref["type"] == cases.FLUID
-        errs = {}
-        for name, st in (("cell", cel), ("plain", pla)):
-            e = {}
-            for k in ("x", "y", "z", "vx", "vy", "vz", "rho"):
-                d = st[k][fl].astype(np.float64) - ref[k][fl]
-                e[k] = {"rms": float(np.sqrt(np.mean(d * d))), "max": float(np.abs(d).max())}
-            disp = np.sqrt(sum((ref[k][fl] - case.pos64[ref["id"][fl], i]) ** 2
-                               for i, k in enumerate("xyz")))
-            e["rms_displacement_fp64"] = float(np.sqrt(np.mean(disp ** 2)))
-            errs[name] = e
-        out["vs_fp64"] = errs
     return out
 
 

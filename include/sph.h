@@ -197,6 +197,8 @@ int sph_get_counts(sph_ctx *ctx, sph_counts *out, void *stream);
 int sph_get_dt(sph_ctx *ctx, float *dt, void *stream);
 int sph_get_pairs(sph_ctx *ctx, uint64_t *pairs, void *stream);
 int sph_get_status(sph_ctx *ctx, uint32_t *flags, void *stream);
+/* Clear the status bits (a kernel on the stream; no host synchronisation). */
+int sph_clear_status(sph_ctx *ctx, void *stream);
 /* Neighbour pairs summed over every interaction since sph_create. */
 int sph_get_pair_total(sph_ctx *ctx, uint64_t *pairs, void *stream);
 /* Candidates (particles of the 27 cells) given the support test, summed over

@@ -219,7 +219,11 @@ def obstacle_tank(seed: int, *, dp: float = 0.004, nx: int = 200, ny: int = 84, 
     cs = 2.0 * params["h"]
     rng = _rng(1000 + seed)
     placed, bnd = [], [tank_walls(nx, ny, nz)]
+    tries = 0
     while len(placed) < n_obstacles:
+        tries += 1
+        if tries > 10000:
+            raise ValueError("obstacle_tank: the obstacles do not fit into the tank")
         i0 = int(rng.integers(nfx + 10, nx - side - 5))
         j0 = int(rng.integers(3, ny - side - 3))
         box = (i0 - 2, i0 + side + 2, j0 - 2, j0 + side + 2)

@@ -438,6 +438,14 @@ int sph_get_status(sph_ctx *c, uint32_t *flags, void *stream) {
     return SPH_OK;
 }
 
+int sph_clear_status(sph_ctx *c, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    hipError_t e = launch_clear_flags(c, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "clear status");
+    return SPH_OK;
+}
+
 int sph_copy_keys(sph_ctx *c, uint32_t *keys_out, uint32_t n, void *stream) {
     int r = enter(c);
     if (r) return r;

@@ -15,6 +15,11 @@ namespace sph {
 #ifndef SPH_COL_SLACK
 #define SPH_COL_SLACK 24
 #endif
+#ifndef SPH_FLUSH_UNROLL
+#define SPH_FLUSH_UNROLL 2
+#endif
+#define SPH_PRAGMA(x) _Pragma(#x)
+#define SPH_UNROLL(n) SPH_PRAGMA(unroll n)
 constexpr int kCap = SPH_INTERACT_CAP;   // neighbour entries buffered per lane before a flush
 // At each run boundary the whole wave flushes together if any lane has more
 // than kCap - kColSlack entries (a converged flush); inside a run a lane
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
             const float kvis = -kp.alpha * kp.h * kp.c0;  // Pi_ij = kvis (s_i^3 + s_j^3) vr R
 
             auto flush = [&](int cnt) {
-#pragma unroll 2
+                SPH_UNROLL(SPH_FLUSH_UNROLL)
                 for (int k = 0; k < cnt; k++) {
                     const uint32_t e = s_list[k][tid];
                     const uint32_t j = s_base[e >> kRunBits][tid] + (e & kRunMax);

@@ -441,4 +441,13 @@ hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void k_clear_flags(DevInfo *__restrict__ info) {
+    if (threadIdx.x == 0) info->flags = 0u;
+}
+
+hipError_t launch_clear_flags(sph_ctx *c, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, c->info);
+    return hipGetLastError();
+}
+
 }  // namespace sph

@@ -104,6 +104,7 @@ hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s);
 hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
                          hipStream_t s);
 hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s);
+hipError_t launch_clear_flags(sph_ctx *c, hipStream_t s);
 
 // interact.hip
 hipError_t launch_interact(sph_ctx *c, const uint8_t *type, uint32_t n, const sph_rates &out,

@@ -126,6 +126,7 @@ def lib() -> C.CDLL:
         L.sph_get_dt.argtypes = [vp, P(C.c_float), vp]
         L.sph_get_pairs.argtypes = [vp, P(C.c_uint64), vp]
         L.sph_get_status.argtypes = [vp, P(C.c_uint32), vp]
+        L.sph_clear_status.argtypes = [vp, vp]
         L.sph_get_pair_total.argtypes = [vp, P(C.c_uint64), vp]
         L.sph_get_candidate_total.argtypes = [vp, P(C.c_uint64), vp]
         L.sph_timing_begin.argtypes = [vp, u32]
@@ -446,6 +447,9 @@ class Context:
         v = C.c_uint32()
         self._check(self.L.sph_get_status(self.h, C.byref(v), _stream_ptr(stream)))
         return int(v.value)
+
+    def clear_status(self, stream=None):
+        self._check(self.L.sph_clear_status(self.h, _stream_ptr(stream)))
 
     def sorted_keys(self, n: int, stream=None):
         import torch

@@ -195,6 +195,7 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
     ctx = ctx or sph.Context(p, n)
     cur = sph.DeviceState.from_numpy(case.state)
     bufs = [sph.DeviceState.empty(n) for _ in range(4)]
+    ctx.clear_status()
     torch.cuda.synchronize()
     books = {"advances": 0, "plain_steps": 0, "judged": 0, "fallback_at": None, "judge": []}
     t0 = time.perf_counter()

@@ -1,0 +1,49 @@
+"""What the trained network gains over the method without it.
+
+A short online training on small seeded obstacle tanks (the project's own
+GPU kernels: plain SPH trajectories, neighbour rows, bfloat16 MFMA forward and
+backward passes, Adam), then judged advances on a layout that training never
+saw, against persistence: the same advance loop with a network that predicts
+no change (the surrogate without its learned part). The trained network must
+cut the error of the four-step velocity and density changes well below
+persistence's and keep the density within the judge's 1 % bound.
+"""
+import numpy as np
+import pytest
+
+from paper_1210_1017_amd import cases, sph, surrogate
+from parity_util import announce
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _tiny(seed):
+    return cases.obstacle_tank(seed, nx=72, ny=30, nz=100, nfx=20, nfz=75, side=8)
+
+
+def test_training_beats_persistence():
+    announce("surrogate short training on tiny obstacle tanks")
+    net, cfg, hist = surrogate.train(n_traj=4, steps_per_traj=480, window_every=8, rows=8192,
+                                     lr=2e-3, lr_final=5e-4, seed=1, case_fn=_tiny,
+                                     log=lambda *m: print(*m, flush=True))
+    print("loss", hist["loss"], flush=True)
+    assert hist["loss"][-1] < 0.5 * hist["loss"][0]
+    hold = _tiny(4242)
+    cfg.judge_every = 1
+    cfg.judge_tol = 1.0  # measure, do not fall back
+    zero = sph.Mlp(cfg.width, 64, train=False)
+    res = {}
+    for name, nt in (("trained", net), ("persistence", zero)):
+        ctx = sph.Context(hold.params, hold.n)
+        ctx.mlp_sync(nt)
+        r = surrogate.run(hold, 160, nt, cfg, ctx=ctx)
+        j = r["books"]["judge"]
+        assert r["books"]["fallback_at"] is None, name
+        res[name] = {k: float(np.mean([e[k] for e in j])) for k in ("rel_du", "rel_drho")}
+        res[name]["max_rel_rho"] = float(max(e["max_rel_rho"] for e in j))
+    print(res, flush=True)
+    assert abs(res["persistence"]["rel_du"] - 1.0) < 1e-6
+    assert res["trained"]["rel_du"] < 0.7 * res["persistence"]["rel_du"]
+    assert res["trained"]["rel_drho"] < res["persistence"]["rel_drho"]
+    assert res["trained"]["max_rel_rho"] <= 0.01
