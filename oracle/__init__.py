@@ -83,8 +83,9 @@ def lib():
         L.orc_internal_energy.argtypes = [pp, C.c_double]
         L.orc_internal_energy.restype = C.c_double
         L.orc_totals.argtypes = [pp, C.c_int64, d, d, d, d, d, d, d, u8, d]
-        L.orc_nearest.argtypes = [pp, C.c_int64, d, d, d, u32, u32, u32, C.c_int64, i64,
+        L.orc_nn_rows.argtypes = [pp, d, d, d, u32, u32, u32, C.c_int64, i64, C.c_float,
                                   C.c_int32, i32, i32]
+        L.orc_nn_sums.argtypes = [pp, d, d, d, d, d, d, d, C.c_int64, i64, i32, C.c_int32, d]
         _lib = L
     return _lib
 
@@ -292,21 +293,33 @@ def neighbours_cells(p: dict, srt: dict, cap: int = 1 << 24):
     return row, cols[:m].copy()
 
 
-def nearest(p: dict, srt: dict, sel, k: int = 64):
-    """The k nearest neighbours (by FP32 squared distance, then index) of the
-    sorted particles ``sel``: (nbr [len(sel), k] int32 with -1 padding, total
-    neighbour count per particle)."""
+def nn_rows(p: dict, srt: dict, sel, r2f: float, k: int = 64):
+    """Neighbours of the sorted particles ``sel`` with FP32 squared distance
+    below the FP32 number ``r2f``, in increasing sorted index: (nbr
+    [len(sel), k] int32 with -1 padding, number found per particle)."""
     s = srt["state"]
-    n0 = int(srt["counts"][0])
     sel = np.ascontiguousarray(sel, dtype=np.int64)
     m = sel.shape[0]
     nbr = np.full((m, k), -1, dtype=np.int32)
     cnt = np.zeros(m, dtype=np.int32)
-    lib().orc_nearest(C.byref(make_params(p)), n0, _d(s["x"]), _d(s["y"]), _d(s["z"]),
+    lib().orc_nn_rows(C.byref(make_params(p)), _d(s["x"]), _d(s["y"]), _d(s["z"]),
                       _ptr(srt["keys"], C.c_uint32), _ptr(srt["begin"], C.c_uint32),
-                      _ptr(srt["end"], C.c_uint32), m, _ptr(sel, C.c_int64), k,
+                      _ptr(srt["end"], C.c_uint32), m, _ptr(sel, C.c_int64), float(r2f), k,
                       _ptr(nbr, C.c_int32), _ptr(cnt, C.c_int32))
     return nbr, cnt
+
+
+def nn_sums(p: dict, srt: dict, sel, nbr) -> np.ndarray:
+    """FP64 pressure acceleration and continuity rate of the sorted particles
+    ``sel`` over their listed neighbours ``nbr`` (-1 = none): [len(sel), 4]."""
+    s = srt["state"]
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    out = np.zeros((sel.shape[0], 4))
+    lib().orc_nn_sums(C.byref(make_params(p)), _d(s["x"]), _d(s["y"]), _d(s["z"]), _d(s["vx"]),
+                      _d(s["vy"]), _d(s["vz"]), _d(s["rho"]), sel.shape[0], _ptr(sel, C.c_int64),
+                      _ptr(nbr, C.c_int32), nbr.shape[1], _d(out))
+    return out
 
 
 def dt(p: dict, srt: dict, acc: dict) -> float:

@@ -2,8 +2,9 @@
 
 The surrogate is an addition to the paper's method: a multilayer perceptron
 that maps the neighbourhood of a particle -- gathered through the cell list of
-Sec. 3.1 and the compact-support test of Sec. 2.2 -- to the change of its
-velocity and density over four time steps. Beyond those two sections nothing
+Sec. 3.1 with the distance test of Sec. 2.2, plus the pressure and continuity
+sums of Sec. 2.2 over it -- to the change of its velocity and density over
+four time steps. Beyond those two sections nothing
 here comes from the paper; each piece follows a standard published definition:
 
 * bfloat16: the upper half of an IEEE binary32 number, rounded to nearest with
@@ -26,12 +27,11 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import nearest
 
 FLUID, BOUNDARY, GHOST = 0, 1, 2
 SLOTS = 64          # neighbours per input row
 SLOT_F = 8          # features per neighbour slot
-OWN_F = 32          # own-particle block (6 used, rest zero)
+OWN_F = 32          # own-particle block (10 used, rest zero)
 N_IN = SLOTS * SLOT_F + OWN_F   # 544
 N_OUT = 4           # (dv_x, dv_y, dv_z, drho), scaled
 BF16_MAX = (2.0 - 2.0 ** -7) * 2.0 ** 127
@@ -57,6 +57,9 @@ def bf16_round(a) -> np.ndarray:
 
 # ------------------------------------------------------------------ features
 
+SUM_COLS = slice(SLOTS * SLOT_F + 6, SLOTS * SLOT_F + 10)   # own-block columns of the pair sums
+
+
 def kind(t: np.ndarray) -> np.ndarray:
     """Particle kind as a feature: -1 for boundary particles, +1 otherwise."""
     return np.where(t == BOUNDARY, -1.0, 1.0)
@@ -65,25 +68,30 @@ def kind(t: np.ndarray) -> np.ndarray:
 def features(p: dict, srt: dict, sel, scales) -> np.ndarray:
     """Input rows of the surrogate for the sorted particles ``sel``.
 
-    ``scales`` = (inv_len, inv_vel, rho_ref, inv_rho), FP32 numbers. For the 64
-    nearest neighbours j of i (``nearest``: the FP32 support test of Sec. 2.2
-    over the 27 cells of Sec. 3.1, ordered by FP32 squared distance, then
-    index), slot s holds
+    ``scales`` = (inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho),
+    FP32 numbers. The neighbours of i are the particles of the 27 cells of
+    Sec. 3.1 whose FP32 squared distance (the expression of the support test
+    of Sec. 2.2) is below r2f, in increasing sorted index (``nn_rows``); the
+    first 64 fill the slots. Slot s holds
         (x_j - x_i) inv_len, (y_j - y_i) inv_len, (z_j - z_i) inv_len,
         (u_j - u_i) inv_vel (3 components), (rho_j - rho_ref) inv_rho, kind_j
-    each an FP32 difference and an FP32 product rounded to bfloat16; empty
+    each an FP32 difference times an FP32 scale rounded to bfloat16; empty
     slots are zero. The own block is
-        (rho_i - rho_ref) inv_rho, u_i inv_vel (3), count_i / 64, kind_i, 0 ...
-    with count_i the number of neighbours before truncation. Ghost rows are
-    zero. Returns an FP64 array of bfloat16 values, shape (len(sel), 544)."""
+        (rho_i - rho_ref) inv_rho, u_i inv_vel (3), count_i / 64, kind_i,
+        ap_i inv_acc (3), dr_i inv_drho, 0 ...
+    with count_i the number of neighbours found and (ap_i, dr_i) the pressure
+    acceleration and continuity rate of Sec. 2.2 summed over the slots
+    (``nn_sums``, FP64 here). Ghost rows are zero. Returns an FP64 array of
+    bfloat16 values, shape (len(sel), 544)."""
+    from . import nn_rows, nn_sums
     s = srt["state"]
     n0 = int(srt["counts"][0])
     sel = np.asarray(sel, dtype=np.int64)
     assert np.all((sel >= 0) & (sel < n0))
-    inv_len, inv_vel, rho_ref, inv_rho = (np.float32(v) for v in scales)
+    inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho = (np.float32(v) for v in scales)
     f = {k: s[k].astype(np.float32) for k in ("x", "y", "z", "vx", "vy", "vz", "rho")}
     typ = s["type"]
-    nbr, cnt = nearest(p, srt, sel, SLOTS)
+    nbr, cnt = nn_rows(p, srt, sel, r2f, SLOTS)
     valid = nbr >= 0
     j = np.where(valid, nbr, 0)
     i = sel[:, None]
@@ -105,6 +113,9 @@ def features(p: dict, srt: dict, sel, scales) -> np.ndarray:
     own[:, 3] = f["vz"][sel] * inv_vel
     own[:, 4] = cnt.astype(np.float32) * np.float32(1.0 / 64.0)
     own[:, 5] = kind(typ[sel])
+    sums = nn_sums(p, srt, sel, nbr)
+    own[:, 6:9] = sums[:, :3] * float(inv_acc)
+    own[:, 9] = sums[:, 3] * float(inv_drho)
     X[typ[sel] == GHOST] = 0.0
     return bf16_round(X)
 

@@ -561,78 +561,92 @@ void orc_totals(const orc_params *p, int64_t n, const double *x, const double *y
     }
 }
 
-/* ------------------------------------------- nearest neighbours (surrogate) */
-
-typedef struct {
-    float r2;
-    int32_t j;
-} r2_entry;
-
-static int r2_cmp(const void *a, const void *b)
-{
-    const r2_entry *x = (const r2_entry *)a, *y = (const r2_entry *)b;
-    if (x->r2 < y->r2) return -1;
-    if (x->r2 > y->r2) return 1;
-    return (x->j > y->j) - (x->j < y->j);
-}
+/* ------------------------------------- neighbour rows of the surrogate */
 
 /*
  * Input neighbourhood of the learned surrogate (an addition to the paper's
  * method, built on its cell list of Sec. 3.1): for each selected particle
- * i = sel[s] of the label-0 prefix, every j != i in the 27 cells around i
- * that passes the FP32 support test of Sec. 2.2, ordered by (FP32 squared
- * distance, j); the first k go to nbr[s*k ...] (-1 where fewer), the full
- * count to count[s]. The squared distance is the same FP32 expression as the
- * support test, so that order and membership are decided in one precision.
+ * i = sel[s] of the label-0 prefix, the particles j != i of the 27 cells
+ * around i's cell with FP32 squared distance
+ * fmaf(dz,dz,fmaf(dy,dy,dx*dx)) < r2f (the support test of Sec. 2.2 with a
+ * smaller radius), in increasing sorted index (the order in which the cells
+ * and the particles within a cell follow each other); the first k go to
+ * nbr[s*k ...] (-1 where fewer), the number found to count[s].
  */
-void orc_nearest(const orc_params *p, int64_t n0, const double *x, const double *y,
-                 const double *z, const uint32_t *skey, const uint32_t *begin,
-                 const uint32_t *end, int64_t nsel, const int64_t *sel, int32_t k,
-                 int32_t *nbr, int32_t *count)
+void orc_nn_rows(const orc_params *p, const double *x, const double *y, const double *z,
+                 const uint32_t *skey, const uint32_t *begin, const uint32_t *end,
+                 int64_t nsel, const int64_t *sel, float r2f, int32_t k, int32_t *nbr,
+                 int32_t *count)
 {
     const int bc = orc_cell_bits(p);
     const uint32_t cmask = (bc >= 32) ? 0xffffffffu : ((1u << bc) - 1u);
     const int ncx = p->ncell[0], ncy = p->ncell[1], ncz = p->ncell[2];
-    const float r2max = support_r2(p);
-    (void)n0;
-#pragma omp parallel
-    {
-        int64_t cap = 256;
-        r2_entry *buf = (r2_entry *)malloc((size_t)cap * sizeof(r2_entry));
-#pragma omp for schedule(dynamic, 64)
-        for (int64_t s = 0; s < nsel; s++) {
-            const int64_t i = sel[s];
-            const uint32_t cell = skey[i] & cmask;
-            const int cz = (int)(cell % (uint32_t)ncz);
-            const int cy = (int)((cell / (uint32_t)ncz) % (uint32_t)ncy);
-            const int cx = (int)(cell / ((uint32_t)ncz * (uint32_t)ncy));
-            const float xi = (float)x[i], yi = (float)y[i], zi = (float)z[i];
-            int64_t m = 0;
-            for (int ox = -1; ox <= 1; ox++)
-            for (int oy = -1; oy <= 1; oy++)
-            for (int oz = -1; oz <= 1; oz++) {
-                const int X = cx + ox, Y = cy + oy, Z = cz + oz;
-                if (X < 0 || X >= ncx || Y < 0 || Y >= ncy || Z < 0 || Z >= ncz) continue;
-                const int64_t c = ((int64_t)X * ncy + Y) * ncz + Z;
-                for (int64_t j = begin[c]; j < (int64_t)end[c]; j++) {
-                    if (j == i) continue;
-                    const float dx = xi - (float)x[j], dy = yi - (float)y[j],
-                                dz = zi - (float)z[j];
-                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    if (!(r2 < r2max)) continue;
-                    if (m == cap) {
-                        cap *= 2;
-                        buf = (r2_entry *)realloc(buf, (size_t)cap * sizeof(r2_entry));
-                    }
-                    buf[m].r2 = r2;
-                    buf[m].j = (int32_t)j;
-                    m++;
-                }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t s = 0; s < nsel; s++) {
+        const int64_t i = sel[s];
+        const uint32_t cell = skey[i] & cmask;
+        const int cz = (int)(cell % (uint32_t)ncz);
+        const int cy = (int)((cell / (uint32_t)ncz) % (uint32_t)ncy);
+        const int cx = (int)(cell / ((uint32_t)ncz * (uint32_t)ncy));
+        int32_t m = 0;
+        for (int q = 0; q < k; q++) nbr[s * k + q] = -1;
+        for (int ox = -1; ox <= 1; ox++)
+        for (int oy = -1; oy <= 1; oy++)
+        for (int oz = -1; oz <= 1; oz++) {
+            const int X = cx + ox, Y = cy + oy, Z = cz + oz;
+            if (X < 0 || X >= ncx || Y < 0 || Y >= ncy || Z < 0 || Z >= ncz) continue;
+            const int64_t c = ((int64_t)X * ncy + Y) * ncz + Z;
+            for (int64_t j = begin[c]; j < (int64_t)end[c]; j++) {
+                if (j == i) continue;
+                if (!within_support((float)x[i], (float)y[i], (float)z[i], (float)x[j],
+                                    (float)y[j], (float)z[j], r2f))
+                    continue;
+                if (m < k) nbr[s * k + m] = (int32_t)j;
+                m++;
             }
-            qsort(buf, (size_t)m, sizeof(r2_entry), r2_cmp);
-            for (int32_t q = 0; q < k; q++) nbr[s * k + q] = (q < m) ? buf[q].j : -1;
-            count[s] = (int32_t)m;
         }
-        free(buf);
+        count[s] = m;
+    }
+}
+
+/*
+ * Pair sums of a surrogate input row over its listed neighbours nbr[s*k ..]
+ * (-1 = none), in FP64 with the kernel gradient and equation of state of
+ * Sec. 2.2: the pressure part of the momentum equation
+ *   ap_i = - sum_j m (p_i/rho_i^2 + p_j/rho_j^2) grad_i W_ij
+ * and the continuity rate
+ *   dr_i = sum_j m (v_i - v_j) . grad_i W_ij,
+ * grad_i W_ij = F(r_ij) (r_i - r_j). out[4 s ..] = (ap_x, ap_y, ap_z, dr).
+ */
+void orc_nn_sums(const orc_params *p, const double *x, const double *y, const double *z,
+                 const double *vx, const double *vy, const double *vz, const double *rho,
+                 int64_t nsel, const int64_t *sel, const int32_t *nbr, int32_t k, double *out)
+{
+    const double m = p->mass, h = p->h;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t s = 0; s < nsel; s++) {
+        const int64_t i = sel[s];
+        double pi, ci;
+        orc_eos(p, rho[i], &pi, &ci);
+        const double Pi = pi / (rho[i] * rho[i]);
+        double ax = 0.0, ay = 0.0, az = 0.0, dr = 0.0;
+        for (int q = 0; q < k; q++) {
+            const int32_t j = nbr[s * k + q];
+            if (j < 0) continue;
+            double pj, cj;
+            orc_eos(p, rho[j], &pj, &cj);
+            const double Pj = pj / (rho[j] * rho[j]);
+            const double rx = x[i] - x[j], ry = y[i] - y[j], rz = z[i] - z[j];
+            const double F = orc_kernel_f(sqrt(rx * rx + ry * ry + rz * rz), h);
+            const double f = m * (Pi + Pj) * F;
+            ax -= f * rx;
+            ay -= f * ry;
+            az -= f * rz;
+            dr += m * F * ((vx[i] - vx[j]) * rx + (vy[i] - vy[j]) * ry + (vz[i] - vz[j]) * rz);
+        }
+        out[4 * s + 0] = ax;
+        out[4 * s + 1] = ay;
+        out[4 * s + 2] = az;
+        out[4 * s + 3] = dr;
     }
 }

@@ -48,49 +48,57 @@ def test_bf16_round_ties_and_limits(mlp, value, rounded):
     assert mlp.bf16_round(np.array([value]))[0] == rounded
 
 
-# --------------------------------------------------- nearest neighbours
+# ------------------------------------------------------ neighbour rows
+
+R_F = 1.85  # feature radius in units of h
+
+
+def _r2f(p):
+    return np.float32((R_F * p["h"]) ** 2)
+
+
+def _scales(p):
+    return (np.float32(1.0 / p["h"]), 2.0, 1000.0, 0.1, _r2f(p), 0.1, 1e-3)
+
 
 def _sorted_case(orc, case):
     return orc.sort_state(case.params, case.state)
 
 
-def test_nearest_matches_brute_force_on_random_cloud(orc):
-    # about 100 neighbours per interior particle, so truncation at 64 matters
+def test_nn_rows_match_brute_force_on_random_cloud(orc):
+    # about 80 particles within 1.85h of an interior particle: the 64-slot cut matters
     case = cases.random_cloud(1800, 0.02, (0.22, 0.22, 0.22), seed=5)
     srt = _sorted_case(orc, case)
     s = srt["state"]
     n = case.n
-    row, cols = orc.neighbours_brute(case.params, s)
+    r2f = _r2f(case.params)
     sel = np.arange(0, n, 7)
-    nbr, cnt = orc.nearest(case.params, srt, sel, 64)
-    assert cnt.max() > 80
+    nbr, cnt = orc.nn_rows(case.params, srt, sel, r2f, 64)
+    assert cnt.max() > 64
+    x = np.stack([s["x"], s["y"], s["z"]], 1)
     for q, i in enumerate(sel):
-        js = cols[row[i]:row[i + 1]]
-        assert cnt[q] == js.size
-        r2 = (s["x"][js] - s["x"][i]) ** 2 + (s["y"][js] - s["y"][i]) ** 2 + \
-             (s["z"][js] - s["z"][i]) ** 2
-        order = js[np.lexsort((js, r2))][:64]
+        r2 = np.sum((x - x[i]) ** 2, axis=1)
+        js = np.nonzero(r2 < float(r2f))[0]
+        js = js[js != i]
+        assert cnt[q] == js.size, i
         got = nbr[q][nbr[q] >= 0]
-        assert np.array_equal(got, order), i
+        assert np.array_equal(got, js[:64]), i
 
 
 def _lattice_case(side=12, dp=0.25):
     p = cases.base_params(dp)
     I, J, K = np.meshgrid(np.arange(side), np.arange(side), np.arange(side), indexing="ij")
     pos = np.stack([I.ravel(), J.ravel(), K.ravel()], 1).astype(np.float64) * dp + dp
-    cs = 2.0 * p["h"]
     cases.set_grid(p, (0.0, 0.0, 0.0), (side * dp + 2 * dp, side * dp + 2 * dp, side * dp + 2 * dp))
     st = cases._make_state(pos, np.full(pos.shape[0], cases.FLUID), np.full(pos.shape[0], 1000.0))
-    assert cs > 0
     return cases.Case("lattice", p, st, pos)
 
 
-def test_nearest_lattice_shells(orc):
-    """Perfect cubic lattice, h = 1.3 dp: an interior particle sees the shells
-    |r|^2/dp^2 = 1..6 (6, 12, 8, 6, 24, 24 points; 80 in all, 2.6^2 = 6.76);
-    the 64 nearest are the first five shells (56) and the 8 lowest indices of
-    the sixth, each shell in index order (the squared distances tie exactly
-    with dp = 1/4)."""
+def test_nn_rows_lattice_shells(orc):
+    """Perfect cubic lattice, h = 1.3 dp: an interior particle has the shells
+    |r|^2/dp^2 = 1..5 (6, 12, 8, 6, 24 points: 56 in all) inside 1.85h
+    (2.405 dp; the sixth shell lies at 2.449 dp), listed in sorted-index
+    order (dp = 1/4 makes every distance exact)."""
     case = _lattice_case()
     srt = _sorted_case(orc, case)
     s = srt["state"]
@@ -99,27 +107,22 @@ def test_nearest_lattice_shells(orc):
                         (np.abs(s["z"] - 7 * dp) < 1e-9))[0]
     assert centre.size == 1
     i = int(centre[0])
-    nbr, cnt = orc.nearest(case.params, srt, [i], 64)
-    assert cnt[0] == 80
-    js = nbr[0]
+    nbr, cnt = orc.nn_rows(case.params, srt, [i], _r2f(case.params), 64)
+    assert cnt[0] == 56
+    js = nbr[0][:56]
+    assert np.all(nbr[0][56:] == -1)
+    assert np.all(np.diff(js) > 0)
     shell = np.rint(((s["x"][js] - s["x"][i]) ** 2 + (s["y"][js] - s["y"][i]) ** 2 +
                      (s["z"][js] - s["z"][i]) ** 2) / dp ** 2).astype(int)
-    assert np.bincount(shell, minlength=7).tolist() == [0, 6, 12, 8, 6, 24, 8]
-    assert np.all(np.diff(shell) >= 0)
-    for sh in range(1, 7):
-        assert np.all(np.diff(js[shell == sh]) > 0)
-    # the 8 taken from the sixth shell are its 8 lowest indices
-    allr = [j for j in range(case.n) if j != i and
-            round(((s["x"][j] - s["x"][i]) ** 2 + (s["y"][j] - s["y"][i]) ** 2 +
-                   (s["z"][j] - s["z"][i]) ** 2) / dp ** 2) == 6]
-    assert js[shell == 6].tolist() == sorted(allr)[:8]
+    assert np.bincount(shell, minlength=6).tolist() == [0, 6, 12, 8, 6, 24]
 
 
 # ------------------------------------------------------------ features
 
 def test_features_hand_computed(orc, mlp):
-    """Three particles: i (fluid), a fluid neighbour at +h/2 in x and a
-    boundary neighbour at -h in z, plus a ghost; one row worked out by hand."""
+    """A fluid particle i, a fluid neighbour at +h/2 in x, a boundary
+    neighbour at -h in z and a ghost at +h/4 in y; i's row worked out by
+    hand (slots in sorted-index order)."""
     p = cases.base_params(0.02)
     h = p["h"]
     pos = np.array([[0.1, 0.1, 0.1], [0.1 + 0.5 * h, 0.1, 0.1], [0.1, 0.1, 0.1 - h],
@@ -134,25 +137,73 @@ def test_features_hand_computed(orc, mlp):
     order = {int(t): k for k, t in enumerate(s["id"])}
     i = order[0]
     inv_len = np.float32(1.0 / h)
-    scales = (inv_len, 2.0, 1000.0, 0.1)
-    X = mlp.features(p, srt, [i], scales)[0]
+    sc = (inv_len, 2.0, 1000.0, 0.1, _r2f(p), 0.1, 1e-3)
+    X = mlp.features(p, srt, [i], sc)[0]
     slots = X[:512].reshape(64, 8)
     own = X[512:]
-    # slot order: the ghost at h/4, the fluid neighbour at h/2, the boundary one at h
     f32 = np.float32
     dxf = float(mlp.bf16_round(float((f32(s["x"][order[1]]) - f32(s["x"][i])) * inv_len)))
-    assert abs(dxf - 0.5) < 0.5 * 2 ** -8
-    assert slots[0, 7] == 1.0 and slots[0, 1] > 0.2  # ghost counts as +1, offset in y
-    assert slots[1].tolist() == [dxf, 0.0, 0.0, 0.5, 0.0, 0.5, 1.0, 1.0]
     dzb = float(mlp.bf16_round(float((f32(s["z"][order[2]]) - f32(s["z"][i])) * inv_len)))
-    assert abs(dzb + 1.0) < 2 ** -7
-    assert slots[2].tolist() == [0.0, 0.0, dzb, -1.0, 0.0, 0.5, -0.5, -1.0]
+    assert abs(dxf - 0.5) < 0.5 * 2 ** -8 and abs(dzb + 1.0) < 2 ** -7
+    rows = {1: [dxf, 0.0, 0.0, 0.5, 0.0, 0.5, 1.0, 1.0],
+            2: [0.0, 0.0, dzb, -1.0, 0.0, 0.5, -0.5, -1.0]}
+    nb = sorted([order[1], order[2], order[3]])     # slot order: sorted index
+    for slot, k in enumerate(nb):
+        pid = int(s["id"][k])
+        if pid in rows:
+            assert slots[slot].tolist() == rows[pid], pid
+        else:  # the ghost: kind +1, offset in y
+            assert slots[slot, 7] == 1.0 and slots[slot, 1] > 0.2
     assert not slots[3:].any()
     assert own[:6].tolist() == [0.0, 1.0, 0.0, -0.5, 3 / 64, 1.0]
-    assert not own[6:].any()
+    assert not own[10:].any()
     # the ghost's row is zero, the boundary particle's kind is -1
-    assert not mlp.features(p, srt, [order[3]], scales).any()
-    assert mlp.features(p, srt, [order[2]], scales)[0, 512 + 5] == -1.0
+    assert not mlp.features(p, srt, [order[3]], sc).any()
+    assert mlp.features(p, srt, [order[2]], sc)[0, 512 + 5] == -1.0
+
+
+def test_nn_sums_equal_interaction_for_a_static_cluster(orc):
+    """With zero velocities the artificial viscosity vanishes (v_ij . r_ij = 0),
+    so for particles whose whole support lies inside the feature radius the
+    pressure sum is the momentum equation's acceleration minus gravity, and
+    the continuity sum is zero: checked against the pinned interaction."""
+    rng = np.random.default_rng(7)
+    p = cases.base_params(0.02)
+    h = p["h"]
+    pos = 0.1 + rng.uniform(-0.4 * h, 0.4 * h, size=(6, 3))   # all pairs closer than 1.4h
+    st = cases._make_state(pos, np.full(6, cases.FLUID), 1000.0 * (1 + rng.uniform(-0.01, 0.01, 6)))
+    cases.set_grid(p, (0.0, 0.0, 0.0), (0.2, 0.2, 0.2))
+    srt = orc.sort_state(p, st)
+    sel = np.arange(6)
+    nbr, cnt = orc.nn_rows(p, srt, sel, _r2f(p), 64)
+    assert np.all(cnt == 5)
+    sums = orc.nn_sums(p, srt, sel, nbr)
+    acc = orc.interact(p, srt)
+    g = np.array(p["g"])
+    a = np.stack([acc["ax"], acc["ay"], acc["az"]], 1) - g
+    assert np.allclose(sums[:, :3], a, rtol=1e-12, atol=1e-12 * np.abs(a).max())
+    assert np.all(sums[:, 3] == 0.0)
+
+
+def test_nn_sums_continuity_equals_interaction(orc):
+    """The continuity rate carries no viscous term, so with random velocities
+    and every neighbour inside the feature radius the continuity sum equals
+    the interaction's drho/dt (pinned separately)."""
+    rng = np.random.default_rng(8)
+    p = cases.base_params(0.02)
+    h = p["h"]
+    pos = 0.1 + rng.uniform(-0.4 * h, 0.4 * h, size=(6, 3))
+    vel = rng.uniform(-0.5, 0.5, size=(6, 3))
+    st = cases._make_state(pos, np.full(6, cases.FLUID), np.full(6, 1000.0), vel)
+    cases.set_grid(p, (0.0, 0.0, 0.0), (0.2, 0.2, 0.2))
+    srt = orc.sort_state(p, st)
+    sel = np.arange(6)
+    nbr, cnt = orc.nn_rows(p, srt, sel, _r2f(p), 64)
+    assert np.all(cnt == 5)
+    sums = orc.nn_sums(p, srt, sel, nbr)
+    acc = orc.interact(p, srt)
+    assert np.allclose(sums[:, 3], acc["drho"], rtol=1e-12, atol=1e-12 * np.abs(acc["drho"]).max())
+    assert np.abs(acc["drho"]).max() > 0
 
 
 def test_targets_definition(mlp):
