@@ -174,7 +174,7 @@ def precision_report(args) -> dict:
             errs[name] = e
         return errs
 
-    ev = max(1, args.report_steps // 10)
+    ev = max(1, min(args.report_steps // 10, 250))  # a progress line at least every 250 steps
     tc = td = tp = 0.0
     for s in range(args.report_steps + 1):
         if s % ev == 0 or s == args.report_steps:

@@ -303,18 +303,22 @@ int sph_get_dt64(sph_ctx *ctx, double *dt, void *stream);
  * Learned surrogate. An addition to the paper's method: a multilayer
  * perceptron that advances fluid and boundary particles by four time steps
  * at once from their neighbourhoods. Its input row for particle i is built
- * from the cell list of Sec. 3.1 and the compact-support test of Sec. 2.2:
- * the 64 nearest neighbours j within 2h (FP32 squared distance
- * fmaf(dz,dz,fmaf(dy,dy,dx*dx)), ties by sorted index), 8 bfloat16 features
- * per neighbour slot and 32 for the particle itself (SPH_NN_IN = 544):
+ * from the cell list of Sec. 3.1 with the FP32 distance expression of the
+ * support test of Sec. 2.2: the particles j != i of the 27 cells around i
+ * with fmaf(dz,dz,fmaf(dy,dy,dx*dx)) < r2f, in increasing sorted index, the
+ * first 64 filling the slots; 8 bfloat16 features per slot and 32 for the
+ * particle itself (SPH_NN_IN = 544):
  *   slot s:  (x_j - x_i) inv_len, (y_j - y_i) inv_len, (z_j - z_i) inv_len,
  *            (u_j - u_i) inv_vel (3), (rho_j - rho_ref) inv_rho, kind_j,
  *            zeros for an empty slot;
  *   own:     (rho_i - rho_ref) inv_rho, u_i inv_vel (3), count_i / 64,
- *            kind_i, 26 zeros;
- * kind = -1 for boundary particles, +1 otherwise; count_i = neighbours in
- * support before truncation; each feature is an FP32 difference times an
- * FP32 scale rounded to bfloat16 (nearest, ties to even). Ghost rows are zero.
+ *            kind_i, ap_i inv_acc (3), dr_i inv_drho, 22 zeros;
+ * kind = -1 for boundary particles, +1 otherwise; count_i = neighbours found
+ * (before the cut at 64); ap_i = -sum_j m (p_i/rho_i^2 + p_j/rho_j^2)
+ * grad_i W_ij and dr_i = sum_j m v_ij . grad_i W_ij over the slots (the
+ * pressure part of the momentum equation and the continuity equation of
+ * Sec. 2.2, FP32). Each feature is FP32 arithmetic rounded to bfloat16
+ * (nearest, ties to even). Ghost rows are zero.
  * Network: 544 -> w -> w -> w -> 4, SiLU after each hidden layer, bfloat16
  * weights and activations with FP32 accumulation on the matrix cores, FP32
  * master weights with Adam. Outputs, scaled: (du_x, du_y, du_z, drho) over
@@ -326,10 +330,14 @@ int sph_get_dt64(sph_ctx *ctx, double *dt, void *stream);
 #define SPH_NN_LAYERS 4
 
 typedef struct sph_nn_scales {
-    float inv_len; /* 1 / length scale (1/h)            */
-    float inv_vel; /* 1 / velocity scale                */
-    float rho_ref; /* reference density (rho0)          */
-    float inv_rho; /* 1 / density scale                 */
+    float inv_len;  /* 1 / length scale (1/h)                  */
+    float inv_vel;  /* 1 / velocity scale                      */
+    float rho_ref;  /* reference density (rho0)                */
+    float inv_rho;  /* 1 / density scale                       */
+    float r2f;      /* squared radius of the neighbourhood     */
+    float inv_acc;  /* 1 / acceleration scale of ap            */
+    float inv_drho; /* 1 / density-rate scale of dr            */
+    float reserved; /* 0                                       */
 } sph_nn_scales;
 
 /* Network and training workspace; every buffer is caller-owned device
@@ -406,12 +414,23 @@ int sph_mlp_adam(sph_ctx *ctx, sph_mlp *net, float lr, float beta1, float beta2,
 int sph_nn_apply(sph_ctx *ctx, sph_soa *sorted, const float *y, uint32_t nrows, float dv_scale,
                  float dr_scale, float dt4, float rho_tol, void *stream);
 
-/* One surrogate advance: sort cur into next (as sph_sort), then one fused
- * kernel builds each particle's input row, runs the network (width 128) and
- * applies the result to next as sph_nn_apply does. */
+/* One surrogate advance: sort cur into next (as sph_sort), build every
+ * particle's input row (into a row buffer the context allocates on the first
+ * call: capacity x SPH_NN_IN bfloat16), then one kernel runs the network
+ * (width 128) on tiles of 64 rows and applies the result to next as
+ * sph_nn_apply does. */
 int sph_nn_advance(sph_ctx *ctx, const sph_mlp *net, const sph_soa *cur, sph_soa *next,
                    uint32_t n, const sph_nn_scales *scales, float dv_scale, float dr_scale,
                    float dt4, float rho_tol, void *stream);
+
+/* Training noise: adds to the velocity and density of every fluid particle
+ * k < n (and to their previous-step values, so a Verlet step sees the same
+ * shift) independent uniform noise of standard deviation sigma_u (m/s, per
+ * component) and sigma_rho (kg/m^3), drawn from a counter-based generator
+ * (murmur3's 32-bit finaliser of seed, k and the component): the same
+ * (seed, n, state) always gives the same result. */
+int sph_nn_perturb(sph_ctx *ctx, sph_soa *st, uint32_t n, uint32_t seed, float sigma_u,
+                   float sigma_rho, void *stream);
 
 /* Error of a surrogate state s against a reference state r reached from the
  * same base state b by plain SPH steps, over the fluid particles of s

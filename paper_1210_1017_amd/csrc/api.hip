@@ -62,7 +62,7 @@ void free_events(sph_ctx *c) {
 
 void free_all(sph_ctx *c) {
     free_events(c);
-    void *vptrs[] = {c->p64, c->drate, c->tot_part, c->nn_part, c->nn_out};
+    void *vptrs[] = {c->p64, c->drate, c->tot_part, c->nn_part, c->nn_out, c->nn_x};
     for (void *p : vptrs)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
@@ -720,7 +720,7 @@ int sph_nn_features(sph_ctx *c, const sph_soa *sorted, const int32_t *rows, uint
         return fail(c, SPH_E_INVALID_ARG, "nrows = %u > n = %u of the sort", nrows, c->sorted_n);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_pack(c, *sorted, c->sorted_n, s);
-    if (e == hipSuccess) e = launch_nn_features(c, sorted->type, rows, nrows, *scales, x, s);
+    if (e == hipSuccess) e = launch_nn_features(c, sorted->type, rows, nrows, *scales, x, 0, s);
     if (e != hipSuccess) return hip_fail(c, e, "features");
     return SPH_OK;
 }
@@ -853,17 +853,41 @@ int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *ne
     int r = enter(c);
     if (r) return r;
     if ((r = mlp_check(c, m, false))) return r;
-    if (m->width != 128) return fail(c, SPH_E_INVALID_ARG, "the fused advance needs width 128");
+    if (m->width != 128) return fail(c, SPH_E_INVALID_ARG, "the advance kernel needs width 128");
     if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
     if (!soa_ok(cur) || !soa_ok(next) || !scales)
         return fail(c, SPH_E_INVALID_ARG, "null argument");
     if (cur->x == next->x || cur->rho == next->rho || cur->type == next->type || cur->id == next->id)
         return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
     hipStream_t s = (hipStream_t)stream;
+    if (c->nn_x_rows < c->capacity) {
+        // input rows of every particle: allocated once per context, on first use
+        if (c->nn_x) (void)hipFree(c->nn_x);
+        c->nn_x = nullptr;
+        c->nn_x_rows = 0;
+        hipError_t e = hipMalloc(&c->nn_x, (size_t)c->capacity * SPH_NN_IN * 2);
+        if (e != hipSuccess) return hip_fail(c, e, "surrogate row buffer");
+        c->nn_x_rows = c->capacity;
+    }
     if ((r = do_sort(c, cur, next, n, s))) return r;
-    hipError_t e = launch_nn_fused(c, *m, *next, n, *scales, dv_scale, dr_scale, dt4, rho_tol, s);
+    hipError_t e = launch_nn_features(c, next->type, nullptr, n, *scales, c->nn_x, 1, s);
+    if (e == hipSuccess)
+        e = launch_nn_mlp_apply(c, *m, *next, c->nn_x, n, dv_scale, dr_scale, dt4, rho_tol, s);
     if (e != hipSuccess) return hip_fail(c, e, "surrogate advance");
     c->have_dt = false;
+    return SPH_OK;
+}
+
+int sph_nn_perturb(sph_ctx *c, sph_soa *st, uint32_t n, uint32_t seed, float sigma_u,
+                   float sigma_rho, void *stream) {
+    int r = enter(c);
+    if (r) return r;
+    if (!soa_ok(st)) return fail(c, SPH_E_INVALID_ARG, "null state array");
+    if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
+    if (!(sigma_u >= 0.0f) || !(sigma_rho >= 0.0f))
+        return fail(c, SPH_E_INVALID_ARG, "noise levels must be >= 0");
+    hipError_t e = launch_nn_perturb(*st, n, seed, sigma_u, sigma_rho, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "perturb");
     return SPH_OK;
 }
 

@@ -156,14 +156,16 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
 #pragma unroll
                     for (int u = 0; u < kUnroll; u++)  // past the run: in-bounds data or 0
                         q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
+                    // append without a branch: the entry is always written to the
+                    // free slot, which only a hit consumes
+                    const uint32_t lim = len - k0;  // candidates left in the run (>= 1)
 #pragma unroll
                     for (int u = 0; u < kUnroll; u++) {
                         const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
                         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        if (k0 + u < len && r2 < kp.r2max) {
-                            *lp = (uint16_t)(((uint32_t)col << kRunBits) + k0 + u);
-                            lp += kInteractThreads;
-                        }
+                        const bool hit = (u < (int)lim) & (r2 < kp.r2max);
+                        *lp = (uint16_t)(((uint32_t)col << kRunBits) + k0 + u);
+                        lp += hit ? kInteractThreads : 0;
                     }
                     if (lp >= lpcap) {
                         const int cnt = (int)((lp - lp0) / kInteractThreads);

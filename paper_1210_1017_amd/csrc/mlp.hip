@@ -14,245 +14,179 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNnSlots = SPH_NN_SLOTS;       // neighbour slots per row
 constexpr int kNnIn = SPH_NN_IN;             // 64 * 8 + 32
-constexpr int kNnList = 128;                 // in-support neighbours kept before the sort
-constexpr uint64_t kNoKey = ~0ull;
+constexpr int kNnUnroll = 8;                 // candidates loaded together in the distance test
+constexpr int kNnRowThreads = 256;
+constexpr uint32_t kNnRsrcWord3 = 0x00020000u;  // buffer resource: 32-bit raw dwords
 
 struct NnScales {
-    float inv_len, inv_vel, rho_ref, inv_rho;
+    float inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho;
 };
 
-// ===================================================== neighbour selection
-// LDS of one wave: the in-support neighbours of the current row as
-// (FP32 squared-distance bits, sorted index).
-struct NnList {
-    uint32_t r2[kNnList];
-    uint32_t j[kNnList];
+typedef float nv4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float nn_kind(uint8_t t) { return t == kBoundary ? -1.0f : 1.0f; }
+
+// ============================================================ input rows
+// One lane per row (the paper's thread-per-particle mapping of Sec. 3.2).
+// Row of sorted particle i: the particles j != i of the 27 cells around i's
+// cell (Sec. 3.1: 9 contiguous z-runs in the x-major cell order) with FP32
+// squared distance fmaf(dz,dz,fmaf(dy,dy,dx*dx)) < r2f, in increasing sorted
+// index (runs and their particles are visited in that order); the first 64
+// fill the slots. Pass 1 tests the candidates (groups of kNnUnroll buffer
+// loads in flight) and appends (run << 12 | offset) entries to the lane's
+// list in LDS; pass 2 walks the list, writes each slot's 8 features and sums
+// the pressure and continuity terms of Sec. 2.2 for the own block.
+struct NnRowLds {
+    uint16_t list[kNnSlots][kNnRowThreads];
+    uint32_t base[9][kNnRowThreads];
 };
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// One compare-exchange stage of a bitonic sort over the wave; element e of
-// the sequence sits in this register of lane e % 64.
-__device__ __forceinline__ uint64_t bitonic_stage(uint64_t key, uint32_t e, uint32_t k,
-                                                  uint32_t jj) {
-    const uint64_t v = shfl_xor_u64(key, (int)jj);
-    const bool asc = (e & k) == 0;
-    const bool lower = (e & jj) == 0;
-    const uint64_t mn = key < v ? key : v, mx = key < v ? v : key;
-    return (lower == asc) ? mn : mx;
-}
-
-// Called by a whole wave for one particle i (wave-uniform): finds every j != i
-// of the 27 cells around i's cell that passes the FP32 support test (Sec. 2.2,
-// cells of Sec. 3.1), keeps the first kNnList in LDS (ballot compaction), and
-// sorts them by (r2, j) with a bitonic network over the wave's registers.
-// Returns in lane l the l-th smallest key (r2 bits << 32 | j), kNoKey if
-// fewer, and the neighbour count before truncation.
-// Latency: lanes 0..8 fetch the bounds of the 9 z-runs at once; the runs are
-// then walked as one flat candidate range, kNnBatch x 64 candidates (their
-// positions loaded together) per round.
-constexpr int kNnBatch = 4;
-
-__device__ __forceinline__ uint64_t nn_select(const KParams &kp, const float4 *__restrict__ pos4,
-                                              const uint32_t *__restrict__ cbeg,
-                                              const uint32_t *__restrict__ cend, uint32_t cell,
-                                              uint32_t i, float4 pi, NnList *L,
-                                              uint32_t &count) {
-    const uint32_t lane = threadIdx.x & 63;
+__device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &sc,
+                                            const float4 *__restrict__ pos4,
+                                            const float4 *__restrict__ vel4,
+                                            const uint8_t *__restrict__ type,
+                                            const uint32_t *__restrict__ sk,
+                                            const uint32_t *__restrict__ cbeg,
+                                            const uint32_t *__restrict__ cend, uint32_t n,
+                                            uint32_t n0, uint32_t i, NnRowLds &L, bf16 *dst,
+                                            size_t cstride, uint32_t *flags) {
+    // dst: the row's first 16-byte chunk; chunk q lies cstride chunks further
+    // (1: rows are contiguous; the row count: chunk-major, chunk q of every
+    // row first, so that a wave's 64 lanes store 1 KB contiguously)
+    const int tid = threadIdx.x;
+    bf16x8 *d8 = reinterpret_cast<bf16x8 *>(dst);
+    bf16x8 zero8;
+#pragma unroll
+    for (int q = 0; q < 8; q++) zero8[q] = (bf16)0.0f;
+    if (i >= n0 || type[i] == kGhost) {
+        for (int q = 0; q < kNnIn / 8; q++) d8[q * cstride] = zero8;
+        return;
+    }
+    const __amdgpu_buffer_rsrc_t rp =
+        __builtin_amdgcn_make_buffer_rsrc((void *)pos4, 0, (int)(n * 16u), kNnRsrcWord3);
+    const float4 pi = pos4[i], vi = vel4[i];
+    const uint32_t cell = sk[i] & kp.cell_mask;
     const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
     const int cz = (int)(cell % ncz), cy = (int)((cell / ncz) % ncy), cx = (int)(cell / (ncz * ncy));
     const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
     const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
-    uint32_t rb = 0, re = 0;
-    if (lane < 9) {
-        const int X = cx + (int)lane / 3 - 1, Y = cy + (int)lane % 3 - 1;
+    // pass 1: distance test, list of the first 64 in sorted-index order
+    uint32_t found = 0, listed = 0;
+    for (int col = 0; col < 9; col++) {
+        const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
+        uint32_t jb = 0, je = 0;
         if (X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
             const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
-            rb = cbeg[c0 + zlo];
-            re = cend[c0 + zhi];
+            jb = cbeg[c0 + zlo];
+            je = cend[c0 + zhi];
         }
-    }
-    // flat candidate t of run r maps to j = t + delta[r], run r spanning
-    // [off[r], off[r+1]) of the flat range (wave-uniform values)
-    uint32_t off[10], delta[9];
-    off[0] = 0;
-#pragma unroll
-    for (int r = 0; r < 9; r++) {
-        const uint32_t b = __builtin_amdgcn_readlane(rb, r), e = __builtin_amdgcn_readlane(re, r);
-        delta[r] = b - off[r];
-        off[r + 1] = off[r] + (e - b);
-    }
-    const uint32_t total = off[9];
-    uint32_t cnt = 0;
-    for (uint32_t t0 = 0; t0 < total; t0 += 64 * kNnBatch) {
-        float4 pj[kNnBatch];
-        uint32_t jv[kNnBatch];
-#pragma unroll
-        for (int u = 0; u < kNnBatch; u++) {
-            const uint32_t t = t0 + 64 * u + lane;
-            uint32_t j = t + delta[0];
-#pragma unroll
-            for (int r = 1; r < 9; r++) j = t >= off[r] ? t + delta[r] : j;
-            jv[u] = t < total ? j : 0xffffffffu;
-            pj[u] = t < total ? pos4[j] : pi;
+        if (je - jb > kRunMax + 1u) {
+            atomicOr(flags, (uint32_t)SPH_S_RUN_OVERFLOW);
+            je = jb + kRunMax + 1u;
         }
+        L.base[col][tid] = jb;
+        const uint32_t len = je - jb, voff = jb * 16u;
+        for (uint32_t k0 = 0; k0 < len; k0 += kNnUnroll) {
+            nv4f q[kNnUnroll];
 #pragma unroll
-        for (int u = 0; u < kNnBatch; u++) {
-            const uint32_t j = jv[u];
-            const float dx = pi.x - pj[u].x, dy = pi.y - pj[u].y, dz = pi.z - pj[u].z;
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const bool ok = j != 0xffffffffu && j != i && r2 < kp.r2max;
-            const uint64_t m = __ballot(ok);
-            const uint32_t pos =
-                cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (ok && pos < (uint32_t)kNnList) {
-                L->r2[pos] = __float_as_uint(r2);
-                L->j[pos] = j;
+            for (int u = 0; u < kNnUnroll; u++)  // past the run: in-bounds data or 0, masked below
+                q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
+#pragma unroll
+            for (int u = 0; u < kNnUnroll; u++) {
+                const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (k0 + u < len && jb + k0 + u != i && r2 < sc.r2f) {
+                    if (listed < (uint32_t)kNnSlots) {
+                        L.list[listed][tid] = (uint16_t)(((uint32_t)col << kRunBits) + k0 + u);
+                        listed++;
+                    }
+                    found++;
+                }
             }
-            cnt += (uint32_t)__popcll(m);
         }
     }
-    count = cnt;
-    wave_lds_sync();
-    const uint32_t m = cnt < (uint32_t)kNnList ? cnt : (uint32_t)kNnList;
-    uint64_t k0 = lane < m ? (((uint64_t)L->r2[lane] << 32) | L->j[lane]) : kNoKey;
-    if (m <= 64) {
-#pragma unroll
-        for (uint32_t k = 2; k <= 64; k <<= 1)
-#pragma unroll
-            for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) k0 = bitonic_stage(k0, lane, k, jj);
-    } else {
-        uint64_t k1 = lane + 64 < m ? (((uint64_t)L->r2[lane + 64] << 32) | L->j[lane + 64])
-                                    : kNoKey;
-        // halves in opposite directions, one merge step keeps the smaller 64
-        // (a bitonic sequence), which the last six stages sort
-#pragma unroll
-        for (uint32_t k = 2; k <= 64; k <<= 1)
-#pragma unroll
-            for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-                k0 = bitonic_stage(k0, lane, k, jj);
-                k1 = bitonic_stage(k1, lane + 64, k, jj);
-            }
-        k0 = k0 < k1 ? k0 : k1;
-#pragma unroll
-        for (uint32_t jj = 32; jj > 0; jj >>= 1) k0 = bitonic_stage(k0, lane, 128, jj);
+    // pass 2: slot features and the pair sums
+    float apx = 0.f, apy = 0.f, apz = 0.f, dr = 0.f;
+    const float inv_2h = 0.5f * kp.inv_h;
+#pragma unroll 4
+    for (uint32_t s = 0; s < listed; s++) {
+        const uint32_t e = L.list[s][tid];
+        const uint32_t j = L.base[e >> kRunBits][tid] + (e & kRunMax);
+        const float4 pj = pos4[j], vj = vel4[j];
+        const float ddx = pj.x - pi.x, ddy = pj.y - pi.y, ddz = pj.z - pi.z;
+        const float dux = vj.x - vi.x, duy = vj.y - vi.y, duz = vj.z - vi.z;
+        bf16x8 f;
+        f[0] = (bf16)(ddx * sc.inv_len);
+        f[1] = (bf16)(ddy * sc.inv_len);
+        f[2] = (bf16)(ddz * sc.inv_len);
+        f[3] = (bf16)(dux * sc.inv_vel);
+        f[4] = (bf16)(duy * sc.inv_vel);
+        f[5] = (bf16)(duz * sc.inv_vel);
+        f[6] = (bf16)((vj.w - sc.rho_ref) * sc.inv_rho);
+        f[7] = (bf16)nn_kind(type[j]);
+        d8[s * cstride] = f;
+        // r_ij = r_i - r_j = -d, v_ij = -du: grad W = kgrad F r_ij with
+        // F = (1 - q/2)^3; the constants m kgrad are applied after the sum
+        const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+        const float t = fmaf(-inv_2h, __builtin_amdgcn_sqrtf(r2), 1.0f);
+        const float F = t * t * t;
+        const float fp = (pi.w + pj.w) * F;
+        apx = fmaf(fp, ddx, apx);  // sum (P_i + P_j) F (r_j - r_i)
+        apy = fmaf(fp, ddy, apy);
+        apz = fmaf(fp, ddz, apz);
+        dr = fmaf(F, fmaf(duz, ddz, fmaf(duy, ddy, dux * ddx)), dr);  // sum F v_ij . r_ij
     }
-    wave_lds_sync();  // the list is rewritten for the next row
-    return k0;
+    for (uint32_t s = listed; s < (uint32_t)kNnSlots; s++) d8[s * cstride] = zero8;
+    // ap = -m kgrad sum (P_i + P_j) F r_ij = m kgrad sum (P_i + P_j) F (r_j - r_i);
+    // dr = m kgrad sum F v_ij . r_ij = m kgrad sum F (u_j - u_i) . (r_j - r_i)
+    const float mk = kp.mass * kp.kgrad;
+    bf16x8 o0 = zero8, o1 = zero8;
+    o0[0] = (bf16)((vi.w - sc.rho_ref) * sc.inv_rho);
+    o0[1] = (bf16)(vi.x * sc.inv_vel);
+    o0[2] = (bf16)(vi.y * sc.inv_vel);
+    o0[3] = (bf16)(vi.z * sc.inv_vel);
+    o0[4] = (bf16)((float)found * (1.0f / 64.0f));
+    o0[5] = (bf16)nn_kind(type[i]);
+    o0[6] = (bf16)(mk * apx * sc.inv_acc);
+    o0[7] = (bf16)(mk * apy * sc.inv_acc);
+    o1[0] = (bf16)(mk * apz * sc.inv_acc);
+    o1[1] = (bf16)(mk * dr * sc.inv_drho);
+    d8[(kNnSlots + 0) * cstride] = o0;
+    d8[(kNnSlots + 1) * cstride] = o1;
+    d8[(kNnSlots + 2) * cstride] = zero8;
+    d8[(kNnSlots + 3) * cstride] = zero8;
 }
 
-__device__ __forceinline__ float nn_kind(uint8_t t) { return t == kBoundary ? -1.0f : 1.0f; }
-
-// The 8 features of the neighbour slot held by this lane (zeros if empty).
-__device__ __forceinline__ bf16x8 nn_slot(const NnScales &sc, const float4 *__restrict__ pos4,
-                                          const float4 *__restrict__ vel4,
-                                          const uint8_t *__restrict__ type, uint64_t key,
-                                          float4 pi, float4 vi) {
-    bf16x8 f;
-    if (key == kNoKey) {
-#pragma unroll
-        for (int q = 0; q < 8; q++) f[q] = (bf16)0.0f;
-        return f;
-    }
-    const uint32_t j = (uint32_t)key;
-    const float4 pj = pos4[j], vj = vel4[j];
-    f[0] = (bf16)((pj.x - pi.x) * sc.inv_len);
-    f[1] = (bf16)((pj.y - pi.y) * sc.inv_len);
-    f[2] = (bf16)((pj.z - pi.z) * sc.inv_len);
-    f[3] = (bf16)((vj.x - vi.x) * sc.inv_vel);
-    f[4] = (bf16)((vj.y - vi.y) * sc.inv_vel);
-    f[5] = (bf16)((vj.z - vi.z) * sc.inv_vel);
-    f[6] = (bf16)((vj.w - sc.rho_ref) * sc.inv_rho);
-    f[7] = (bf16)nn_kind(type[j]);
-    return f;
+// rows[r] (or r) for r < nrows, one lane each; row-major X (chunk_major = 0)
+// or chunk-major X (chunk q of row r at chunk q * nrows + r)
+__global__ __launch_bounds__(kNnRowThreads) void k_nn_features(
+    KParams kp, NnScales sc, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4,
+    const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
+    const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend, uint32_t n,
+    DevInfo *__restrict__ info, const int32_t *__restrict__ rows, uint32_t nrows,
+    bf16 *__restrict__ X, int chunk_major) {
+    __shared__ NnRowLds L;
+    const uint32_t r = xcd_block(blockIdx.x, gridDim.x) * kNnRowThreads + threadIdx.x;
+    if (r >= nrows) return;
+    const uint32_t i = rows ? (uint32_t)rows[r] : r;
+    bf16 *dst = chunk_major ? X + (size_t)r * 8 : X + (size_t)r * kNnIn;
+    nn_lane_row(kp, sc, pos4, vel4, type, sk, cbeg, cend, n, info->n_label[0], i, L, dst,
+                chunk_major ? (size_t)nrows : 1, &info->flags);
 }
 
-// The own block, 8 columns per lane for lanes 0..3 (lane 0 carries the six
-// used values, the rest is zero).
-__device__ __forceinline__ bf16x8 nn_own(const NnScales &sc, uint32_t lane, float4 vi,
-                                         uint32_t count, uint8_t t) {
-    bf16x8 f;
-#pragma unroll
-    for (int q = 0; q < 8; q++) f[q] = (bf16)0.0f;
-    if (lane == 0) {
-        f[0] = (bf16)((vi.w - sc.rho_ref) * sc.inv_rho);
-        f[1] = (bf16)(vi.x * sc.inv_vel);
-        f[2] = (bf16)(vi.y * sc.inv_vel);
-        f[3] = (bf16)(vi.z * sc.inv_vel);
-        f[4] = (bf16)((float)count * (1.0f / 64.0f));
-        f[5] = (bf16)nn_kind(t);
-    }
-    return f;
-}
-
-// Builds row `i` (sorted index) into dst (row of kNnIn bfloat16, 16-byte
-// aligned; global or LDS). Whole wave, i wave-uniform.
-__device__ __forceinline__ void nn_row(const KParams &kp, const NnScales &sc,
-                                       const float4 *__restrict__ pos4,
-                                       const float4 *__restrict__ vel4,
-                                       const uint8_t *__restrict__ type,
-                                       const uint32_t *__restrict__ sk,
-                                       const uint32_t *__restrict__ cbeg,
-                                       const uint32_t *__restrict__ cend, uint32_t i,
-                                       uint32_t n0, NnList *L, bf16 *dst, uint32_t *flags) {
-    const uint32_t lane = threadIdx.x & 63;
-    i = __builtin_amdgcn_readfirstlane(i);
-    bf16x8 *d8 = reinterpret_cast<bf16x8 *>(dst);
-    if (i >= n0 || type[i] == kGhost) {
-        bf16x8 z;
-#pragma unroll
-        for (int q = 0; q < 8; q++) z[q] = (bf16)0.0f;
-        d8[lane] = z;
-        if (lane < 4) d8[kNnSlots + lane] = z;
-        return;
-    }
-    const float4 pi = pos4[i], vi = vel4[i];
-    uint32_t count;
-    const uint64_t key = nn_select(kp, pos4, cbeg, cend, sk[i] & kp.cell_mask, i, pi, L, count);
-    if (count > (uint32_t)kNnList && lane == 0) atomicOr(flags, (uint32_t)SPH_S_NN_LIST);
-    d8[lane] = nn_slot(sc, pos4, vel4, type, key, pi, vi);
-    if (lane < 4) d8[kNnSlots + lane] = nn_own(sc, lane, vi, count, type[i]);
-}
-
-__global__ __launch_bounds__(256) void k_nn_features(KParams kp, NnScales sc,
-                                                     const float4 *__restrict__ pos4,
-                                                     const float4 *__restrict__ vel4,
-                                                     const uint8_t *__restrict__ type,
-                                                     const uint32_t *__restrict__ sk,
-                                                     const uint32_t *__restrict__ cbeg,
-                                                     const uint32_t *__restrict__ cend,
-                                                     DevInfo *__restrict__ info,
-                                                     const int32_t *__restrict__ rows,
-                                                     uint32_t nrows, bf16 *__restrict__ X) {
-    __shared__ NnList s_list[4];
-    const uint32_t w = threadIdx.x >> 6;
-    const uint32_t n0 = info->n_label[0];
-    for (uint32_t r = blockIdx.x * 4 + w; r < nrows; r += gridDim.x * 4) {
-        const uint32_t i = rows ? (uint32_t)rows[r] : r;
-        nn_row(kp, sc, pos4, vel4, type, sk, cbeg, cend, i, n0, &s_list[w],
-               X + (size_t)r * kNnIn, &info->flags);
-    }
+static NnScales nn_scales(const sph_nn_scales &s) {
+    return NnScales{s.inv_len, s.inv_vel, s.rho_ref, s.inv_rho, s.r2f, s.inv_acc, s.inv_drho};
 }
 
 hipError_t launch_nn_features(sph_ctx *c, const uint8_t *type, const int32_t *rows,
-                              uint32_t nrows, const sph_nn_scales &s, void *X, hipStream_t st) {
+                              uint32_t nrows, const sph_nn_scales &s, void *X, int chunk_major,
+                              hipStream_t st) {
     if (nrows == 0) return hipSuccess;
-    const NnScales sc{s.inv_len, s.inv_vel, s.rho_ref, s.inv_rho};
-    const uint32_t blocks = (nrows + 3) / 4 < 65536u ? (nrows + 3) / 4 : 65536u;
-    hipLaunchKernelGGL(k_nn_features, dim3(blocks), dim3(256), 0, st, c->kp, sc, c->pos4,
-                       c->vel4, type, c->keys_sorted, c->cell_begin, c->cell_end, c->info, rows,
-                       nrows, (bf16 *)X);
+    const uint32_t n = c->sorted_n;
+    hipLaunchKernelGGL(k_nn_features, dim3((nrows + kNnRowThreads - 1) / kNnRowThreads),
+                       dim3(kNnRowThreads), 0, st, c->kp, nn_scales(s), c->pos4, c->vel4, type,
+                       c->keys_sorted, c->cell_begin, c->cell_end, n, c->info, rows, nrows,
+                       (bf16 *)X, chunk_major);
     return hipGetLastError();
 }
 
@@ -399,9 +333,15 @@ hipError_t launch_gemm(const void *A, const void *B, float *C, int M, int N, int
 }
 
 // ============================================================ element-wise
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+// SiLU z sigma(z) with the hardware exp2 and reciprocal (about 1 ulp each):
+// sigma(z) = 1 / (1 + 2^(-z log2 e)); for z -> -inf the reciprocal of inf is
+// 0, so SiLU -> -0 as it should.
+__device__ __forceinline__ float sigmoid_fast(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504f * z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid_fast(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-    const float s = 1.0f / (1.0f + expf(-z));
+    const float s = sigmoid_fast(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -645,6 +585,48 @@ hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, uint32
     return hipGetLastError();
 }
 
+// Training noise (see sph_nn_perturb): murmur3's 32-bit finaliser as a
+// counter-based generator, one value per (seed, particle, component).
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ float noise_u(uint32_t seed, uint32_t k, uint32_t c) {
+    const uint32_t h = fmix32(seed ^ fmix32(4u * k + c + 0x9e3779b9u));
+    return (float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f;  // uniform in [-1, 1)
+}
+
+__global__ __launch_bounds__(256) void k_nn_perturb(sph_soa st, uint32_t n, uint32_t seed,
+                                                    float au, float ar) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n || st.type[k] != kFluid) return;
+    float *v[3] = {st.vx, st.vy, st.vz};
+    float *vp[3] = {st.vxp, st.vyp, st.vzp};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const float e = au * noise_u(seed, k, (uint32_t)d);
+        v[d][k] += e;
+        vp[d][k] += e;
+    }
+    const float e = ar * noise_u(seed, k, 3u);
+    st.rho[k] += e;
+    st.rhop[k] += e;
+}
+
+hipError_t launch_nn_perturb(const sph_soa &st, uint32_t n, uint32_t seed, float sigma_u,
+                             float sigma_rho, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const float k3 = 1.7320508f;  // a uniform on [-a, a) has standard deviation a / sqrt(3)
+    hipLaunchKernelGGL(k_nn_perturb, grid1(n), dim3(256), 0, s, st, n, seed, k3 * sigma_u,
+                       k3 * sigma_rho);
+    return hipGetLastError();
+}
+
 // Error of surrogate state S against reference R from base B (see
 // sph_nn_judge): per-block partials, then one block adds them in order.
 constexpr int kJudge = 8;
@@ -717,149 +699,205 @@ hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
     return hipGetLastError();
 }
 
-// ================================================== fused surrogate advance
-// One workgroup (14 waves) per tile of 64 sorted particles:
-//  1. the waves build the 64 input rows (nn_row, 4 or 5 each) into an LDS
-//     tile [64][kXS]; the row being built doubles as that wave's neighbour
-//     list;
-//  2. layer 1 (544 -> 128): wave w < 8 computes output columns
-//     [16w, 16w+16) for all 64 rows, A fragments from the LDS tile, B
-//     fragments (16 bytes of a weight row) straight from global memory (the
-//     weights stay in L2, each read once per tile);
-//  3. bias + SiLU to bfloat16 into LDS (two ping-pong tiles inside the input
-//     tile's space), layers 2 and 3 (128 -> 128) likewise;
-//  4. layer 4 (128 -> 4) with the output columns padded to 16, one row block
-//     per wave w < 4; the 64 x 4 result goes through LDS to one thread per
-//     particle, which applies it (nn_apply_one).
-// LDS: 64 x 552 bfloat16 (70.6 KB) + 1 KB, two workgroups (28 waves) per CU.
-constexpr int kFW = 128;          // hidden width of the fused kernel
+// ============================================ network + application kernel
+// Persistent: one workgroup (4 waves) per CU walks the tiles of 64
+// consecutive rows of a chunk-major X (rows of sorted particles
+// base .. base + 63). Wave w owns output columns [32w, 32w+32) of the three
+// hidden layers and keeps its weight fragments (the B operands of
+// v_mfma_f32_16x16x32_bf16: 16 bytes of a weight row per lane, k step and
+// 16-column block) in registers for the whole kernel, so the layers read
+// only LDS; each A fragment read from LDS feeds two MFMAs. Per tile:
+//  1. the tile, prefetched into registers during the previous tile, is
+//     stored into LDS [64][kXS] (1 KB contiguous per chunk and tile);
+//  2. layer 1 (544 -> 128) for all 64 rows of the wave's columns; bias +
+//     SiLU to bfloat16 into LDS (ping-pong tiles inside the input tile's
+//     space), layers 2 and 3 (128 -> 128) likewise;
+//  3. layer 4 (128 -> 4, output columns padded to 16): one row block per
+//     wave; the 64 x 4 result goes through LDS to one thread per particle,
+//     which applies it (nn_apply_one).
+constexpr int kFW = 128;          // hidden width of this kernel
 constexpr int kXS = kNnIn + 8;    // padded row of the input tile (bfloat16)
 constexpr int kHS = kFW + 8;      // padded row of a hidden activation tile
-constexpr int kFusedWaves = 14;  // two workgroups per CU at 7 waves per SIMD
-constexpr int kMlpWaves = kFW / 16;
+constexpr int kMlpWaves = 4;
+constexpr int kMlpCols = kFW / kMlpWaves;   // 32 output columns per wave
+constexpr int kMlpCB = kMlpCols / 16;       // 16-column MFMA blocks per wave
+constexpr int kMlpThreads = 64 * kMlpWaves;
+constexpr int kChunks = kNnIn / 8;                                  // 16-byte chunks per row
+constexpr int kPref = (64 * kChunks + kMlpThreads - 1) / kMlpThreads;  // chunks per thread
 
 struct FusedNet {
     const bf16 *w0, *w1, *w2, *w3;
     const float *b0, *b1, *b2, *b3;
 };
 
-// acc[rb] = A(LDS rows 16 rb.., row stride lda) x W^T(cols col0 .. col0+15)
-template <int KD>
-__device__ __forceinline__ void fused_layer(const bf16 *sA, int lda, const bf16 *__restrict__ W,
-                                            int col0, f32x4 (&acc)[4]) {
+// acc[rb][cb] = A(LDS rows 16 rb.., row stride lda) x B fragments wb[cb][ks]
+template <int KS>
+__device__ __forceinline__ void mlp_layer(const bf16 *sA, int lda,
+                                          const bf16x8 (&wb)[kMlpCB][KS],
+                                          f32x4 (&acc)[4][kMlpCB]) {
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kb = (lane >> 4) * 8;
 #pragma unroll
-    for (int a = 0; a < 4; a++) acc[a] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16 *wrow = W + (size_t)(col0 + row) * KD + kb;
-#pragma unroll 2
-    for (int k0 = 0; k0 < KD; k0 += 32) {
-        const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(wrow + k0);
-        bf16x8 fa[4];
+    for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int a = 0; a < 4; a++)
-            fa[a] = *reinterpret_cast<const bf16x8 *>(sA + (a * 16 + row) * lda + k0 + kb);
+        for (int c = 0; c < kMlpCB; c++) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int a = 0; a < 4; a++)
-            acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[a], 0, 0, 0);
+    for (int ks = 0; ks < KS; ks++) {
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            const bf16x8 fa =
+                *reinterpret_cast<const bf16x8 *>(sA + (a * 16 + row) * lda + ks * 32 + kb);
+#pragma unroll
+            for (int c = 0; c < kMlpCB; c++)
+                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, wb[c][ks], acc[a][c], 0, 0, 0);
+        }
     }
 }
 
-// bias + SiLU of a 64 x 16 column slab (cols col0..) into an LDS tile
-__device__ __forceinline__ void fused_store_act(const f32x4 (&acc)[4],
-                                                const float *__restrict__ bias, int col0,
-                                                bf16 *sH) {
+// bias + SiLU of the wave's 64 x 32 slab (cols col0..) into an LDS tile
+__device__ __forceinline__ void mlp_store_act(const f32x4 (&acc)[4][kMlpCB],
+                                              const float (&bias)[kMlpCB], int col0, bf16 *sH) {
     const int lane = threadIdx.x & 63;
-    const int c = col0 + (lane & 15), rb = (lane >> 4) * 4;
-    const float bc = bias[c];
+    const int rb = (lane >> 4) * 4;
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int c = 0; c < kMlpCB; c++) {
+        const int col = col0 + c * 16 + (lane & 15);
 #pragma unroll
-        for (int r = 0; r < 4; r++) sH[(a * 16 + rb + r) * kHS + c] = (bf16)silu(acc[a][r] + bc);
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                sH[(a * 16 + rb + r) * kHS + col] = (bf16)silu(acc[a][c][r] + bias[c]);
+    }
 }
 
-__global__ __launch_bounds__(64 * 14, 2) void k_nn_fused(KParams kp, NnScales sc, FusedNet net,
-                                                      const float4 *__restrict__ pos4,
-                                                      const float4 *__restrict__ vel4,
-                                                      const uint32_t *__restrict__ sk,
-                                                      const uint32_t *__restrict__ cbeg,
-                                                      const uint32_t *__restrict__ cend,
-                                                      sph_soa st, NnApply ap,
-                                                      DevInfo *__restrict__ info) {
+// Workgroup barrier that waits for this wave's LDS operations only: unlike
+// __syncthreads() it leaves the next tile's global prefetch loads in flight.
+// The memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int KS>
+__device__ __forceinline__ void load_frags(const bf16 *__restrict__ W, int ncols_real, int col,
+                                           bf16x8 (&wb)[KS]) {
+    const int kb = ((threadIdx.x & 63) >> 4) * 8;
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+        if (col < ncols_real) {
+            wb[ks] = *reinterpret_cast<const bf16x8 *>(W + (size_t)col * (KS * 32) + ks * 32 + kb);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; q++) wb[ks][q] = (bf16)0.0f;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMlpThreads, 1) void k_nn_mlp_apply(KParams kp, FusedNet net,
+                                                                  const bf16 *__restrict__ X,
+                                                                  uint32_t nrows, sph_soa st,
+                                                                  NnApply ap,
+                                                                  DevInfo *__restrict__ info) {
     __shared__ __attribute__((aligned(16))) bf16 sX[64 * kXS];
     __shared__ float sY[64][4];
     const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t n0 = info->n_label[0];
-    const uint32_t base = xcd_block(blockIdx.x, gridDim.x) * 64;
-    // 1. input rows (each row's LDS space is its wave's neighbour list first)
-    for (uint32_t rr = w; rr < 64; rr += kFusedWaves)
-        nn_row(kp, sc, pos4, vel4, st.type, sk, cbeg, cend, base + rr, n0,
-               reinterpret_cast<NnList *>(sX + rr * kXS), sX + rr * kXS, &info->flags);
-    __syncthreads();
-    // 2-3. hidden layers; activations ping-pong between two tiles in sX
-    bf16 *h0 = sX, *h1 = sX + 64 * kHS;
-    f32x4 acc[4];
-    const int col0 = (int)w * 16;
-    const bool mlp = w < (uint32_t)kMlpWaves;
-    if (mlp) fused_layer<kNnIn>(sX, kXS, net.w0, col0, acc);
-    __syncthreads();  // every wave is done reading the input tile
-    if (mlp) fused_store_act(acc, net.b0, col0, h0);
-    __syncthreads();
-    if (mlp) {
-        fused_layer<kFW>(h0, kHS, net.w1, col0, acc);
-        fused_store_act(acc, net.b1, col0, h1);
-    }
-    __syncthreads();
-    if (mlp) {
-        fused_layer<kFW>(h1, kHS, net.w2, col0, acc);
-        fused_store_act(acc, net.b2, col0, h0);  // h0's last reads (layer 2) ended at the sync above
-    }
-    __syncthreads();
-    // 4. output layer: rows [16w, 16w+16), 4 real columns of 16
-    if (w < 4) {
-        const int row = lane & 15, kb = (lane >> 4) * 8;
-        f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint32_t ntiles = (nrows + 63) / 64;
+    const int col0 = (int)w * kMlpCols;
+    // weight fragments and biases of this wave, for the whole kernel
+    bf16x8 wb0[kMlpCB][kNnIn / 32], wb1[kMlpCB][kFW / 32], wb2[kMlpCB][kFW / 32];
+    bf16x8 wb3[1][kFW / 32];
+    float bias0[kMlpCB], bias1[kMlpCB], bias2[kMlpCB];
 #pragma unroll
-        for (int k0 = 0; k0 < kFW; k0 += 32) {
-            const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(h0 + (w * 16 + row) * kHS + k0 + kb);
-            bf16x8 fb;
-            if (row < SPH_NN_OUT) {
-                fb = *reinterpret_cast<const bf16x8 *>(net.w3 + (size_t)row * kFW + k0 + kb);
+    for (int c = 0; c < kMlpCB; c++) {
+        const int col = col0 + c * 16 + (int)(lane & 15);
+        load_frags<kNnIn / 32>(net.w0, kFW, col, wb0[c]);
+        load_frags<kFW / 32>(net.w1, kFW, col, wb1[c]);
+        load_frags<kFW / 32>(net.w2, kFW, col, wb2[c]);
+        bias0[c] = net.b0[col];
+        bias1[c] = net.b1[col];
+        bias2[c] = net.b2[col];
+    }
+    load_frags<kFW / 32>(net.w3, SPH_NN_OUT, (int)(lane & 15), wb3[0]);
+    const float bias3 = (lane & 15) < SPH_NN_OUT ? net.b3[lane & 15] : 0.0f;
+    bf16x8 pf[kPref];
+    auto prefetch = [&](uint32_t tile) {
+        const uint32_t base = tile * 64;
+#pragma unroll
+        for (int e = 0; e < kPref; e++) {
+            const int c = e * kMlpThreads + (int)threadIdx.x;  // chunk-major: row = c % 64
+            const int q = c / 64, row = c % 64;
+            if (c < 64 * kChunks && base + row < nrows) {
+                pf[e] = *reinterpret_cast<const bf16x8 *>(X + ((size_t)q * nrows + base + row) * 8);
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; q++) fb[q] = (bf16)0.0f;
+                for (int k = 0; k < 8; k++) pf[e][k] = (bf16)0.0f;
             }
-            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, o, 0, 0, 0);
         }
-        const int col = lane & 15, rb = (lane >> 4) * 4;
-        if (col < SPH_NN_OUT) {
-            const float bc = net.b3[col];
+    };
+    uint32_t tile = blockIdx.x;
+    if (tile < ntiles) prefetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const uint32_t base = tile * 64;
 #pragma unroll
-            for (int r = 0; r < 4; r++) sY[w * 16 + rb + r][col] = o[r] + bc;
+        for (int e = 0; e < kPref; e++) {
+            const int c = e * kMlpThreads + (int)threadIdx.x;
+            if (c < 64 * kChunks)
+                *reinterpret_cast<bf16x8 *>(sX + (c % 64) * kXS + (c / 64) * 8) = pf[e];
         }
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const uint32_t k = base + threadIdx.x;
-        if (k < n0)
-            nn_apply_one(kp, st, k, sY[threadIdx.x][0], sY[threadIdx.x][1], sY[threadIdx.x][2],
-                         sY[threadIdx.x][3], ap, &info->flags);
+        lds_barrier();
+        if (tile + gridDim.x < ntiles) prefetch(tile + gridDim.x);
+        bf16 *h0 = sX, *h1 = sX + 64 * kHS;
+        f32x4 acc[4][kMlpCB];
+        mlp_layer<kNnIn / 32>(sX, kXS, wb0, acc);
+        lds_barrier();  // every wave is done reading the input tile
+        mlp_store_act(acc, bias0, col0, h0);
+        lds_barrier();
+        mlp_layer<kFW / 32>(h0, kHS, wb1, acc);
+        mlp_store_act(acc, bias1, col0, h1);
+        lds_barrier();
+        mlp_layer<kFW / 32>(h1, kHS, wb2, acc);
+        mlp_store_act(acc, bias2, col0, h0);  // h0's last reads (layer 2) ended at the barrier above
+        lds_barrier();
+        {
+            const int row = lane & 15, kb = (lane >> 4) * 8;
+            f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < kFW / 32; ks++) {
+                const bf16x8 fa =
+                    *reinterpret_cast<const bf16x8 *>(h0 + (w * 16 + row) * kHS + ks * 32 + kb);
+                o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, wb3[0][ks], o, 0, 0, 0);
+            }
+            const int col = lane & 15, rb = (lane >> 4) * 4;
+            if (col < SPH_NN_OUT) {
+#pragma unroll
+                for (int r = 0; r < 4; r++) sY[w * 16 + rb + r][col] = o[r] + bias3;
+            }
+        }
+        lds_barrier();
+        if (threadIdx.x < 64) {
+            const uint32_t k = base + threadIdx.x;
+            if (k < n0 && k < nrows)
+                nn_apply_one(kp, st, k, sY[threadIdx.x][0], sY[threadIdx.x][1],
+                             sY[threadIdx.x][2], sY[threadIdx.x][3], ap, &info->flags);
+        }
+        lds_barrier();  // sX and sY are rewritten for the next tile
     }
 }
 
-hipError_t launch_nn_fused(sph_ctx *c, const sph_mlp &m, const sph_soa &st, uint32_t n,
-                           const sph_nn_scales &s, float dv_scale, float dr_scale, float dt4,
-                           float rho_tol, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    const NnScales sc{s.inv_len, s.inv_vel, s.rho_ref, s.inv_rho};
+hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
+                               uint32_t nrows, float dv_scale, float dr_scale, float dt4,
+                               float rho_tol, hipStream_t stream) {
+    if (nrows == 0) return hipSuccess;
     const FusedNet net{(const bf16 *)m.wb[0], (const bf16 *)m.wb[1], (const bf16 *)m.wb[2],
                        (const bf16 *)m.wb[3], m.b[0], m.b[1], m.b[2], m.b[3]};
     const NnApply ap{dv_scale, dr_scale, dt4, rho_tol};
-    // tiles over all n: rows past the label-0 prefix are zero and not applied
-    hipLaunchKernelGGL(k_nn_fused, dim3((n + 63) / 64), dim3(64 * kFusedWaves), 0, stream, c->kp,
-                       sc, net,
-                       c->pos4, c->vel4, c->keys_sorted, c->cell_begin, c->cell_end, st, ap,
-                       c->info);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint32_t ntiles = (nrows + 63) / 64;
+    const uint32_t grid = ntiles < (uint32_t)cus ? ntiles : (uint32_t)cus;
+    hipLaunchKernelGGL(k_nn_mlp_apply, dim3(grid), dim3(kMlpThreads), 0, stream, c->kp, net,
+                       (const bf16 *)X, nrows, st, ap, c->info);
     return hipGetLastError();
 }
 

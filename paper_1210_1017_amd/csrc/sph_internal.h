@@ -80,6 +80,8 @@ struct sph_ctx {
     double *tot_part = nullptr;   // 8 doubles per totals block
     double *nn_part = nullptr;    // 8 doubles per surrogate-judge block
     double *nn_out = nullptr;     // 8 doubles: judge result
+    void *nn_x = nullptr;         // surrogate input rows of sph_nn_advance (lazily allocated)
+    size_t nn_x_rows = 0;
     uint32_t tot_blocks = 0;
     int last_path = 0;            // 0 plain, 1 cell, 2 FP64: which state the tables describe
     // optional per-phase timing of sph_step (events: start, sorted, interacted, updated)
@@ -144,7 +146,8 @@ hipError_t launch_totals_d(sph_ctx *c, const sph_dstate &st, uint32_t n, double 
 // mlp.hip (learned surrogate)
 constexpr int kMlpSplits = 32;  // split-K slices of a weight-gradient GEMM, at most
 hipError_t launch_nn_features(sph_ctx *c, const uint8_t *type, const int32_t *rows,
-                              uint32_t nrows, const sph_nn_scales &s, void *X, hipStream_t st);
+                              uint32_t nrows, const sph_nn_scales &s, void *X, int chunk_major,
+                              hipStream_t st);
 hipError_t launch_gemm(const void *A, const void *B, float *C, int M, int N, int K,
                        long long sam, long long sak, long long sbk, long long sbn, long long scm,
                        long long scn, int accumulate, float *part, hipStream_t s);
@@ -166,12 +169,14 @@ hipError_t launch_nn_targets(const sph_soa &a, const sph_soa &b, const int32_t *
 hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, uint32_t nrows,
                            float dv_scale, float dr_scale, float dt4, float rho_tol,
                            hipStream_t s);
+hipError_t launch_nn_perturb(const sph_soa &st, uint32_t n, uint32_t seed, float sigma_u,
+                             float sigma_rho, hipStream_t s);
 hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
                            const int32_t *where_r, const int32_t *where_b, uint32_t n,
                            double *part, double *out, hipStream_t s);
-hipError_t launch_nn_fused(sph_ctx *c, const sph_mlp &m, const sph_soa &st, uint32_t n,
-                           const sph_nn_scales &s, float dv_scale, float dr_scale, float dt4,
-                           float rho_tol, hipStream_t stream);
+hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
+                               uint32_t nrows, float dv_scale, float dr_scale, float dt4,
+                               float rho_tol, hipStream_t stream);
 
 // update.hip
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,

@@ -81,7 +81,8 @@ class Counts(C.Structure):
 
 class NnScales(C.Structure):
     _fields_ = [("inv_len", C.c_float), ("inv_vel", C.c_float), ("rho_ref", C.c_float),
-                ("inv_rho", C.c_float)]
+                ("inv_rho", C.c_float), ("r2f", C.c_float), ("inv_acc", C.c_float),
+                ("inv_drho", C.c_float), ("reserved", C.c_float)]
 
 
 _P4 = C.c_void_p * 4
@@ -157,6 +158,7 @@ def lib() -> C.CDLL:
         L.sph_nn_apply.argtypes = [vp, P(SoA), vp, u32, f32, f32, f32, f32, vp]
         L.sph_nn_advance.argtypes = [vp, P(MlpStruct), P(SoA), P(SoA), u32, P(NnScales), f32,
                                      f32, f32, f32, vp]
+        L.sph_nn_perturb.argtypes = [vp, P(SoA), u32, u32, f32, f32, vp]
         L.sph_nn_judge.argtypes = [vp, P(SoA), P(SoA), P(SoA), vp, vp, u32, P(C.c_double), vp]
         _lib = L
     return _lib
@@ -471,7 +473,7 @@ class Context:
         self._check(self.L.sph_mlp_sync(self.h, C.byref(net.struct()), _stream_ptr(stream)))
 
     def nn_features(self, srt: DeviceState, rows, nrows: int, scales, X, stream=None):
-        sc = NnScales(*[float(v) for v in scales])
+        sc = NnScales(*[float(v) for v in scales[:7]])
         self._check(self.L.sph_nn_features(self.h, C.byref(srt.soa()),
                                            None if rows is None else _addr(rows), nrows,
                                            C.byref(sc), _addr(X), _stream_ptr(stream)))
@@ -509,10 +511,15 @@ class Context:
 
     def nn_advance(self, net: "Mlp", cur: DeviceState, nxt: DeviceState, n: int, scales,
                    dv_scale: float, dr_scale: float, dt4: float, rho_tol: float, stream=None):
-        sc = NnScales(*[float(v) for v in scales])
+        sc = NnScales(*[float(v) for v in scales[:7]])
         self._check(self.L.sph_nn_advance(self.h, C.byref(net.struct()), C.byref(cur.soa()),
                                           C.byref(nxt.soa()), n, C.byref(sc), dv_scale, dr_scale,
                                           dt4, rho_tol, _stream_ptr(stream)))
+
+    def nn_perturb(self, st: DeviceState, n: int, seed: int, sigma_u: float, sigma_rho: float,
+                   stream=None):
+        self._check(self.L.sph_nn_perturb(self.h, C.byref(st.soa()), n, int(seed) & 0xffffffff,
+                                          sigma_u, sigma_rho, _stream_ptr(stream)))
 
     def nn_judge(self, s: DeviceState, r: DeviceState, b: DeviceState, where_r, where_b, n: int,
                  stream=None) -> np.ndarray:

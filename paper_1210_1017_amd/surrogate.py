@@ -33,17 +33,25 @@ class NnConfig:
     width: int = 128
     vel_scale: float = 1.0        # m/s: velocity features are u / vel_scale
     rho_feat: float = 0.01        # density features are (rho - rho0) / (rho0 rho_feat)
+    radius: float = 1.85          # neighbourhood radius of a row, in h
+    acc_feat: float = 10.0        # m/s^2: the pressure-acceleration features are ap / acc_feat
+    drho_feat: float = 1000.0     # kg/m^3/s: the continuity feature is dr / drho_feat
     acc_scale: float = 1.0        # m/s^2: velocity targets are (du/dt) / acc_scale
     drho_scale: float = 1.0       # kg/m^3/s: density targets are (drho/dt) / drho_scale
     rho_band: float = 0.02        # |rho/rho0 - 1| allowed after an advance (training range)
-    judge_every: int = 8          # advances between two judge checks
+    judge_every: int = 8          # unjudged advances between two judge checks (at most)
+    adaptive: bool = True         # check more often as the judged error grows
     judge_tol: float = 0.01       # max |rho_sur - rho_sph| / rho_sph before fallback
+    keep_judged: bool = True      # continue from the judge's plain result (a periodic correction)
     meta: dict = field(default_factory=dict)
 
     def scales(self, params: dict) -> tuple:
-        """(inv_len, inv_vel, rho_ref, inv_rho) of the input rows."""
-        rho0 = float(params["rho0"])
-        return (1.0 / float(params["h"]), 1.0 / self.vel_scale, rho0, 1.0 / (rho0 * self.rho_feat))
+        """(inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho) of the
+        input rows, as FP32 numbers."""
+        rho0, h = float(params["rho0"]), float(params["h"])
+        v = (1.0 / h, 1.0 / self.vel_scale, rho0, 1.0 / (rho0 * self.rho_feat),
+             (self.radius * h) ** 2, 1.0 / self.acc_feat, 1.0 / self.drho_feat)
+        return tuple(float(np.float32(x)) for x in v)
 
 
 def save(path: str, net: sph.Mlp, cfg: NnConfig):
@@ -87,11 +95,22 @@ def _others(bufs, *used):
 def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
           rows: int = 32768, lr: float = 1e-3, lr_final: float = 1e-4, seed: int = 0,
           width: int = 128, case_fn=cases.obstacle_tank, log=print,
-          time_budget_s: float | None = None):
+          time_budget_s: float | None = None, noise_u: float = 0.02,
+          noise_rho: float = 2.0, wcol=(1.0, 1.0, 1.0, 2.0), rollout_prob: float = 0.5,
+          rollout_max: int = 3, rollout_after: int = 500):
     """Online training: for each of n_traj seeded layouts, run plain SPH for
     steps_per_traj steps; every window_every steps, take the sorted state A,
     build the input rows of `rows` randomly drawn particles, run 4 more plain
     steps to B, and take one Adam step on the targets (B - A) / (4 dt).
+    Every other window first adds noise to A's fluid velocities and densities
+    (sph_nn_perturb; standard deviations drawn per window up to noise_u m/s
+    and noise_rho kg/m^3), so that the network also sees, and learns SPH's
+    response to, states a little off the plain trajectory, as its own
+    advances produce. wcol weights the four output columns in the loss.
+    Rollouts (after rollout_after windows): with probability rollout_prob a
+    window starts from the state left by 1..rollout_max advances of the
+    network being trained (sph_nn_advance) instead of plain steps, so that
+    the targets also cover SPH's response to the network's own errors.
     Returns (net, cfg, history)."""
     import torch
     cfg = NnConfig(width=width)
@@ -99,6 +118,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     hist = {"loss": [], "traj": [], "window": [], "seconds": []}
+    noise_rng = np.random.Generator(np.random.PCG64(seed + 17))
     t0 = time.time()
     total_windows = n_traj * (steps_per_traj // window_every)
     wi = 0
@@ -127,9 +147,21 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
                 nxt = _others(bufs, cur)[0]
                 ctx.step(cur, nxt, n, step)
                 cur, step = nxt, step + 1
+            if (wi >= rollout_after and rollout_max > 0
+                    and noise_rng.uniform() < rollout_prob):
+                span = K_STEPS * ctx.dt()
+                for _ in range(int(noise_rng.integers(1, rollout_max + 1))):
+                    nxt = _others(bufs, cur)[0]
+                    ctx.nn_advance(net, cur, nxt, n, scales, span * cfg.acc_scale,
+                                   span * cfg.drho_scale, span, 1.0)
+                    cur, step = nxt, step + K_STEPS
             # window: sorted copy A, input rows, 4 plain steps to B
             A = _others(bufs, cur)[0]
             ctx.sort(cur, A, n)
+            if wi % 2 == 1 and (noise_u > 0 or noise_rho > 0):
+                # a noise level drawn per window, up to the given maxima
+                lvl = float(noise_rng.uniform(0.0, 1.0))
+                ctx.nn_perturb(A, n, seed * 7919 + wi, lvl * noise_u, lvl * noise_rho)
             n0 = ctx.counts()["n_label"][0]
             r = torch.randint(0, n0, (rows,), generator=gen, device="cuda", dtype=torch.int32)
             ctx.nn_features(A, r, rows, scales, X)
@@ -148,7 +180,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
             frac = wi / max(total_windows - 1, 1)
             lr_t = lr * (lr_final / lr) ** frac
             ctx.mlp_forward(net, X, rows, Y)
-            ctx.mlp_backward(net, X, rows, T, (1.0, 1.0, 1.0, 1.0))
+            ctx.mlp_backward(net, X, rows, T, wcol)
             ctx.mlp_adam(net, lr_t)
             if wi % 50 == 0:
                 loss = float(net.loss.item())
@@ -173,6 +205,8 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
             break
     cfg.rho_band = float(max(0.02, 1.5 * rho_dev_max))
     cfg.meta.update({"trajectories": tr + 1, "windows": wi, "rows": rows,
+                     "noise_u": noise_u, "noise_rho": noise_rho,
+                     "rollout_prob": rollout_prob, "rollout_max": rollout_max,
                      "steps_per_traj": steps_per_traj, "window_every": window_every,
                      "train_seconds": time.time() - t0, "seed": seed,
                      "final_loss": hist["loss"][-1] if hist["loss"] else None})
@@ -184,12 +218,15 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
 def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig | None = None,
         ctx: sph.Context | None = None, judge: bool = True, log=None) -> dict:
     """Advance ``case`` by ``steps`` time steps. With ``net`` (and its cfg),
-    k = 4 steps per surrogate advance; every cfg.judge_every-th advance the
-    same 4 steps also run as plain SPH from the same state and
-    sph_nn_judge compares the two; an error above cfg.judge_tol, a
-    non-finite value or a density outside cfg.rho_band switches to plain SPH
-    for the rest of the run (the judged plain result is kept). Without a net:
-    plain SPH. Returns the final device state, wall time and books."""
+    k = 4 steps per surrogate advance. The first advance and then one after
+    every cfg.judge_every unjudged ones are judged: the same 4 steps also run
+    as plain SPH from the same state and sph_nn_judge compares the two by
+    particle id. With cfg.adaptive the gap shrinks to a half (a quarter) once
+    the judged max density error passes 0.3 (0.6) of cfg.judge_tol. An error
+    above cfg.judge_tol, a non-finite value or a density outside cfg.rho_band
+    switches to plain SPH for the rest of the run. With cfg.keep_judged the
+    loop continues from the judge's plain result. Without a net: plain SPH.
+    Returns the final device state, wall time and books."""
     import torch
     n, p = case.n, case.params
     ctx = ctx or sph.Context(p, n)
@@ -197,7 +234,8 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
     bufs = [sph.DeviceState.empty(n) for _ in range(4)]
     ctx.clear_status()
     torch.cuda.synchronize()
-    books = {"advances": 0, "plain_steps": 0, "judged": 0, "fallback_at": None, "judge": []}
+    books = {"advances": 0, "plain_steps": 0, "judged": 0, "kept_plain": 0, "fallback_at": None,
+             "judge": []}
     t0 = time.perf_counter()
     step = 0
     if net is None:
@@ -214,6 +252,8 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
     where_b = torch.empty(n, dtype=torch.int32, device="cuda")
     fallback = False
     dt = None
+    interval = cfg.judge_every  # advances between judge checks
+    since_judge = interval      # the first advance is judged
 
     def others(*used):
         return _others(bufs, *used)
@@ -231,7 +271,8 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
         ctx.nn_advance(net, cur, S, n, scales, span * cfg.acc_scale, span * cfg.drho_scale, span,
                        cfg.rho_band)
         bad = ctx.status() & (sph.STATUS_NN_RANGE | sph.STATUS_NONFINITE)
-        do_judge = judge and (books["advances"] % cfg.judge_every == 0)
+        do_judge = judge and since_judge >= interval
+        since_judge = 0 if do_judge else since_judge + 1
         if do_judge or bad:
             R, _, dts = _plain_steps(ctx, cur, others(cur, S)[:2], n, step, K_STEPS)
             books["plain_steps"] += K_STEPS
@@ -246,6 +287,13 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
                                        "rel_du": float(np.sqrt(m[3] / max(m[4], 1e-300))),
                                        "rel_dx": float(np.sqrt(m[5] / max(m[6], 1e-300)))})
                 bad = m[0] > cfg.judge_tol
+                if cfg.adaptive:
+                    # judge more often as the error approaches the tolerance
+                    r = m[0] / cfg.judge_tol
+                    interval = (cfg.judge_every if r < 0.3 else
+                                max(1, cfg.judge_every // 2) if r < 0.6 else
+                                max(1, cfg.judge_every // 4))
+            books["advances"] += 1
             if bad:
                 fallback = True
                 books["fallback_at"] = step
@@ -253,8 +301,13 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
                     log(f"[surrogate] fallback to plain SPH at step {step}")
                 cur, step = R, step + K_STEPS
                 continue
+            if cfg.keep_judged:
+                books["kept_plain"] += 1
+                cur, step = R, step + K_STEPS
+                continue
+        else:
+            books["advances"] += 1
         cur, step = S, step + K_STEPS
-        books["advances"] += 1
     torch.cuda.synchronize()
     return {"state": cur, "seconds": time.perf_counter() - t0, "books": books, "ctx": ctx}
 

@@ -28,11 +28,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GRAD_TOL = 5e-3
-SCALES = (np.float32(1.0), np.float32(2.0), np.float32(1000.0), np.float32(0.1))
-
-
 def _scales(p):
-    return (np.float32(1.0 / p["h"]),) + SCALES[1:]
+    """(inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho)"""
+    return (np.float32(1.0 / p["h"]), np.float32(2.0), np.float32(1000.0), np.float32(0.1),
+            np.float32((1.85 * p["h"]) ** 2), np.float32(0.1), np.float32(1e-3))
 
 
 def _bf16_dev(a):
@@ -50,6 +49,19 @@ def _sorted_gpu(case):
     out = sph.DeviceState.empty(n)
     ctx.sort(cur, out, n)
     return ctx, cur, out
+
+
+def _compare_rows(got, want, name):
+    """Every slot feature and the own block's plain values bit-exact; the four
+    pair-sum features (FP32 sums on the GPU, FP64 in the oracle, both rounded
+    to bfloat16) within one bfloat16 step."""
+    plain = np.ones(sph.NN_IN, dtype=bool)
+    plain[om.SUM_COLS] = False
+    bad = np.nonzero(np.any(got[:, plain] != want[:, plain], axis=1))[0]
+    assert bad.size == 0, (name, bad[:5])
+    g, w = got[:, om.SUM_COLS], want[:, om.SUM_COLS]
+    assert np.all(np.abs(g - w) <= 2.0 ** -7 * np.abs(w) + 1e-3), (name, np.abs(g - w).max())
+    assert np.mean(g != w) < 0.02, name
 
 
 FEATURE_CASES = {
@@ -74,8 +86,7 @@ def test_features_bit_exact(name):
     srt = oracle.sort_state(p, case.state)
     want = om.features(p, srt, np.arange(n0), sc)
     got = _f32(X[:n0])
-    bad = np.nonzero(np.any(got != want, axis=1))[0]
-    assert bad.size == 0, (name, bad[:5], n0)
+    _compare_rows(got, want, name)
     # a row subset with repeats and rows outside the label-0 prefix
     rng = np.random.default_rng(1)
     rows = rng.integers(0, n0, 300).astype(np.int32)
@@ -86,7 +97,7 @@ def test_features_bit_exact(name):
     ctx.nn_features(out, rt, len(rows), sc, Xs)
     gs = _f32(Xs)
     inside = (rows >= 0) & (rows < n0)
-    assert np.array_equal(gs[inside], want[rows[inside]])
+    _compare_rows(gs[inside], want[rows[inside]], name + " subset")
     assert not gs[~inside].any()
 
 
