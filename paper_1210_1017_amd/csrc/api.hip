@@ -62,7 +62,7 @@ void free_events(sph_ctx *c) {
 
 void free_all(sph_ctx *c) {
     free_events(c);
-    void *vptrs[] = {c->p64, c->drate, c->tot_part, c->nn_part, c->nn_out, c->nn_x};
+    void *vptrs[] = {c->p64, c->drate, c->tot_part, c->nn_part, c->nn_out, c->nn_x, c->nn_y};
     for (void *p : vptrs)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
@@ -861,18 +861,22 @@ int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *ne
         return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
     hipStream_t s = (hipStream_t)stream;
     if (c->nn_x_rows < c->capacity) {
-        // input rows of every particle: allocated once per context, on first use
+        // rows and outputs of every particle: allocated once per context, on first use
         if (c->nn_x) (void)hipFree(c->nn_x);
+        if (c->nn_y) (void)hipFree(c->nn_y);
         c->nn_x = nullptr;
+        c->nn_y = nullptr;
         c->nn_x_rows = 0;
         hipError_t e = hipMalloc(&c->nn_x, (size_t)c->capacity * SPH_NN_IN * 2);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->nn_y, (size_t)c->capacity * SPH_NN_OUT * 4);
         if (e != hipSuccess) return hip_fail(c, e, "surrogate row buffer");
         c->nn_x_rows = c->capacity;
     }
     if ((r = do_sort(c, cur, next, n, s))) return r;
     hipError_t e = launch_nn_features(c, next->type, nullptr, n, *scales, c->nn_x, 1, s);
     if (e == hipSuccess)
-        e = launch_nn_mlp_apply(c, *m, *next, c->nn_x, n, dv_scale, dr_scale, dt4, rho_tol, s);
+        e = launch_nn_mlp_apply(c, *m, *next, c->nn_x, c->nn_y, n, dv_scale, dr_scale, dt4,
+                                rho_tol, s);
     if (e != hipSuccess) return hip_fail(c, e, "surrogate advance");
     c->have_dt = false;
     return SPH_OK;

@@ -700,26 +700,27 @@ hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
 }
 
 // ============================================ network + application kernel
-// Persistent: one workgroup (4 waves) per CU walks the tiles of 64
+// Persistent: one workgroup (8 waves) per CU walks the tiles of 64
 // consecutive rows of a chunk-major X (rows of sorted particles
-// base .. base + 63). Wave w owns output columns [32w, 32w+32) of the three
+// base .. base + 63). Wave w owns output columns [16w, 16w+16) of the three
 // hidden layers and keeps its weight fragments (the B operands of
 // v_mfma_f32_16x16x32_bf16: 16 bytes of a weight row per lane, k step and
 // 16-column block) in registers for the whole kernel, so the layers read
-// only LDS; each A fragment read from LDS feeds two MFMAs. Per tile:
+// only LDS. Per tile:
 //  1. the tile, prefetched into registers during the previous tile, is
 //     stored into LDS [64][kXS] (1 KB contiguous per chunk and tile);
 //  2. layer 1 (544 -> 128) for all 64 rows of the wave's columns; bias +
 //     SiLU to bfloat16 into LDS (ping-pong tiles inside the input tile's
 //     space), layers 2 and 3 (128 -> 128) likewise;
 //  3. layer 4 (128 -> 4, output columns padded to 16): one row block per
-//     wave; the 64 x 4 result goes through LDS to one thread per particle,
-//     which applies it (nn_apply_one).
+//     wave w < 4, written to Y (FP32 [nrows][4]); k_nn_apply applies Y to the
+//     state afterwards (its loads and stores then overlap freely instead of
+//     holding up the tile loop).
 constexpr int kFW = 128;          // hidden width of this kernel
 constexpr int kXS = kNnIn + 8;    // padded row of the input tile (bfloat16)
 constexpr int kHS = kFW + 8;      // padded row of a hidden activation tile
-constexpr int kMlpWaves = 4;
-constexpr int kMlpCols = kFW / kMlpWaves;   // 32 output columns per wave
+constexpr int kMlpWaves = 8;
+constexpr int kMlpCols = kFW / kMlpWaves;   // 16 output columns per wave
 constexpr int kMlpCB = kMlpCols / 16;       // 16-column MFMA blocks per wave
 constexpr int kMlpThreads = 64 * kMlpWaves;
 constexpr int kChunks = kNnIn / 8;                                  // 16-byte chunks per row
@@ -792,15 +793,12 @@ __device__ __forceinline__ void load_frags(const bf16 *__restrict__ W, int ncols
     }
 }
 
-__global__ __launch_bounds__(kMlpThreads, 1) void k_nn_mlp_apply(KParams kp, FusedNet net,
-                                                                  const bf16 *__restrict__ X,
-                                                                  uint32_t nrows, sph_soa st,
-                                                                  NnApply ap,
-                                                                  DevInfo *__restrict__ info) {
+__global__ __launch_bounds__(kMlpThreads, 1) void k_nn_mlp(FusedNet net,
+                                                            const bf16 *__restrict__ X,
+                                                            uint32_t nrows,
+                                                            float *__restrict__ Y) {
     __shared__ __attribute__((aligned(16))) bf16 sX[64 * kXS];
-    __shared__ float sY[64][4];
     const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t n0 = info->n_label[0];
     const uint32_t ntiles = (nrows + 63) / 64;
     const int col0 = (int)w * kMlpCols;
     // weight fragments and biases of this wave, for the whole kernel
@@ -858,7 +856,7 @@ __global__ __launch_bounds__(kMlpThreads, 1) void k_nn_mlp_apply(KParams kp, Fus
         mlp_layer<kFW / 32>(h1, kHS, wb2, acc);
         mlp_store_act(acc, bias2, col0, h0);  // h0's last reads (layer 2) ended at the barrier above
         lds_barrier();
-        {
+        if (w < 4) {
             const int row = lane & 15, kb = (lane >> 4) * 8;
             f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -870,35 +868,32 @@ __global__ __launch_bounds__(kMlpThreads, 1) void k_nn_mlp_apply(KParams kp, Fus
             const int col = lane & 15, rb = (lane >> 4) * 4;
             if (col < SPH_NN_OUT) {
 #pragma unroll
-                for (int r = 0; r < 4; r++) sY[w * 16 + rb + r][col] = o[r] + bias3;
+                for (int r = 0; r < 4; r++) {
+                    const uint32_t k = base + w * 16 + rb + r;
+                    if (k < nrows) Y[4 * (size_t)k + col] = o[r] + bias3;
+                }
             }
         }
-        lds_barrier();
-        if (threadIdx.x < 64) {
-            const uint32_t k = base + threadIdx.x;
-            if (k < n0 && k < nrows)
-                nn_apply_one(kp, st, k, sY[threadIdx.x][0], sY[threadIdx.x][1],
-                             sY[threadIdx.x][2], sY[threadIdx.x][3], ap, &info->flags);
-        }
-        lds_barrier();  // sX and sY are rewritten for the next tile
+        lds_barrier();  // sX is rewritten for the next tile
     }
 }
 
 hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
-                               uint32_t nrows, float dv_scale, float dr_scale, float dt4,
-                               float rho_tol, hipStream_t stream) {
+                               float *Y, uint32_t nrows, float dv_scale, float dr_scale,
+                               float dt4, float rho_tol, hipStream_t stream) {
     if (nrows == 0) return hipSuccess;
     const FusedNet net{(const bf16 *)m.wb[0], (const bf16 *)m.wb[1], (const bf16 *)m.wb[2],
                        (const bf16 *)m.wb[3], m.b[0], m.b[1], m.b[2], m.b[3]};
-    const NnApply ap{dv_scale, dr_scale, dt4, rho_tol};
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const uint32_t ntiles = (nrows + 63) / 64;
     const uint32_t grid = ntiles < (uint32_t)cus ? ntiles : (uint32_t)cus;
-    hipLaunchKernelGGL(k_nn_mlp_apply, dim3(grid), dim3(kMlpThreads), 0, stream, c->kp, net,
-                       (const bf16 *)X, nrows, st, ap, c->info);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_nn_mlp, dim3(grid), dim3(kMlpThreads), 0, stream, net, (const bf16 *)X,
+                       nrows, Y);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_nn_apply(c, st, Y, nrows, dv_scale, dr_scale, dt4, rho_tol, stream);
 }
 
 }  // namespace sph

@@ -81,6 +81,7 @@ struct sph_ctx {
     double *nn_part = nullptr;    // 8 doubles per surrogate-judge block
     double *nn_out = nullptr;     // 8 doubles: judge result
     void *nn_x = nullptr;         // surrogate input rows of sph_nn_advance (lazily allocated)
+    float *nn_y = nullptr;        // its network outputs, 4 per row
     size_t nn_x_rows = 0;
     uint32_t tot_blocks = 0;
     int last_path = 0;            // 0 plain, 1 cell, 2 FP64: which state the tables describe
@@ -175,8 +176,8 @@ hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
                            const int32_t *where_r, const int32_t *where_b, uint32_t n,
                            double *part, double *out, hipStream_t s);
 hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
-                               uint32_t nrows, float dv_scale, float dr_scale, float dt4,
-                               float rho_tol, hipStream_t stream);
+                               float *Y, uint32_t nrows, float dv_scale, float dr_scale,
+                               float dt4, float rho_tol, hipStream_t stream);
 
 // update.hip
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
