@@ -39,7 +39,7 @@ class _Params(C.Structure):
                 ("gamma", C.c_double), ("c0", C.c_double), ("alpha", C.c_double),
                 ("eta_over_h", C.c_double), ("cfl", C.c_double), ("mass", C.c_double),
                 ("g", C.c_double * 3), ("origin", C.c_double * 3), ("ncell", C.c_int32 * 3),
-                ("euler_every", C.c_int32), ("slab_mode", C.c_int32), ("pad_", C.c_int32),
+                ("euler_every", C.c_int32), ("slab_mode", C.c_int32), ("options", C.c_int32),
                 ("slab_xlo", C.c_double), ("slab_xhi", C.c_double)]
 
 
@@ -66,6 +66,9 @@ def lib():
         L.orc_kernel_w.restype = C.c_double
         L.orc_kernel_f.argtypes = [C.c_double, C.c_double]
         L.orc_kernel_f.restype = C.c_double
+        for f in ("orc_cubic_w", "orc_cubic_f"):
+            getattr(L, f).argtypes = [C.c_double, C.c_double]
+            getattr(L, f).restype = C.c_double
         L.orc_eos.argtypes = [pp, C.c_double, d, d]
         L.orc_interact.argtypes = [pp, C.c_int64, d, d, d, d, d, d, d, u8, u32, u32, u32,
                                    C.c_int64, C.c_int64, i64, d, d, d, d, d, d, d, i64]
@@ -109,6 +112,7 @@ def make_params(p: dict) -> _Params:
         s.ncell[a] = int(p["ncell"][a])
     s.euler_every = int(p["euler_every"])
     s.slab_mode = int(p.get("slab_mode", 0))
+    s.options = int(p.get("options", 0))
     s.slab_xlo = float(p.get("slab_xlo", 0.0))
     s.slab_xhi = float(p.get("slab_xhi", 0.0))
     return s
@@ -211,6 +215,16 @@ def kernel_w(r: float, h: float) -> float:
 
 def kernel_f(r: float, h: float) -> float:
     return float(lib().orc_kernel_f(r, h))
+
+
+def cubic_w(r: float, h: float) -> float:
+    """Cubic spline kernel W(r) of Sec. 2.2 (3-D, support 2h)."""
+    return float(lib().orc_cubic_w(r, h))
+
+
+def cubic_f(r: float, h: float) -> float:
+    """F(r) of the cubic spline: grad_i W_ij = F(r) (r_i - r_j)."""
+    return float(lib().orc_cubic_f(r, h))
 
 
 def eos(p: dict, rho: float):

@@ -120,17 +120,46 @@ def features(p: dict, srt: dict, sel, scales) -> np.ndarray:
     return bf16_round(X)
 
 
-def targets(a: dict, b_by_id: dict, rows, inv_dv: float, inv_dr: float) -> np.ndarray:
+def rates(p: dict, srt: dict, sel, scales) -> np.ndarray:
+    """Pair-sum rates of the rows of ``sel`` (FP64, shape (len(sel), 4)): for
+    a fluid particle the pressure acceleration of Sec. 2.2 over the row's
+    neighbours plus gravity, (ap + g), for other particles 0; and the
+    continuity rate dr over the same neighbours. Ghost rows are zero. These
+    are the part of the four-step change that a residual network does not
+    predict."""
+    from . import nn_rows, nn_sums
+    s = srt["state"]
+    sel = np.asarray(sel, dtype=np.int64)
+    r2f = np.float32(scales[4])
+    nbr, _ = nn_rows(p, srt, sel, r2f, SLOTS)
+    sums = nn_sums(p, srt, sel, nbr)
+    typ = s["type"][sel]
+    out = np.zeros((sel.shape[0], 4))
+    fl = typ == FLUID
+    out[fl, :3] = sums[fl, :3] + np.asarray(p["g"], dtype=np.float64)
+    out[typ != GHOST, 3] = sums[typ != GHOST, 3]
+    return out
+
+
+def targets(a: dict, b_by_id: dict, rows, inv_dv: float, inv_dr: float,
+            rts=None, span: float = 0.0) -> np.ndarray:
     """Training targets for particles ``rows`` of state ``a``: the FP32 changes
-    (u_b - u_a) inv_dv (3 components) and (rho_b - rho_a) inv_dr, where b is
-    the same particle (same id) in the later state. ``b_by_id`` holds that
-    state's FP32 arrays indexed by id."""
+    ((u_b - u_a) - span rts[:, :3]) inv_dv (3 components) and
+    ((rho_b - rho_a) - span rts[:, 3]) inv_dr, where b is the same particle
+    (same id) in the later state, every operation rounded to FP32 in that
+    order. ``b_by_id`` holds that state's FP32 arrays indexed by id; ``rts``
+    (FP32 rates, one row per entry of ``rows``) defaults to zeros."""
     rows = np.asarray(rows, dtype=np.int64)
     ids = a["id"][rows]
+    if rts is None:
+        rts = np.zeros((rows.shape[0], 4), dtype=np.float32)
+    rts = np.asarray(rts, dtype=np.float32)
+    sp = np.float32(span)
     out = []
-    for k, sc in (("vx", inv_dv), ("vy", inv_dv), ("vz", inv_dv), ("rho", inv_dr)):
-        out.append((b_by_id[k][ids].astype(np.float32) - a[k][rows].astype(np.float32))
-                   * np.float32(sc))
+    for c, (k, sc) in enumerate((("vx", inv_dv), ("vy", inv_dv), ("vz", inv_dv),
+                                 ("rho", inv_dr))):
+        d = b_by_id[k][ids].astype(np.float32) - a[k][rows].astype(np.float32)
+        out.append((d - sp * rts[:, c]) * np.float32(sc))
     return np.stack(out, axis=1)
 
 

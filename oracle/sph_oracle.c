@@ -37,9 +37,14 @@ typedef struct {
     int32_t ncell[3];
     int32_t euler_every;
     int32_t slab_mode;
-    int32_t pad_;
+    int32_t options;   /* OPT_* bits below */
     double slab_xlo, slab_xhi;
 } orc_params;
+
+/* Variants of the plain step: the cubic spline kernel of Sec. 2.2 in place of
+ * Wendland C2, and a density floor rho >= rho0 for boundary particles after
+ * each update (a common practice with dynamic boundaries, not in the paper). */
+enum { OPT_CUBIC = 1, OPT_RHO_FLOOR = 2 };
 
 int orc_abi_version(void) { return 1; }
 
@@ -217,6 +222,39 @@ double orc_kernel_f(double r, double h)
     return -5.0 * aD * t * t * t / (h * h);
 }
 
+/* Cubic spline kernel in 3-D (the kernel of Sec. 2.2, support 2h), in the
+ * textbook form with q = r/h and aD = 1/(pi h^3):
+ *   W = aD (1 - 3q^2/2 + 3q^3/4)   for 0 <= q < 1,
+ *   W = aD (2 - q)^3 / 4           for 1 <= q < 2,   0 beyond. */
+double orc_cubic_w(double r, double h)
+{
+    const double q = r / h;
+    const double aD = 1.0 / (M_PI * h * h * h);
+    if (q >= 2.0) return 0.0;
+    if (q < 1.0) return aD * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+    const double t = 2.0 - q;
+    return aD * 0.25 * t * t * t;
+}
+
+/* grad_i W_ij = F(r) (r_i - r_j) for the cubic spline: dW/dq = aD (-3q +
+ * 9q^2/4) below q = 1 and -3 aD (2 - q)^2 / 4 above, and F = (dW/dq)/(h r)
+ * = (dW/dq) / (h^2 q). */
+double orc_cubic_f(double r, double h)
+{
+    const double q = r / h;
+    const double aD = 1.0 / (M_PI * h * h * h);
+    if (q >= 2.0) return 0.0;
+    if (q < 1.0) return aD * (-3.0 + 2.25 * q) / (h * h);
+    const double t = 2.0 - q;
+    return -0.75 * aD * t * t / (q * h * h);
+}
+
+/* F of the kernel that the parameters select. */
+static double kernel_f(const orc_params *p, double r)
+{
+    return (p->options & OPT_CUBIC) ? orc_cubic_f(r, p->h) : orc_kernel_f(r, p->h);
+}
+
 /* Tait equation of state, Sec. 2.2: p = B[(rho/rho0)^gamma - 1],
  * B = c0^2 rho0 / gamma; sound speed c = sqrt(dp/drho) =
  * c0 (rho/rho0)^((gamma-1)/2). */
@@ -248,7 +286,7 @@ static void pair_terms(const orc_params *p, double rx, double ry, double rz,
 {
     const double h = p->h, m = p->mass;
     const double r2 = rx * rx + ry * ry + rz * rz;
-    const double F = orc_kernel_f(sqrt(r2), h);
+    const double F = kernel_f(p, sqrt(r2));
     const double vr = ux * rx + uy * ry + uz * rz;
     const double eta = p->eta_over_h * h;
     const double mu = h * vr / (r2 + eta * eta);
@@ -499,6 +537,8 @@ double orc_dt(const orc_params *p, int64_t n0, const uint8_t *type, const double
  *   always    r' = r + dt v + dt^2 a / 2,  then (v_prev, rho_prev) <- (v, rho).
  * Fluid updates r, v, rho. Boundary particles update rho only (position and
  * velocity fixed, Sec. 2.3). Ghosts are not updated. Applies to [0, n0).
+ * With OPT_RHO_FLOOR a boundary particle's new density is raised to rho0 when
+ * it falls below.
  */
 void orc_verlet(const orc_params *p, int64_t n0, int64_t step, double dt,
                 const uint8_t *type, double *x, double *y, double *z, double *vx,
@@ -509,7 +549,9 @@ void orc_verlet(const orc_params *p, int64_t n0, int64_t step, double dt,
     const int euler = p->euler_every > 0 ? (step % p->euler_every == 0) : (step == 0);
     for (int64_t i = 0; i < n0; i++) {
         if (type[i] == T_GHOST) continue;
-        const double r_new = euler ? rho[i] + dt * drho[i] : rhop[i] + 2.0 * dt * drho[i];
+        double r_new = euler ? rho[i] + dt * drho[i] : rhop[i] + 2.0 * dt * drho[i];
+        if ((p->options & OPT_RHO_FLOOR) && type[i] == T_BOUNDARY && r_new < p->rho0)
+            r_new = p->rho0;
         rhop[i] = rho[i];
         rho[i] = r_new;
         if (type[i] != T_FLUID) continue;
@@ -616,7 +658,9 @@ void orc_nn_rows(const orc_params *p, const double *x, const double *y, const do
  *   ap_i = - sum_j m (p_i/rho_i^2 + p_j/rho_j^2) grad_i W_ij
  * and the continuity rate
  *   dr_i = sum_j m (v_i - v_j) . grad_i W_ij,
- * grad_i W_ij = F(r_ij) (r_i - r_j). out[4 s ..] = (ap_x, ap_y, ap_z, dr).
+ * grad_i W_ij = F(r_ij) (r_i - r_j) with the Wendland kernel whatever the
+ * options select (the surrogate's inputs are defined with it).
+ * out[4 s ..] = (ap_x, ap_y, ap_z, dr).
  */
 void orc_nn_sums(const orc_params *p, const double *x, const double *y, const double *z,
                  const double *vx, const double *vy, const double *vz, const double *rho,

@@ -206,6 +206,44 @@ def test_nn_sums_continuity_equals_interaction(orc):
     assert np.abs(acc["drho"]).max() > 0
 
 
+def test_rates_are_interaction_rates_for_a_static_cluster(orc, mlp):
+    """A static fluid cluster with a boundary particle and a ghost, every pair
+    inside the feature radius: the residual base rates of a fluid particle are
+    the interaction's acceleration (gravity included, no viscosity at rest)
+    and its drho/dt; a boundary particle gets no velocity rate and its
+    continuity rate; a ghost gets zeros."""
+    rng = np.random.default_rng(9)
+    p = cases.base_params(0.02)
+    h = p["h"]
+    pos = 0.1 + rng.uniform(-0.4 * h, 0.4 * h, size=(7, 3))
+    typ = np.array([0, 0, 0, 0, 0, 1, 2])
+    st = cases._make_state(pos, typ, 1000.0 * (1 + rng.uniform(-0.01, 0.01, 7)))
+    cases.set_grid(p, (0.0, 0.0, 0.0), (0.2, 0.2, 0.2))
+    srt = orc.sort_state(p, st)
+    sc = (1.0, 1.0, 1000.0, 1.0, _r2f(p), 1.0, 1.0)
+    n0 = int(srt["counts"][0])
+    R = mlp.rates(p, srt, np.arange(n0), sc)
+    acc = orc.interact(p, srt)
+    t = srt["state"]["type"][:n0]
+    fl, bd, gh = t == cases.FLUID, t == cases.BOUNDARY, t == cases.GHOST
+    a = np.stack([acc["ax"], acc["ay"], acc["az"]], 1)
+    assert np.allclose(R[fl, :3], a[fl], rtol=1e-12, atol=1e-12 * np.abs(a).max())
+    assert np.all(R[bd, :3] == 0.0) and np.all(R[gh] == 0.0)
+    assert np.allclose(R[bd, 3], acc["drho"][bd], rtol=1e-12, atol=1e-9)
+    assert np.abs(a[fl] - np.array(p["g"])).max() > 1.0  # pressure acts
+
+
+def test_targets_with_rates(mlp):
+    """Targets minus span times the rates, each operation rounded to FP32."""
+    a = {"vx": np.float32([1, 2]), "vy": np.float32([0, 0]), "vz": np.float32([0, 1]),
+         "rho": np.float32([1000, 1001]), "id": np.int32([1, 0])}
+    b = {"vx": np.float32([2.5, 1.0]), "vy": np.float32([0, 0]), "vz": np.float32([1, 0]),
+         "rho": np.float32([1003, 1000])}
+    rts = np.float32([[1, 2, 3, 4], [0.5, 0, 0, -8]])
+    T = mlp.targets(a, b, [0, 1], 2.0, 0.5, rts=rts, span=0.25)
+    assert T.tolist() == [[-0.5, -1.0, -1.5, -0.5], [0.75, 0.0, 0.0, 2.0]]
+
+
 def test_targets_definition(mlp):
     a = {"vx": np.float32([1, 2]), "vy": np.float32([0, 0]), "vz": np.float32([0, 1]),
          "rho": np.float32([1000, 1001]), "id": np.int32([1, 0])}

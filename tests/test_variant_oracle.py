@@ -1,0 +1,143 @@
+"""Pins of the oracle's kernel and integrator variants (no GPU).
+
+The cubic spline kernel of Sec. 2.2 (support 2h) is checked against the
+properties the section lists for a smoothing function (unit integral, compact
+support, monotone decrease) and against its textbook values; its gradient
+factor against a numerical derivative of W and against the divergence
+identity that every normalised kernel satisfies; the interaction with it
+against a finite-difference gradient of W and against momentum conservation.
+The boundary density floor against its definition on hand-made states.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from paper_1210_1017_amd import cases
+
+
+def _cubic(p):
+    q = dict(p)
+    q["options"] = 1
+    return q
+
+
+@pytest.mark.parametrize("h", [0.026, 1.3, 0.00169])
+def test_cubic_unit_integral_support_monotone(orc, h):
+    # piecewise quadrature (the kernel has a kink in its third derivative at q = 1)
+    f = lambda r: 4 * math.pi * r * r * orc.cubic_w(r, h)
+    val = quad(f, 0, h, epsabs=0, epsrel=1e-13)[0] + quad(f, h, 2 * h, epsabs=0, epsrel=1e-13)[0]
+    assert abs(val - 1.0) <= 1e-10
+    assert orc.cubic_w(2 * h, h) == 0.0 and orc.cubic_f(2 * h, h) == 0.0
+    assert orc.cubic_w(3 * h, h) == 0.0
+    w = np.array([orc.cubic_w(r, h) for r in np.linspace(0, 2 * h, 401)])
+    assert np.all(np.diff(w) < 0)
+
+
+def test_cubic_textbook_values(orc):
+    """The 3-D cubic spline is 1/(pi h^3) at the centre, 1/(4 pi h^3) at q = 1
+    and 1/(32 pi h^3) at q = 3/2 (from (2 - q)^3 / 4 = 1/32)."""
+    h = 0.7
+    k = 1.0 / (math.pi * h ** 3)
+    assert abs(orc.cubic_w(0.0, h) - k) <= 1e-15 * k
+    assert abs(orc.cubic_w(h, h) - k / 4) <= 1e-15 * k
+    assert abs(orc.cubic_w(1.5 * h, h) - k / 32) <= 1e-15 * k
+    # the inner polynomial 1 - 3q^2/2 + 3q^3/4 at q = 1/2: 1 - 3/8 + 3/32 = 23/32
+    assert abs(orc.cubic_w(0.5 * h, h) - 23 * k / 32) <= 1e-15 * k
+
+
+def test_cubic_gradient_is_derivative(orc):
+    h = 0.026
+    qs = np.concatenate([np.linspace(0.05, 1.95, 39), [0.999, 1.001]])
+    for q in qs:
+        r = q * h
+        eps = 1e-7 * h
+        dw = (orc.cubic_w(r + eps, h) - orc.cubic_w(r - eps, h)) / (2 * eps)
+        assert abs(orc.cubic_f(r, h) * r - dw) <= 1e-6 * abs(dw) + 1e-9, q
+
+
+@pytest.mark.parametrize("which", ["cubic", "wendland"])
+def test_divergence_identity(orc, which):
+    """For a kernel with unit integral, int grad W . r dV = -3 (integration by
+    parts of r . grad W), i.e. 4 pi int_0^2h F(r) r^4 dr = -3: the SPH
+    estimate of div(r) = 3 is exact in the continuum limit."""
+    h = 0.026
+    F = orc.cubic_f if which == "cubic" else orc.kernel_f
+    g = lambda r: 4 * math.pi * F(r, h) * r ** 4
+    val = quad(g, 0, h, epsabs=0, epsrel=1e-13)[0] + quad(g, h, 2 * h, epsabs=0, epsrel=1e-13)[0]
+    assert abs(val + 3.0) <= 1e-10
+
+
+def test_cubic_lattice_sum_near_one(orc):
+    """On the workload's lattice (h = 1.3 dp) the particle sum of W dp^3 is a
+    quadrature of the unit integral: within 2 % of 1."""
+    hq = 1.3
+    s = 0.0
+    for i in range(-3, 4):
+        for j in range(-3, 4):
+            for k in range(-3, 4):
+                s += orc.cubic_w(math.sqrt(i * i + j * j + k * k), hq)
+    assert abs(s - 1.0) <= 0.02
+
+
+def _pair_state(d, rho):
+    return cases._make_state(np.array([[0.0, 0, 0], [d, 0, 0]]), np.zeros(2),
+                             np.array(rho, dtype=float), np.zeros((2, 3)))
+
+
+@pytest.mark.parametrize("q", [0.6, 1.0 / 1.3, 1.4, 1.9])
+def test_cubic_pair_force_matches_numerical_gradient(orc, q):
+    """Two fluid particles at rest with rho != rho0 (pressure, no viscosity):
+    a_0 = -m (P_0 + P_1) grad_0 W_01, with grad W from a central difference of
+    the oracle's W in x (not its F)."""
+    p = _cubic(cases.base_params(0.02))
+    cases.set_grid(p, (-0.1, -0.1, -0.1), (0.1, 0.1, 0.1))
+    p["g"] = (0.0, 0.0, 0.0)
+    h = p["h"]
+    d = float(np.float32(q * h))
+    rho = [1003.0, 1001.0]
+    out = orc.interact(p, orc.sort_state(p, _pair_state(d, rho)))
+    P = [orc.eos(p, r)[0] / (r * r) for r in rho]
+    eps = 1e-7 * h
+    # W as a function of x_0 with r = |x_0 - x_1|, x_1 = d: dW/dx_0 at x_0 = 0
+    gx = (orc.cubic_w(abs(eps - d), h) - orc.cubic_w(abs(-eps - d), h)) / (2 * eps)
+    want = -p["mass"] * (P[0] + P[1]) * gx
+    i0 = int(np.argmin(orc.sort_state(p, _pair_state(d, rho))["state"]["x"]))
+    got = out["ax"][i0]
+    assert abs(got - want) <= 1e-6 * abs(want), (got, want)
+    assert got < 0.0  # compressed pair pushes apart: particle 0 (left) moves left
+    assert out["ay"][i0] == 0.0 and out["az"][i0] == 0.0
+
+
+def test_cubic_zero_net_force_and_differs_from_wendland(orc):
+    case = cases.periodic_block(9, 0.02, seed=3)
+    p = _cubic(case.params)
+    out = orc.interact_brute(p, case.state, box=p["box"])
+    a = np.stack([out["ax"], out["ay"], out["az"]], 1) - np.array(p["g"])
+    net = p["mass"] * a.sum(0)
+    assert np.all(np.abs(net) <= 1e-12 * p["mass"] * np.abs(a).sum())
+    w = orc.interact_brute(case.params, case.state, box=p["box"])
+    assert np.array_equal(out["npair"], w["npair"])  # same support 2h
+    assert not np.allclose(out["ax"], w["ax"])
+
+
+def test_boundary_density_floor(orc):
+    """With the floor, a boundary particle whose updated density falls below
+    rho0 gets rho0; fluid particles and boundary densities above rho0 are
+    untouched; without it the boundary density falls below rho0."""
+    p = cases.base_params(0.02)
+    st = orc.to_f64(cases._make_state(
+        np.array([[0.0, 0, 0], [1, 1, 1], [2, 2, 2], [3, 3, 3]]),
+        np.array([1, 1, 0, 2]), np.array([1000.5, 1002.0, 999.0, 990.0]), np.zeros((4, 3))))
+    acc = dict(ax=np.zeros(4), ay=np.zeros(4), az=np.zeros(4), drho=np.full(4, -1000.0))
+    dtv = 1e-3  # drho dt = -1 kg/m^3 (Euler at step 0)
+    plain = orc.verlet(p, st, 4, 0, dtv, acc)
+    pf = dict(p)
+    pf["options"] = 2
+    fl = orc.verlet(pf, st, 4, 0, dtv, acc)
+    assert plain["rho"][0] == pytest.approx(999.5) and fl["rho"][0] == 1000.0
+    assert plain["rho"][1] == fl["rho"][1] == pytest.approx(1001.0)
+    assert plain["rho"][2] == fl["rho"][2] == pytest.approx(998.0)  # fluid: no floor
+    assert plain["rho"][3] == fl["rho"][3] == 990.0                 # ghost: untouched
+    assert fl["rhop"][0] == 1000.5  # the previous value rotates as usual
