@@ -319,8 +319,12 @@ def main() -> int:
             "judge_max_rel_rho": max(judged) if judged else None,
             "judged_advances": len(judged), "advances": rep["surrogate_books"]["advances"],
             "fallback_at": rep["surrogate_books"]["fallback_at"],
+            "residual": bool(rep["config"].get("residual", False)),
             "final_vs_plain": rep["final_vs_plain"],
             "persistence_final_vs_plain": rep["persistence_final_vs_plain"]}
+        if "rates_only_final_vs_plain" in rep:
+            out["surrogate"]["rates_only_final_vs_plain"] = rep["rates_only_final_vs_plain"]
+            out["surrogate"]["rates_only_fallback_at"] = rep["rates_only_books"]["fallback_at"]
     if args.cpu_seconds > 0:
         print(f"[bench] CPU oracle baseline: ~{args.cpu_seconds:.0f} s", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)

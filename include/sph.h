@@ -61,9 +61,9 @@ enum {
     SPH_S_EXCLUDED = 1u << 3,     /* some particles lie outside the cell grid (label 3)   */
     SPH_S_NN_RANGE = 1u << 4,     /* surrogate: a result was non-finite or its density
                                      left the allowed band (sph_nn_apply, sph_nn_advance) */
-    SPH_S_NN_LIST = 1u << 5       /* surrogate: a particle had more than 128 neighbours in
-                                     support; its row used the nearest 64 of the first
-                                     128 found                                             */
+    SPH_S_NN_LIST = 1u << 5       /* surrogate: a row found more than 64 neighbours within
+                                     its radius; its slots and sums kept the first 64 in
+                                     sorted-index order (informational)                    */
 };
 
 /* Run parameters. */
@@ -84,11 +84,27 @@ typedef struct sph_params {
     int32_t slab_mode;  /* 1: sub-domain [slab_xlo, slab_xhi) with migration
                            labels; the grid must then run from slab_xlo - 2h
                            and hold (slab_xhi - slab_xlo)/2h + 2 x-layers       */
-    int32_t reserved_;  /* must be 0                                            */
+    int32_t options;    /* SPH_O_* bits: variants of the plain FP32 step (0 for
+                           the Wendland kernel and no density floor)          */
     double slab_xlo, slab_xhi;
     uint32_t capacity;  /* maximum particle count of any call, < 2^28           */
     uint32_t features;  /* SPH_F_* bits: extra scratch for the variant paths    */
 } sph_params;
+
+/* Option bits of sph_params.options. They change what sph_interact,
+ * sph_update and sph_step compute; the cell, FP64 and surrogate entry points
+ * keep the Wendland kernel and reject a context created with options != 0
+ * (SPH_E_INVALID_ARG).
+ *   SPH_O_CUBIC      the cubic spline kernel of Sec. 2.2 (support 2h):
+ *                    W = aD (1 - 3q^2/2 + 3q^3/4) for q < 1, aD (2 - q)^3 / 4
+ *                    for 1 <= q < 2, aD = 1/(pi h^3), q = r/h;
+ *   SPH_O_RHO_FLOOR  a boundary particle's density is raised to rho0 after
+ *                    each update when it falls below (dynamic boundaries of
+ *                    Sec. 2.3; a common practice, not in the paper). */
+enum {
+    SPH_O_CUBIC = 1u << 0,
+    SPH_O_RHO_FLOOR = 1u << 1
+};
 
 /* Feature bits of sph_params.features. */
 enum {
@@ -372,20 +388,27 @@ int sph_mlp_sync(sph_ctx *ctx, sph_mlp *net, void *stream);
  * n): row r describes sorted particle rows[r] (rows == NULL: particle r).
  * x: bfloat16 [nrows][SPH_NN_IN], device. A row index outside the label-0
  * prefix gives a zero row. Re-packs the sorted arrays first, so the state
- * may have been changed in place since the sort (not reordered). */
+ * may have been changed in place since the sort (not reordered).
+ * rates (optional, NULL: not written): FP32 [nrows][4], device: the row's
+ * pair sums as rates in FP32 before any scaling, (ap + g) for fluid rows and
+ * 0 for others (3 components), and dr; zero for ghosts and out-of-prefix rows.
+ * They are what sph_nn_targets and sph_nn_apply take as the part of the
+ * change that the network need not predict. */
 int sph_nn_features(sph_ctx *ctx, const sph_soa *sorted, const int32_t *rows, uint32_t nrows,
-                    const sph_nn_scales *scales, void *x, void *stream);
+                    const sph_nn_scales *scales, void *x, float *rates, void *stream);
 
 /* where[id[k]] = k for k < n (ids must be a permutation of 0..n-1). */
 int sph_nn_index(sph_ctx *ctx, const int32_t *id, uint32_t n, int32_t *where, void *stream);
 
 /* Training targets: for r < nrows, particle k = rows[r] (or r) of state a
  * and the particle with the same id in state b (index where_b[id]):
- * t[4r..4r+3] = ((u_b - u_a) inv_dv (3 components), (rho_b - rho_a) inv_dr),
- * FP32. */
+ * t[4r..4r+3] = (((u_b - u_a) - span rates[4r..]) inv_dv (3 components),
+ * ((rho_b - rho_a) - span rates[4r+3]) inv_dr), in FP32 in that order
+ * without contraction. rates: FP32 [nrows][4] of sph_nn_features for the
+ * same rows, or NULL for zeros. */
 int sph_nn_targets(sph_ctx *ctx, const sph_soa *a, const sph_soa *b, const int32_t *where_b,
-                   const int32_t *rows, uint32_t nrows, float inv_dv, float inv_dr, float *t,
-                   void *stream);
+                   const int32_t *rows, uint32_t nrows, const float *rates, float span,
+                   float inv_dv, float inv_dr, float *t, void *stream);
 
 /* Forward pass of rows x (bfloat16 [rows][SPH_NN_IN]) into y (FP32
  * [rows][4]); keeps the activations in net for sph_mlp_backward.
@@ -405,23 +428,27 @@ int sph_mlp_adam(sph_ctx *ctx, sph_mlp *net, float lr, float beta1, float beta2,
                  uint32_t t, void *stream);
 
 /* Apply network outputs y (FP32 [nrows][4], row r = sorted particle r) to
- * the sorted state over a span dt4 of four steps: fluid u += y[0..2]
- * dv_scale, x += dt4 (u_old + u_new)/2; fluid and boundary rho += y[3]
- * dr_scale; ghosts untouched. The previous-step arrays are set to one step
- * back along the same change (new - change/4), so a following Verlet step
- * continues the leapfrog. A non-finite result or |rho/rho0 - 1| > rho_tol
- * sets SPH_S_NN_RANGE. */
-int sph_nn_apply(sph_ctx *ctx, sph_soa *sorted, const float *y, uint32_t nrows, float dv_scale,
-                 float dr_scale, float dt4, float rho_tol, void *stream);
+ * the sorted state over a span dt4 of four steps, with rates (FP32
+ * [nrows][4] of sph_nn_features, or NULL for zeros): fluid u += dt4
+ * rates[0..2] + y[0..2] dv_scale, x += dt4 (u_old + u_new)/2; fluid and
+ * boundary rho += dt4 rates[3] + y[3] dr_scale; ghosts untouched. The
+ * previous-step arrays are set to one step back along the same change (new -
+ * change/4), so a following Verlet step continues the leapfrog. A
+ * non-finite result or |rho/rho0 - 1| > rho_tol sets SPH_S_NN_RANGE. */
+int sph_nn_apply(sph_ctx *ctx, sph_soa *sorted, const float *y, const float *rates,
+                 uint32_t nrows, float dv_scale, float dr_scale, float dt4, float rho_tol,
+                 void *stream);
 
 /* One surrogate advance: sort cur into next (as sph_sort), build every
- * particle's input row (into a row buffer the context allocates on the first
- * call: capacity x SPH_NN_IN bfloat16), then one kernel runs the network
- * (width 128) on tiles of 64 rows and applies the result to next as
- * sph_nn_apply does. */
+ * particle's input row (into buffers the context allocates on the first call:
+ * capacity x SPH_NN_IN bfloat16 rows, 4 FP32 rates and 4 FP32 outputs per
+ * particle), then one kernel runs the network (width 128) on tiles of 64 rows
+ * and the result is applied to next as sph_nn_apply does, with the rows'
+ * rates if residual != 0 (a network trained on targets with rates) and
+ * without them otherwise. */
 int sph_nn_advance(sph_ctx *ctx, const sph_mlp *net, const sph_soa *cur, sph_soa *next,
                    uint32_t n, const sph_nn_scales *scales, float dv_scale, float dr_scale,
-                   float dt4, float rho_tol, void *stream);
+                   float dt4, float rho_tol, int residual, void *stream);
 
 /* Training noise: adds to the velocity and density of every fluid particle
  * k < n (and to their previous-step values, so a Verlet step sees the same

@@ -62,7 +62,8 @@ void free_events(sph_ctx *c) {
 
 void free_all(sph_ctx *c) {
     free_events(c);
-    void *vptrs[] = {c->p64, c->drate, c->tot_part, c->nn_part, c->nn_out, c->nn_x, c->nn_y};
+    void *vptrs[] = {c->p64,    c->drate, c->tot_part, c->nn_part,
+                     c->nn_out, c->nn_x,  c->nn_y,     c->nn_rate};
     for (void *p : vptrs)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
@@ -103,8 +104,12 @@ int sph_create(const sph_params *p, sph_ctx **out) {
         return fail(nullptr, SPH_E_INVALID_ARG, "physical parameters must be positive");
     if (p->gamma != 7.0)
         return fail(nullptr, SPH_E_INVALID_ARG, "gamma must be 7 (Tait law of the method)");
-    if (p->reserved_ != 0 || (p->features & ~(uint32_t)(SPH_F_CELL | SPH_F_FP64)) != 0)
-        return fail(nullptr, SPH_E_INVALID_ARG, "reserved fields and unknown feature bits must be zero");
+    if ((p->options & ~(int32_t)(SPH_O_CUBIC | SPH_O_RHO_FLOOR)) != 0 ||
+        (p->features & ~(uint32_t)(SPH_F_CELL | SPH_F_FP64)) != 0)
+        return fail(nullptr, SPH_E_INVALID_ARG, "unknown option or feature bits");
+    if (p->options != 0 && p->features != 0)
+        return fail(nullptr, SPH_E_INVALID_ARG,
+                    "the cell and FP64 paths keep the Wendland kernel: options must be 0");
     for (int a = 0; a < 3; a++)
         if (p->ncell[a] < 1 || !isfinite(p->origin[a]) || !isfinite(p->g[a]))
             return fail(nullptr, SPH_E_INVALID_ARG, "bad grid or gravity on axis %d", a);
@@ -166,6 +171,8 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     k.gz = (float)p->g[2];
     const double aD = 21.0 / (16.0 * M_PI * p->h * p->h * p->h);
     k.kgrad = (float)(-5.0 * aD / (p->h * p->h));
+    k.kgrad_cubic = (float)(-0.75 / (M_PI * p->h * p->h * p->h) / (p->h * p->h));
+    k.options = p->options;
     k.cfl = (float)p->cfl;
     k.euler_every = p->euler_every;
 
@@ -709,18 +716,21 @@ int sph_mlp_sync(sph_ctx *c, sph_mlp *m, void *stream) {
 }
 
 int sph_nn_features(sph_ctx *c, const sph_soa *sorted, const int32_t *rows, uint32_t nrows,
-                    const sph_nn_scales *scales, void *x, void *stream) {
+                    const sph_nn_scales *scales, void *x, float *rates, void *stream) {
     int r = enter(c);
     if (r) return r;
     if (!soa_ok(sorted) || !scales || (nrows && !x))
         return fail(c, SPH_E_INVALID_ARG, "null argument");
+    if (c->prm.options != 0)
+        return fail(c, SPH_E_INVALID_ARG, "surrogate rows use the Wendland kernel: options must be 0");
     if (!c->have_sort || c->last_path != 0)
         return fail(c, SPH_E_STATE, "sph_nn_features needs a preceding sph_sort");
     if (!rows && nrows > c->sorted_n)
         return fail(c, SPH_E_INVALID_ARG, "nrows = %u > n = %u of the sort", nrows, c->sorted_n);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_pack(c, *sorted, c->sorted_n, s);
-    if (e == hipSuccess) e = launch_nn_features(c, sorted->type, rows, nrows, *scales, x, 0, s);
+    if (e == hipSuccess)
+        e = launch_nn_features(c, sorted->type, rows, nrows, *scales, x, 0, rates, s);
     if (e != hipSuccess) return hip_fail(c, e, "features");
     return SPH_OK;
 }
@@ -736,14 +746,14 @@ int sph_nn_index(sph_ctx *c, const int32_t *id, uint32_t n, int32_t *where, void
 }
 
 int sph_nn_targets(sph_ctx *c, const sph_soa *a, const sph_soa *b, const int32_t *where_b,
-                   const int32_t *rows, uint32_t nrows, float inv_dv, float inv_dr, float *t,
-                   void *stream) {
+                   const int32_t *rows, uint32_t nrows, const float *rates, float span,
+                   float inv_dv, float inv_dr, float *t, void *stream) {
     int r = enter(c);
     if (r) return r;
     if (!soa_ok(a) || !soa_ok(b) || (nrows && (!where_b || !t)))
         return fail(c, SPH_E_INVALID_ARG, "null argument");
-    hipError_t e = launch_nn_targets(*a, *b, where_b, rows, nrows, inv_dv, inv_dr, t,
-                                     (hipStream_t)stream);
+    hipError_t e = launch_nn_targets(*a, *b, where_b, rows, nrows, rates, span, inv_dv, inv_dr,
+                                     t, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "targets");
     return SPH_OK;
 }
@@ -833,14 +843,14 @@ int sph_mlp_adam(sph_ctx *c, sph_mlp *m, float lr, float beta1, float beta2, flo
     return SPH_OK;
 }
 
-int sph_nn_apply(sph_ctx *c, sph_soa *sorted, const float *y, uint32_t nrows, float dv_scale,
-                 float dr_scale, float dt4, float rho_tol, void *stream) {
+int sph_nn_apply(sph_ctx *c, sph_soa *sorted, const float *y, const float *rates, uint32_t nrows,
+                 float dv_scale, float dr_scale, float dt4, float rho_tol, void *stream) {
     int r = enter(c);
     if (r) return r;
     if (!soa_ok(sorted) || (nrows && !y)) return fail(c, SPH_E_INVALID_ARG, "null argument");
     if (!c->have_sort || c->last_path != 0 || nrows > c->sorted_n)
         return fail(c, SPH_E_STATE, "sph_nn_apply needs a preceding sph_sort of >= nrows");
-    hipError_t e = launch_nn_apply(c, *sorted, y, nrows, dv_scale, dr_scale, dt4, rho_tol,
+    hipError_t e = launch_nn_apply(c, *sorted, y, rates, nrows, dv_scale, dr_scale, dt4, rho_tol,
                                    (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "apply");
     c->have_dt = false;
@@ -849,11 +859,13 @@ int sph_nn_apply(sph_ctx *c, sph_soa *sorted, const float *y, uint32_t nrows, fl
 
 int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *next, uint32_t n,
                    const sph_nn_scales *scales, float dv_scale, float dr_scale, float dt4,
-                   float rho_tol, void *stream) {
+                   float rho_tol, int residual, void *stream) {
     int r = enter(c);
     if (r) return r;
     if ((r = mlp_check(c, m, false))) return r;
     if (m->width != 128) return fail(c, SPH_E_INVALID_ARG, "the advance kernel needs width 128");
+    if (c->prm.options != 0)
+        return fail(c, SPH_E_INVALID_ARG, "surrogate rows use the Wendland kernel: options must be 0");
     if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
     if (!soa_ok(cur) || !soa_ok(next) || !scales)
         return fail(c, SPH_E_INVALID_ARG, "null argument");
@@ -864,19 +876,23 @@ int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *ne
         // rows and outputs of every particle: allocated once per context, on first use
         if (c->nn_x) (void)hipFree(c->nn_x);
         if (c->nn_y) (void)hipFree(c->nn_y);
+        if (c->nn_rate) (void)hipFree(c->nn_rate);
         c->nn_x = nullptr;
         c->nn_y = nullptr;
+        c->nn_rate = nullptr;
         c->nn_x_rows = 0;
         hipError_t e = hipMalloc(&c->nn_x, (size_t)c->capacity * SPH_NN_IN * 2);
         if (e == hipSuccess) e = hipMalloc((void **)&c->nn_y, (size_t)c->capacity * SPH_NN_OUT * 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->nn_rate, (size_t)c->capacity * 16);
         if (e != hipSuccess) return hip_fail(c, e, "surrogate row buffer");
         c->nn_x_rows = c->capacity;
     }
     if ((r = do_sort(c, cur, next, n, s))) return r;
-    hipError_t e = launch_nn_features(c, next->type, nullptr, n, *scales, c->nn_x, 1, s);
+    float *rates = residual ? c->nn_rate : nullptr;
+    hipError_t e = launch_nn_features(c, next->type, nullptr, n, *scales, c->nn_x, 1, rates, s);
     if (e == hipSuccess)
-        e = launch_nn_mlp_apply(c, *m, *next, c->nn_x, c->nn_y, n, dv_scale, dr_scale, dt4,
-                                rho_tol, s);
+        e = launch_nn_mlp_apply(c, *m, *next, c->nn_x, c->nn_y, rates, n, dv_scale, dr_scale,
+                                dt4, rho_tol, s);
     if (e != hipSuccess) return hip_fail(c, e, "surrogate advance");
     c->have_dt = false;
     return SPH_OK;

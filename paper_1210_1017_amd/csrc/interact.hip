@@ -43,8 +43,12 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 //            16-bit (run, offset) entries;
 //   compute: the pair terms are evaluated for the listed neighbours only.
 // The list is flushed early if it fills (dense regions), so any neighbour
-// count is handled. The gradient constant -5 aD / h^2 and the mass are
-// applied once per particle after the sums.
+// count is handled. The gradient constant and the mass are applied once per
+// particle after the sums: grad_i W_ij = kgrad G(q) r_ij with
+//   Wendland C2:   G = (1 - q/2)^3,                         kgrad = -5 aD / h^2;
+//   cubic spline:  G = 4 - 3q (q < 1), (2 - q)^2 / q (q >= 1), kgrad = -3 aD / (4 h^2)
+// (the two aD of the kernels' definitions differ).
+template <bool kCubic>
 __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
     KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4, uint32_t n,
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
@@ -99,8 +103,16 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
                     const v4f vj = __builtin_amdgcn_raw_buffer_load_b128(rv, j * 16u, 0, 0);
                     const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
                     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
-                    const float F = t * t * t;  // grad W / (kgrad r_ij)
+                    float F;  // grad W / (kgrad r_ij)
+                    if (kCubic) {
+                        const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h;
+                        const float t = 2.0f - q;
+                        const float outer = t * t * __builtin_amdgcn_rcpf(q);
+                        F = q < 1.0f ? fmaf(-3.0f, q, 4.0f) : outer;
+                    } else {
+                        const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
+                        F = t * t * t;
+                    }
                     const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
                     const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
                     drho = fmaf(F, vr, drho);
@@ -179,7 +191,7 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
             flush(cnt);
             npair = listed + cnt - 1u;  // minus the self entry
         }
-        const float m = kp.mass, mk = kp.mass * kp.kgrad;
+        const float m = kp.mass, mk = kp.mass * (kCubic ? kp.kgrad_cubic : kp.kgrad);
         float ax = 0.f, ay = 0.f, az = 0.f, ar = 0.f;
         if (ti == kFluid) {
             ax = fmaf(-mk, axs, kp.gx);
@@ -240,9 +252,10 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
 hipError_t launch_interact(sph_ctx *c, const uint8_t *type, uint32_t n, const sph_rates &out,
                            hipStream_t s, hipEvent_t after_kernel) {
     const uint32_t nb = n == 0 ? 1 : (n + kInteractThreads - 1) / kInteractThreads;
-    hipLaunchKernelGGL(k_interact, dim3(nb), dim3(kInteractThreads), 0, s, c->kp, c->pos4,
-                       c->vel4, n, type, c->keys_sorted, c->cell_begin, c->cell_end, c->info,
-                       out.ax, out.ay, out.az, out.arho, out.press, out.nu, out.npair);
+    auto kern = (c->kp.options & SPH_O_CUBIC) ? k_interact<true> : k_interact<false>;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kInteractThreads), 0, s, c->kp, c->pos4, c->vel4, n,
+                       type, c->keys_sorted, c->cell_begin, c->cell_end, c->info, out.ax, out.ay,
+                       out.az, out.arho, out.press, out.nu, out.npair);
     if (after_kernel) (void)hipEventRecord(after_kernel, s);
     return hipGetLastError();
 }

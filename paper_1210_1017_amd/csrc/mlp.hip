@@ -32,10 +32,12 @@ __device__ __forceinline__ float nn_kind(uint8_t t) { return t == kBoundary ? -1
 // cell (Sec. 3.1: 9 contiguous z-runs in the x-major cell order) with FP32
 // squared distance fmaf(dz,dz,fmaf(dy,dy,dx*dx)) < r2f, in increasing sorted
 // index (runs and their particles are visited in that order); the first 64
-// fill the slots. Pass 1 tests the candidates (groups of kNnUnroll buffer
-// loads in flight) and appends (run << 12 | offset) entries to the lane's
-// list in LDS; pass 2 walks the list, writes each slot's 8 features and sums
-// the pressure and continuity terms of Sec. 2.2 for the own block.
+// fill the slots (more found: SPH_S_NN_LIST). Pass 1 tests the candidates
+// (groups of kNnUnroll buffer loads in flight) and appends (run << 12 |
+// offset) entries to the lane's list in LDS; pass 2 walks the list, writes
+// each slot's 8 features and sums the pressure and continuity terms of
+// Sec. 2.2 for the own block and, if asked, for the FP32 rates of the row
+// (pressure acceleration + g for fluid, 0 otherwise; continuity rate).
 struct NnRowLds {
     uint16_t list[kNnSlots][kNnRowThreads];
     uint32_t base[9][kNnRowThreads];
@@ -49,7 +51,7 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
                                             const uint32_t *__restrict__ cbeg,
                                             const uint32_t *__restrict__ cend, uint32_t n,
                                             uint32_t n0, uint32_t i, NnRowLds &L, bf16 *dst,
-                                            size_t cstride, uint32_t *flags) {
+                                            size_t cstride, float4 *rate, uint32_t *flags) {
     // dst: the row's first 16-byte chunk; chunk q lies cstride chunks further
     // (1: rows are contiguous; the row count: chunk-major, chunk q of every
     // row first, so that a wave's 64 lanes store 1 KB contiguously)
@@ -60,6 +62,7 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
     for (int q = 0; q < 8; q++) zero8[q] = (bf16)0.0f;
     if (i >= n0 || type[i] == kGhost) {
         for (int q = 0; q < kNnIn / 8; q++) d8[q * cstride] = zero8;
+        if (rate) *rate = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
     const __amdgpu_buffer_rsrc_t rp =
@@ -137,9 +140,15 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
         dr = fmaf(F, fmaf(duz, ddz, fmaf(duy, ddy, dux * ddx)), dr);  // sum F v_ij . r_ij
     }
     for (uint32_t s = listed; s < (uint32_t)kNnSlots; s++) d8[s * cstride] = zero8;
+    if (found > (uint32_t)kNnSlots) atomicOr(flags, (uint32_t)SPH_S_NN_LIST);
     // ap = -m kgrad sum (P_i + P_j) F r_ij = m kgrad sum (P_i + P_j) F (r_j - r_i);
     // dr = m kgrad sum F v_ij . r_ij = m kgrad sum F (u_j - u_i) . (r_j - r_i)
     const float mk = kp.mass * kp.kgrad;
+    if (rate) {
+        const bool fl = type[i] == kFluid;
+        *rate = make_float4(fl ? fmaf(mk, apx, kp.gx) : 0.f, fl ? fmaf(mk, apy, kp.gy) : 0.f,
+                            fl ? fmaf(mk, apz, kp.gz) : 0.f, mk * dr);
+    }
     bf16x8 o0 = zero8, o1 = zero8;
     o0[0] = (bf16)((vi.w - sc.rho_ref) * sc.inv_rho);
     o0[1] = (bf16)(vi.x * sc.inv_vel);
@@ -164,14 +173,14 @@ __global__ __launch_bounds__(kNnRowThreads) void k_nn_features(
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
     const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend, uint32_t n,
     DevInfo *__restrict__ info, const int32_t *__restrict__ rows, uint32_t nrows,
-    bf16 *__restrict__ X, int chunk_major) {
+    bf16 *__restrict__ X, int chunk_major, float4 *__restrict__ rates) {
     __shared__ NnRowLds L;
     const uint32_t r = xcd_block(blockIdx.x, gridDim.x) * kNnRowThreads + threadIdx.x;
     if (r >= nrows) return;
     const uint32_t i = rows ? (uint32_t)rows[r] : r;
     bf16 *dst = chunk_major ? X + (size_t)r * 8 : X + (size_t)r * kNnIn;
     nn_lane_row(kp, sc, pos4, vel4, type, sk, cbeg, cend, n, info->n_label[0], i, L, dst,
-                chunk_major ? (size_t)nrows : 1, &info->flags);
+                chunk_major ? (size_t)nrows : 1, rates ? rates + r : nullptr, &info->flags);
 }
 
 static NnScales nn_scales(const sph_nn_scales &s) {
@@ -180,13 +189,13 @@ static NnScales nn_scales(const sph_nn_scales &s) {
 
 hipError_t launch_nn_features(sph_ctx *c, const uint8_t *type, const int32_t *rows,
                               uint32_t nrows, const sph_nn_scales &s, void *X, int chunk_major,
-                              hipStream_t st) {
+                              float *rates, hipStream_t st) {
     if (nrows == 0) return hipSuccess;
     const uint32_t n = c->sorted_n;
     hipLaunchKernelGGL(k_nn_features, dim3((nrows + kNnRowThreads - 1) / kNnRowThreads),
                        dim3(kNnRowThreads), 0, st, c->kp, nn_scales(s), c->pos4, c->vel4, type,
                        c->keys_sorted, c->cell_begin, c->cell_end, n, c->info, rows, nrows,
-                       (bf16 *)X, chunk_major);
+                       (bf16 *)X, chunk_major, (float4 *)rates);
     return hipGetLastError();
 }
 
@@ -511,24 +520,28 @@ hipError_t launch_id_scatter(const int32_t *id, uint32_t n, int32_t *where, hipS
 __global__ __launch_bounds__(256) void k_nn_targets(sph_soa a, sph_soa b,
                                                     const int32_t *__restrict__ where_b,
                                                     const int32_t *__restrict__ rows,
-                                                    uint32_t nrows, float inv_dv, float inv_dr,
+                                                    uint32_t nrows,
+                                                    const float4 *__restrict__ rates, float span,
+                                                    float inv_dv, float inv_dr,
                                                     float *__restrict__ T) {
+#pragma clang fp contract(off)
     const uint32_t r = blockIdx.x * 256 + threadIdx.x;
     if (r >= nrows) return;
     const uint32_t k = rows ? (uint32_t)rows[r] : r;
     const int32_t q = where_b[a.id[k]];
-    T[4 * r + 0] = (b.vx[q] - a.vx[k]) * inv_dv;
-    T[4 * r + 1] = (b.vy[q] - a.vy[k]) * inv_dv;
-    T[4 * r + 2] = (b.vz[q] - a.vz[k]) * inv_dv;
-    T[4 * r + 3] = (b.rho[q] - a.rho[k]) * inv_dr;
+    const float4 rt = rates ? rates[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    T[4 * r + 0] = ((b.vx[q] - a.vx[k]) - span * rt.x) * inv_dv;
+    T[4 * r + 1] = ((b.vy[q] - a.vy[k]) - span * rt.y) * inv_dv;
+    T[4 * r + 2] = ((b.vz[q] - a.vz[k]) - span * rt.z) * inv_dv;
+    T[4 * r + 3] = ((b.rho[q] - a.rho[k]) - span * rt.w) * inv_dr;
 }
 
 hipError_t launch_nn_targets(const sph_soa &a, const sph_soa &b, const int32_t *where_b,
-                             const int32_t *rows, uint32_t nrows, float inv_dv, float inv_dr,
-                             float *T, hipStream_t s) {
+                             const int32_t *rows, uint32_t nrows, const float *rates, float span,
+                             float inv_dv, float inv_dr, float *T, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_nn_targets, grid1(nrows), dim3(256), 0, s, a, b, where_b, rows, nrows,
-                       inv_dv, inv_dr, T);
+                       (const float4 *)rates, span, inv_dv, inv_dr, T);
     return hipGetLastError();
 }
 
@@ -536,13 +549,14 @@ struct NnApply {
     float dv_scale, dr_scale, dt4, rho_tol;
 };
 
-// Applies output (y0..y3) to sorted particle k: see sph_nn_apply.
+// Applies output (y0..y3) and the row's rates rt (zeros: none) to sorted
+// particle k: see sph_nn_apply.
 __device__ __forceinline__ void nn_apply_one(const KParams &kp, const sph_soa &st, uint32_t k,
-                                             float y0, float y1, float y2, float y3,
+                                             float y0, float y1, float y2, float y3, float4 rt,
                                              const NnApply &ap, uint32_t *flags) {
     const uint8_t t = st.type[k];
     if (t == kGhost) return;
-    const float dr = y3 * ap.dr_scale;
+    const float dr = fmaf(ap.dt4, rt.w, y3 * ap.dr_scale);
     const float rn = st.rho[k] + dr;
     st.rho[k] = rn;
     st.rhop[k] = rn - 0.25f * dr;
@@ -552,10 +566,11 @@ __device__ __forceinline__ void nn_apply_one(const KParams &kp, const sph_soa &s
         float *vel[3] = {st.vx, st.vy, st.vz};
         float *velp[3] = {st.vxp, st.vyp, st.vzp};
         const float y[3] = {y0, y1, y2};
+        const float b[3] = {rt.x, rt.y, rt.z};
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             const float v = vel[d][k];
-            const float dv = y[d] * ap.dv_scale;
+            const float dv = fmaf(ap.dt4, b[d], y[d] * ap.dv_scale);
             const float vn = v + dv;
             const float xn = pos[d][k] + ap.dt4 * 0.5f * (v + vn);
             pos[d][k] = xn;
@@ -568,20 +583,24 @@ __device__ __forceinline__ void nn_apply_one(const KParams &kp, const sph_soa &s
 }
 
 __global__ __launch_bounds__(256) void k_nn_apply(KParams kp, sph_soa st,
-                                                  const float *__restrict__ Y, uint32_t nrows,
-                                                  NnApply ap, DevInfo *__restrict__ info) {
+                                                  const float *__restrict__ Y,
+                                                  const float4 *__restrict__ rates,
+                                                  uint32_t nrows, NnApply ap,
+                                                  DevInfo *__restrict__ info) {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
     if (k >= nrows || k >= info->n_label[0]) return;
-    nn_apply_one(kp, st, k, Y[4 * k], Y[4 * k + 1], Y[4 * k + 2], Y[4 * k + 3], ap, &info->flags);
+    const float4 rt = rates ? rates[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+    nn_apply_one(kp, st, k, Y[4 * k], Y[4 * k + 1], Y[4 * k + 2], Y[4 * k + 3], rt, ap,
+                 &info->flags);
 }
 
-hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, uint32_t nrows,
-                           float dv_scale, float dr_scale, float dt4, float rho_tol,
-                           hipStream_t s) {
+hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, const float *rates,
+                           uint32_t nrows, float dv_scale, float dr_scale, float dt4,
+                           float rho_tol, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     const NnApply ap{dv_scale, dr_scale, dt4, rho_tol};
-    hipLaunchKernelGGL(k_nn_apply, grid1(nrows), dim3(256), 0, s, c->kp, st, Y, nrows, ap,
-                       c->info);
+    hipLaunchKernelGGL(k_nn_apply, grid1(nrows), dim3(256), 0, s, c->kp, st, Y,
+                       (const float4 *)rates, nrows, ap, c->info);
     return hipGetLastError();
 }
 
@@ -879,8 +898,8 @@ __global__ __launch_bounds__(kMlpThreads, 1) void k_nn_mlp(FusedNet net,
 }
 
 hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
-                               float *Y, uint32_t nrows, float dv_scale, float dr_scale,
-                               float dt4, float rho_tol, hipStream_t stream) {
+                               float *Y, const float *rates, uint32_t nrows, float dv_scale,
+                               float dr_scale, float dt4, float rho_tol, hipStream_t stream) {
     if (nrows == 0) return hipSuccess;
     const FusedNet net{(const bf16 *)m.wb[0], (const bf16 *)m.wb[1], (const bf16 *)m.wb[2],
                        (const bf16 *)m.wb[3], m.b[0], m.b[1], m.b[2], m.b[3]};
@@ -893,7 +912,7 @@ hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, 
                        nrows, Y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_nn_apply(c, st, Y, nrows, dv_scale, dr_scale, dt4, rho_tol, stream);
+    return launch_nn_apply(c, st, Y, rates, nrows, dv_scale, dr_scale, dt4, rho_tol, stream);
 }
 
 }  // namespace sph

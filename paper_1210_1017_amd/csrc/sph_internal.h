@@ -33,8 +33,10 @@ struct KParams {
     float rho0, inv_rho0, B, c0;
     float gx, gy, gz;
     float kgrad;  // -5 aD / h^2, aD = 21 / (16 pi h^3): grad W = kgrad (1 - q/2)^3 r_ij
+    float kgrad_cubic;  // -3 aD / (4 h^2), aD = 1 / (pi h^3): cubic spline, see k_interact
     float cfl;
     int32_t euler_every;
+    int32_t options;    // SPH_O_* bits
 };
 
 // Device-resident results of the last sort / interaction.
@@ -82,6 +84,7 @@ struct sph_ctx {
     double *nn_out = nullptr;     // 8 doubles: judge result
     void *nn_x = nullptr;         // surrogate input rows of sph_nn_advance (lazily allocated)
     float *nn_y = nullptr;        // its network outputs, 4 per row
+    float *nn_rate = nullptr;     // the rows' pair-sum rates, 4 per row
     size_t nn_x_rows = 0;
     uint32_t tot_blocks = 0;
     int last_path = 0;            // 0 plain, 1 cell, 2 FP64: which state the tables describe
@@ -148,7 +151,7 @@ hipError_t launch_totals_d(sph_ctx *c, const sph_dstate &st, uint32_t n, double 
 constexpr int kMlpSplits = 32;  // split-K slices of a weight-gradient GEMM, at most
 hipError_t launch_nn_features(sph_ctx *c, const uint8_t *type, const int32_t *rows,
                               uint32_t nrows, const sph_nn_scales &s, void *X, int chunk_major,
-                              hipStream_t st);
+                              float *rates, hipStream_t st);
 hipError_t launch_gemm(const void *A, const void *B, float *C, int M, int N, int K,
                        long long sam, long long sak, long long sbk, long long sbn, long long scm,
                        long long scn, int accumulate, float *part, hipStream_t s);
@@ -165,19 +168,19 @@ hipError_t launch_adam(float *w, float *m, float *v, const float *g, void *wb, l
 hipError_t launch_f32_to_bf16(const float *a, void *b, long long n, hipStream_t s);
 hipError_t launch_id_scatter(const int32_t *id, uint32_t n, int32_t *where, hipStream_t s);
 hipError_t launch_nn_targets(const sph_soa &a, const sph_soa &b, const int32_t *where_b,
-                             const int32_t *rows, uint32_t nrows, float inv_dv, float inv_dr,
-                             float *T, hipStream_t s);
-hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, uint32_t nrows,
-                           float dv_scale, float dr_scale, float dt4, float rho_tol,
-                           hipStream_t s);
+                             const int32_t *rows, uint32_t nrows, const float *rates, float span,
+                             float inv_dv, float inv_dr, float *T, hipStream_t s);
+hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, const float *rates,
+                           uint32_t nrows, float dv_scale, float dr_scale, float dt4,
+                           float rho_tol, hipStream_t s);
 hipError_t launch_nn_perturb(const sph_soa &st, uint32_t n, uint32_t seed, float sigma_u,
                              float sigma_rho, hipStream_t s);
 hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
                            const int32_t *where_r, const int32_t *where_b, uint32_t n,
                            double *part, double *out, hipStream_t s);
 hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
-                               float *Y, uint32_t nrows, float dv_scale, float dr_scale,
-                               float dt4, float rho_tol, hipStream_t stream);
+                               float *Y, const float *rates, uint32_t nrows, float dv_scale,
+                               float dr_scale, float dt4, float rho_tol, hipStream_t stream);
 
 // update.hip
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,

@@ -10,6 +10,7 @@ namespace sph {
 //   Euler:    v' = v + dt a,        rho' = rho + dt D
 //   leapfrog: v' = v_prev + 2dt a,  rho' = rho_prev + 2dt D
 //   r' = r + dt v + dt^2 a / 2, then (v_prev, rho_prev) <- (v, rho).
+// With SPH_O_RHO_FLOOR a boundary particle's new density is at least rho0.
 __global__ __launch_bounds__(256) void k_verlet(KParams kp, sph_soa st,
                                                 const float *__restrict__ ax,
                                                 const float *__restrict__ ay,
@@ -27,7 +28,8 @@ __global__ __launch_bounds__(256) void k_verlet(KParams kp, sph_soa st,
     const uint8_t t = st.type[k];
     if (t == kGhost) return;
     const float rho = st.rho[k];
-    const float rn = euler ? fmaf(dt, arho[k], rho) : fmaf(2.0f * dt, arho[k], st.rhop[k]);
+    float rn = euler ? fmaf(dt, arho[k], rho) : fmaf(2.0f * dt, arho[k], st.rhop[k]);
+    if ((kp.options & SPH_O_RHO_FLOOR) && t == kBoundary && rn < kp.rho0) rn = kp.rho0;
     st.rhop[k] = rho;
     st.rho[k] = rn;
     bool ok = isfinite(rn);

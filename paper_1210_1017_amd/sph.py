@@ -36,11 +36,12 @@ class Params(C.Structure):
                 ("gamma", C.c_double), ("c0", C.c_double), ("alpha", C.c_double),
                 ("eta_over_h", C.c_double), ("cfl", C.c_double), ("mass", C.c_double),
                 ("g", C.c_double * 3), ("origin", C.c_double * 3), ("ncell", C.c_int32 * 3),
-                ("euler_every", C.c_int32), ("slab_mode", C.c_int32), ("reserved_", C.c_int32),
+                ("euler_every", C.c_int32), ("slab_mode", C.c_int32), ("options", C.c_int32),
                 ("slab_xlo", C.c_double), ("slab_xhi", C.c_double),
                 ("capacity", C.c_uint32), ("features", C.c_uint32)]
 
 FEATURE_CELL, FEATURE_FP64 = 1, 2
+OPTION_CUBIC, OPTION_RHO_FLOOR = 1, 2
 CSTATE_FIELDS = ("cell", "ox", "oy", "oz", "vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop",
                  "type", "id")
 DSTATE_F64 = ("x", "y", "z", "vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop")
@@ -149,15 +150,15 @@ def lib() -> C.CDLL:
         L.sph_mlp_work_floats.argtypes = [C.c_int32, u32]
         L.sph_mlp_work_floats.restype = u64
         L.sph_mlp_sync.argtypes = [vp, P(MlpStruct), vp]
-        L.sph_nn_features.argtypes = [vp, P(SoA), vp, u32, P(NnScales), vp, vp]
+        L.sph_nn_features.argtypes = [vp, P(SoA), vp, u32, P(NnScales), vp, vp, vp]
         L.sph_nn_index.argtypes = [vp, vp, u32, vp, vp]
-        L.sph_nn_targets.argtypes = [vp, P(SoA), P(SoA), vp, vp, u32, f32, f32, vp, vp]
+        L.sph_nn_targets.argtypes = [vp, P(SoA), P(SoA), vp, vp, u32, vp, f32, f32, f32, vp, vp]
         L.sph_mlp_forward.argtypes = [vp, P(MlpStruct), vp, u32, vp, vp]
         L.sph_mlp_backward.argtypes = [vp, P(MlpStruct), vp, u32, vp, P(f32), vp]
         L.sph_mlp_adam.argtypes = [vp, P(MlpStruct), f32, f32, f32, f32, u32, vp]
-        L.sph_nn_apply.argtypes = [vp, P(SoA), vp, u32, f32, f32, f32, f32, vp]
+        L.sph_nn_apply.argtypes = [vp, P(SoA), vp, vp, u32, f32, f32, f32, f32, vp]
         L.sph_nn_advance.argtypes = [vp, P(MlpStruct), P(SoA), P(SoA), u32, P(NnScales), f32,
-                                     f32, f32, f32, vp]
+                                     f32, f32, f32, i32, vp]
         L.sph_nn_perturb.argtypes = [vp, P(SoA), u32, u32, f32, f32, vp]
         L.sph_nn_judge.argtypes = [vp, P(SoA), P(SoA), P(SoA), vp, vp, u32, P(C.c_double), vp]
         _lib = L
@@ -181,6 +182,7 @@ def make_params(p: dict, capacity: int, features: int = 0) -> Params:
         s.ncell[a] = int(p["ncell"][a])
     s.euler_every = int(p["euler_every"])
     s.slab_mode = int(p.get("slab_mode", 0))
+    s.options = int(p.get("options", 0))
     s.slab_xlo = float(p.get("slab_xlo", 0.0))
     s.slab_xhi = float(p.get("slab_xhi", 0.0))
     s.capacity = int(capacity)
@@ -472,20 +474,24 @@ class Context:
     def mlp_sync(self, net: "Mlp", stream=None):
         self._check(self.L.sph_mlp_sync(self.h, C.byref(net.struct()), _stream_ptr(stream)))
 
-    def nn_features(self, srt: DeviceState, rows, nrows: int, scales, X, stream=None):
+    def nn_features(self, srt: DeviceState, rows, nrows: int, scales, X, rates=None,
+                    stream=None):
         sc = NnScales(*[float(v) for v in scales[:7]])
         self._check(self.L.sph_nn_features(self.h, C.byref(srt.soa()),
                                            None if rows is None else _addr(rows), nrows,
-                                           C.byref(sc), _addr(X), _stream_ptr(stream)))
+                                           C.byref(sc), _addr(X),
+                                           None if rates is None else _addr(rates),
+                                           _stream_ptr(stream)))
 
     def nn_index(self, ids, n: int, where, stream=None):
         self._check(self.L.sph_nn_index(self.h, _addr(ids), n, _addr(where), _stream_ptr(stream)))
 
     def nn_targets(self, a: DeviceState, b: DeviceState, where_b, rows, nrows: int,
-                   inv_dv: float, inv_dr: float, T, stream=None):
+                   inv_dv: float, inv_dr: float, T, rates=None, span: float = 0.0, stream=None):
         self._check(self.L.sph_nn_targets(self.h, C.byref(a.soa()), C.byref(b.soa()),
                                           _addr(where_b), None if rows is None else _addr(rows),
-                                          nrows, inv_dv, inv_dr, _addr(T), _stream_ptr(stream)))
+                                          nrows, None if rates is None else _addr(rates), span,
+                                          inv_dv, inv_dr, _addr(T), _stream_ptr(stream)))
 
     def mlp_forward(self, net: "Mlp", X, rows: int, Y, stream=None):
         self._check(self.L.sph_mlp_forward(self.h, C.byref(net.struct()), _addr(X), rows,
@@ -505,16 +511,19 @@ class Context:
                                         int(t), _stream_ptr(stream)))
 
     def nn_apply(self, srt: DeviceState, Y, nrows: int, dv_scale: float, dr_scale: float,
-                 dt4: float, rho_tol: float, stream=None):
-        self._check(self.L.sph_nn_apply(self.h, C.byref(srt.soa()), _addr(Y), nrows, dv_scale,
-                                        dr_scale, dt4, rho_tol, _stream_ptr(stream)))
+                 dt4: float, rho_tol: float, rates=None, stream=None):
+        self._check(self.L.sph_nn_apply(self.h, C.byref(srt.soa()), _addr(Y),
+                                        None if rates is None else _addr(rates), nrows,
+                                        dv_scale, dr_scale, dt4, rho_tol, _stream_ptr(stream)))
 
     def nn_advance(self, net: "Mlp", cur: DeviceState, nxt: DeviceState, n: int, scales,
-                   dv_scale: float, dr_scale: float, dt4: float, rho_tol: float, stream=None):
+                   dv_scale: float, dr_scale: float, dt4: float, rho_tol: float,
+                   residual: bool = False, stream=None):
         sc = NnScales(*[float(v) for v in scales[:7]])
         self._check(self.L.sph_nn_advance(self.h, C.byref(net.struct()), C.byref(cur.soa()),
                                           C.byref(nxt.soa()), n, C.byref(sc), dv_scale, dr_scale,
-                                          dt4, rho_tol, _stream_ptr(stream)))
+                                          dt4, rho_tol, int(bool(residual)),
+                                          _stream_ptr(stream)))
 
     def nn_perturb(self, st: DeviceState, n: int, seed: int, sigma_u: float, sigma_rho: float,
                    stream=None):

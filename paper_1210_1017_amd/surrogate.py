@@ -11,14 +11,18 @@ The network predicts, for each fluid or boundary particle, the mean rates
 du/dt (3 components, in units of ``acc_scale``) and drho/dt (in units of
 ``drho_scale``) over the next k = 4 time steps; an advance applies them over
 4 dt with the dt of the latest plain step (the CFL dt is dominated by the
-nearly constant sound speed).
+nearly constant sound speed). With ``residual`` (the default of training)
+the network predicts only the part of those rates beyond the row's own pair
+sums: the pressure acceleration plus gravity and the continuity rate of
+Sec. 2.2 over the row's neighbours, which the rows kernel computes in FP32
+and the advance adds exactly.
 """
 from __future__ import annotations
 
 import json
 import os
 import time
-from dataclasses import asdict, dataclass, field
+from dataclasses import asdict, dataclass, field, replace
 
 import numpy as np
 
@@ -43,6 +47,7 @@ class NnConfig:
     adaptive: bool = True         # check more often as the judged error grows
     judge_tol: float = 0.01       # max |rho_sur - rho_sph| / rho_sph before fallback
     keep_judged: bool = True      # continue from the judge's plain result (a periodic correction)
+    residual: bool = False        # targets are the rates beyond the rows' own pair-sum rates
     meta: dict = field(default_factory=dict)
 
     def scales(self, params: dict) -> tuple:
@@ -97,7 +102,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
           width: int = 128, case_fn=cases.obstacle_tank, log=print,
           time_budget_s: float | None = None, noise_u: float = 0.02,
           noise_rho: float = 2.0, wcol=(1.0, 1.0, 1.0, 2.0), rollout_prob: float = 0.5,
-          rollout_max: int = 3, rollout_after: int = 500):
+          rollout_max: int = 3, rollout_after: int = 500, residual: bool = True):
     """Online training: for each of n_traj seeded layouts, run plain SPH for
     steps_per_traj steps; every window_every steps, take the sorted state A,
     build the input rows of `rows` randomly drawn particles, run 4 more plain
@@ -111,9 +116,10 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
     window starts from the state left by 1..rollout_max advances of the
     network being trained (sph_nn_advance) instead of plain steps, so that
     the targets also cover SPH's response to the network's own errors.
-    Returns (net, cfg, history)."""
+    With residual, the targets are (B - A) / (4 dt) minus the rows' pair-sum
+    rates (sph_nn_features' rates output). Returns (net, cfg, history)."""
     import torch
-    cfg = NnConfig(width=width)
+    cfg = NnConfig(width=width, residual=bool(residual))
     net = None
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
@@ -123,6 +129,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
     total_windows = n_traj * (steps_per_traj // window_every)
     wi = 0
     rho_dev_max = 0.0
+    ms_acc, ms_drho = [], []
     for tr in range(n_traj):
         case = case_fn(seed * 100003 + tr)
         n, p = case.n, case.params
@@ -134,6 +141,8 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
             X = torch.empty(rows, sph.NN_IN, dtype=torch.bfloat16, device="cuda")
             T = torch.empty(rows, sph.NN_OUT, dtype=torch.float32, device="cuda")
             Y = torch.empty(rows, sph.NN_OUT, dtype=torch.float32, device="cuda")
+            Rt = (torch.empty(rows, sph.NN_OUT, dtype=torch.float32, device="cuda")
+                  if cfg.residual else None)
             where = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
         if where.numel() < n:
             where = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -153,7 +162,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
                 for _ in range(int(noise_rng.integers(1, rollout_max + 1))):
                     nxt = _others(bufs, cur)[0]
                     ctx.nn_advance(net, cur, nxt, n, scales, span * cfg.acc_scale,
-                                   span * cfg.drho_scale, span, 1.0)
+                                   span * cfg.drho_scale, span, 1.0, residual=cfg.residual)
                     cur, step = nxt, step + K_STEPS
             # window: sorted copy A, input rows, 4 plain steps to B
             A = _others(bufs, cur)[0]
@@ -164,19 +173,27 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
                 ctx.nn_perturb(A, n, seed * 7919 + wi, lvl * noise_u, lvl * noise_rho)
             n0 = ctx.counts()["n_label"][0]
             r = torch.randint(0, n0, (rows,), generator=gen, device="cuda", dtype=torch.int32)
-            ctx.nn_features(A, r, rows, scales, X)
+            ctx.nn_features(A, r, rows, scales, X, rates=Rt)
             B, step, dts = _plain_steps(ctx, A, _others(bufs, A)[:2], n, step, K_STEPS)
             span = float(sum(dts))
             ctx.nn_index(B.t["id"], n, where)
             if cfg.meta.get("scaled") is None:
-                # unit scales on the first window: set them from the data
-                ctx.nn_targets(A, B, where, r, rows, 1.0 / span, 1.0 / span, T)
+                # target scales from the data: the mean squares of the unit-scale
+                # targets over the windows of the first half of the first
+                # trajectory (the flow develops from rest), no training before
+                ctx.nn_targets(A, B, where, r, rows, 1.0 / span, 1.0 / span, T, rates=Rt,
+                               span=span)
                 t_host = T.cpu().numpy().astype(np.float64)
-                cfg.acc_scale = float(max(np.sqrt(np.mean(t_host[:, :3] ** 2)), 1e-3))
-                cfg.drho_scale = float(max(np.sqrt(np.mean(t_host[:, 3] ** 2)), 1e-3))
+                ms_acc.append(float(np.mean(t_host[:, :3] ** 2)))
+                ms_drho.append(float(np.mean(t_host[:, 3] ** 2)))
+                if step < steps_per_traj // 2:
+                    cur = B
+                    continue
+                cfg.acc_scale = float(max(np.sqrt(np.mean(ms_acc)), 1e-3))
+                cfg.drho_scale = float(max(np.sqrt(np.mean(ms_drho)), 1e-3))
                 cfg.meta["scaled"] = True
             ctx.nn_targets(A, B, where, r, rows, 1.0 / (span * cfg.acc_scale),
-                           1.0 / (span * cfg.drho_scale), T)
+                           1.0 / (span * cfg.drho_scale), T, rates=Rt, span=span)
             frac = wi / max(total_windows - 1, 1)
             lr_t = lr * (lr_final / lr) ** frac
             ctx.mlp_forward(net, X, rows, Y)
@@ -269,7 +286,7 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
         S = others(cur)[0]
         span = K_STEPS * dt
         ctx.nn_advance(net, cur, S, n, scales, span * cfg.acc_scale, span * cfg.drho_scale, span,
-                       cfg.rho_band)
+                       cfg.rho_band, residual=cfg.residual)
         bad = ctx.status() & (sph.STATUS_NN_RANGE | sph.STATUS_NONFINITE)
         do_judge = judge and since_judge >= interval
         since_judge = 0 if do_judge else since_judge + 1
@@ -337,8 +354,9 @@ def report(steps: int = 1000, weights: str | None = None, judge_every: int | Non
     """Surrogate against plain FP32 SPH on the 1.47M-particle obstacle dam
     break with a layout that training never saw: steps/s of both loops, and
     the surrogate state after ``steps`` steps against the plain state by id;
-    the same for persistence (a network that predicts no change), which shows
-    what the trained network adds."""
+    the same for persistence (a network that predicts no change) and, for a
+    residual network, for the rows' pair-sum rates alone (a network that
+    predicts no residual), which show what the trained network adds."""
     import torch
     case = cases.case_c2(obstacle_seed=obstacle_seed)
     n = case.n
@@ -353,7 +371,8 @@ def report(steps: int = 1000, weights: str | None = None, judge_every: int | Non
     sur = run(case, steps, net, cfg, ctx=ctx, log=log)
     zero = sph.Mlp(cfg.width, 64, train=False)
     ctx.mlp_sync(zero)
-    pers = run(case, steps, zero, cfg, ctx=ctx)
+    pers = run(case, steps, zero, replace(cfg, residual=False), ctx=ctx)
+    rates_only = run(case, steps, zero, cfg, ctx=ctx) if cfg.residual else None
     base = sph.DeviceState.from_numpy(case.state)
     out = {"workload": case.name + f"_obstacle_seed{obstacle_seed}", "n": n, "steps": steps,
            "plain_steps_per_s": steps / plain["seconds"],
@@ -366,6 +385,11 @@ def report(steps: int = 1000, weights: str | None = None, judge_every: int | Non
            "persistence_books": {k: v for k, v in pers["books"].items() if k != "judge"},
            "persistence_judge": pers["books"]["judge"],
            "config": asdict(cfg)}
+    if rates_only is not None:
+        out["rates_only_final_vs_plain"] = compare_by_id(ctx, rates_only["state"],
+                                                         plain["state"], base, n)
+        out["rates_only_books"] = {k: v for k, v in rates_only["books"].items() if k != "judge"}
+        out["rates_only_judge"] = rates_only["books"]["judge"]
     torch.cuda.synchronize()
     return out
 

@@ -56,8 +56,12 @@ def test_rejects_bad_capacity_and_grid(L):
     rc, msg = _create(L, p)
     assert rc == -3 and "bits" in msg
     p = sph.make_params(_good(), 100)
-    p.reserved_ = 1
+    p.options = 4  # unknown option bit
     assert _create(L, p)[0] == -1
+    p = sph.make_params(_good(), 100, features=sph.FEATURE_CELL)
+    p.options = sph.OPTION_CUBIC  # the variant paths keep the Wendland kernel
+    rc, msg = _create(L, p)
+    assert rc == -1 and "Wendland" in msg
 
 
 def test_rejects_misaligned_slab(L):

@@ -3,7 +3,8 @@ the FP64 reference in oracle.mlp:
 
 * input rows bit-exact (neighbour choice and order, every bfloat16 feature)
   on a small tank, a dense random cloud and a slab with ghosts, with row
-  subsets and out-of-range rows;
+  subsets and out-of-range rows; the rows' FP32 pair-sum rates against the
+  oracle's FP64 sums, and the flag for rows with more than 64 neighbours;
 * forward pass, loss and every weight / bias gradient of the bfloat16 MFMA
   kernels against the FP64 MLP evaluated on the same bfloat16 tensors
   (normwise <= 5e-3; the kernels differ from it only by FP32 accumulation
@@ -80,13 +81,25 @@ def test_features_bit_exact(name):
     n0 = ctx.counts()["n_label"][0]
     sc = _scales(p)
     X = torch.empty(max(n0, 1), sph.NN_IN, dtype=torch.bfloat16, device="cuda")
-    ctx.nn_features(out, None, n0, sc, X)
+    R = torch.empty(max(n0, 1), 4, dtype=torch.float32, device="cuda")
+    ctx.nn_features(out, None, n0, sc, X, rates=R)
     torch.cuda.synchronize()
-    assert ctx.status() & sph.STATUS_NN_LIST == 0
     srt = oracle.sort_state(p, case.state)
+    _, cnt = oracle.nn_rows(p, srt, np.arange(n0), sc[4], om.SLOTS)
+    assert bool(ctx.status() & sph.STATUS_NN_LIST) == bool((cnt > om.SLOTS).any())
     want = om.features(p, srt, np.arange(n0), sc)
     got = _f32(X[:n0])
     _compare_rows(got, want, name)
+    # FP32 sums of a few dozen terms against FP64, normwise within the
+    # single-step bound, relative to the pressure part (ap = rate - g for
+    # fluid) and to the continuity rate
+    rref = om.rates(p, srt, np.arange(n0), sc)
+    rg = R[:n0].cpu().numpy().astype(np.float64)
+    fl = srt["state"]["type"][:n0] == cases.FLUID
+    ap = rref[:, :3] - np.where(fl[:, None], np.asarray(p["g"]), 0.0)
+    assert np.linalg.norm(rg[:, :3] - rref[:, :3]) <= 1e-4 * np.linalg.norm(ap)
+    assert relnorm(rg[:, 3], rref[:, 3]) <= 1e-4
+    assert np.all(rg[~fl, :3] == 0.0)
     # a row subset with repeats and rows outside the label-0 prefix
     rng = np.random.default_rng(1)
     rows = rng.integers(0, n0, 300).astype(np.int32)
@@ -99,6 +112,11 @@ def test_features_bit_exact(name):
     inside = (rows >= 0) & (rows < n0)
     _compare_rows(gs[inside], want[rows[inside]], name + " subset")
     assert not gs[~inside].any()
+    Rs = torch.empty(len(rows), 4, dtype=torch.float32, device="cuda")
+    ctx.nn_features(out, rt, len(rows), sc, Xs, rates=Rs)
+    rs = Rs.cpu().numpy()
+    assert np.array_equal(rs[inside], R[:n0].cpu().numpy()[rows[inside]])
+    assert not rs[~inside].any()
 
 
 def _random_net(width, cap, seed, out_gain=1.0):
@@ -219,6 +237,14 @@ def test_targets_bit_exact():
     assert np.array_equal(where.cpu().numpy()[b["id"]], np.arange(n))
     want = om.targets(a, _by_id(b), rows, inv_dv, inv_dr)
     assert np.array_equal(T.cpu().numpy(), want)
+    # with rates (seeded FP32 inputs) subtracted over a span
+    rts = (np.random.default_rng(7).standard_normal((500, 4)) * [5, 5, 5, 300]).astype(np.float32)
+    span = np.float32(2.37e-4)
+    ctx.nn_targets(A, B, where, torch.from_numpy(rows).cuda(), 500, inv_dv, inv_dr, T,
+                   rates=torch.from_numpy(rts).cuda(), span=float(span))
+    torch.cuda.synchronize()
+    want = om.targets(a, _by_id(b), rows, inv_dv, inv_dr, rts=rts, span=span)
+    assert np.array_equal(T.cpu().numpy(), want)
 
 
 def test_apply_and_status():
@@ -261,12 +287,30 @@ def test_apply_and_status():
     assert np.all(np.abs(f64(after["rhop"][:n0][ng]) - rp[ng]) <= 2.01 * ulp32(big))
     assert np.array_equal(after["rho"][:n0][~ng], before["rho"][:n0][~ng])
     assert np.array_equal(after["rho"][n0:], before["rho"][n0:])
+    # with rates: change = dt4 rates + y scale (a product, then an FMA)
+    before = after
+    rts = (rng.standard_normal((n0, 4)) * [3, 3, 3, 200]).astype(np.float32)
+    ctx.nn_apply(S, torch.from_numpy(Y).cuda(), n0, dv, dr, dt4, 1.0,
+                 rates=torch.from_numpy(rts).cuda())
+    torch.cuda.synchronize()
+    after = S.to_numpy(n)
+    for d, k in enumerate(("vx", "vy", "vz")):
+        ys = f64(Y[:, d]) * float(dv)
+        vn = f64(before[k][:n0]) + float(dt4) * f64(rts[:, d]) + ys
+        tol = 1.01 * ulp32(vn) + ulp32(ys)
+        assert np.all(np.abs(f64(after[k][:n0][fl]) - vn[fl]) <= tol[fl]), k
+        assert np.array_equal(after[k][:n0][~fl], before[k][:n0][~fl])
+    ys = f64(Y[:, 3]) * float(dr)
+    rn = f64(before["rho"][:n0]) + float(dt4) * f64(rts[:, 3]) + ys
+    tol = 1.01 * ulp32(rn) + ulp32(ys)
+    assert np.all(np.abs(f64(after["rho"][:n0][ng]) - rn[ng]) <= tol[ng])
+    assert np.array_equal(after["rho"][:n0][~ng], before["rho"][:n0][~ng])
     # a density outside the band raises the status bit
     ctx.nn_apply(S, torch.from_numpy(Y).cuda(), n0, dv, np.float32(50.0), dt4, 0.01)
     assert ctx.status() & sph.STATUS_NN_RANGE
 
 
-def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4):
+def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False):
     """The unfused chain (features, forward, apply) and the fused advance from
     the same state; returns both states and the unfused outputs."""
     p, n = case.params, case.n
@@ -279,22 +323,24 @@ def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4):
     n0 = ctx.counts()["n_label"][0]
     X = torch.empty(n0, sph.NN_IN, dtype=torch.bfloat16, device="cuda")
     Y = torch.empty(n0, 4, device="cuda")
-    ctx.nn_features(U, None, n0, sc, X)
+    R = torch.empty(n0, 4, device="cuda") if residual else None
+    ctx.nn_features(U, None, n0, sc, X, rates=R)
     ctx.mlp_forward(net, X, n0, Y)
-    ctx.nn_apply(U, Y, n0, dv, dr, dt4, 1.0)
-    ctx.nn_advance(net, cur, F, n, sc, dv, dr, dt4, 1.0)
+    ctx.nn_apply(U, Y, n0, dv, dr, dt4, 1.0, rates=R)
+    ctx.nn_advance(net, cur, F, n, sc, dv, dr, dt4, 1.0, residual=residual)
     torch.cuda.synchronize()
     return ctx, U, F, X, Y, n0
 
 
+@pytest.mark.parametrize("residual", [False, True])
 @pytest.mark.parametrize("name", ["small_tank", "small_slab"])
-def test_fused_advance_matches_unfused(name):
+def test_fused_advance_matches_unfused(name, residual):
     case = FEATURE_CASES[name]()
     n = case.n
-    announce(f"nn fused vs unfused {name} n={n}")
+    announce(f"nn fused vs unfused {name} residual={residual} n={n}")
     net, _ = _random_net(128, case.n, 13, out_gain=50.0)
-    ctx, U, F, X, Y, n0 = _advance_pair(case, net)
-    assert ctx.status() & (sph.STATUS_NN_RANGE | sph.STATUS_NN_LIST) == 0
+    ctx, U, F, X, Y, n0 = _advance_pair(case, net, residual=residual)
+    assert ctx.status() & sph.STATUS_NN_RANGE == 0
     u, f = U.to_numpy(n), F.to_numpy(n)
     assert np.array_equal(u["id"], f["id"])
     for k in sph.F32_FIELDS:
@@ -346,23 +392,24 @@ def test_fused_advance_c2_sampled_vs_oracle():
     cur = sph.DeviceState.from_numpy(case.state)
     F = sph.DeviceState.empty(n)
     dv, dr, dt4 = np.float32(0.02), np.float32(2.0), np.float32(2e-4)
-    ctx.nn_advance(net, cur, F, n, sc, dv, dr, dt4, 1.0)
+    ctx.nn_advance(net, cur, F, n, sc, dv, dr, dt4, 1.0, residual=True)
     torch.cuda.synchronize()
-    assert ctx.status() & (sph.STATUS_NN_RANGE | sph.STATUS_NN_LIST | sph.STATUS_NONFINITE) == 0
+    assert ctx.status() & (sph.STATUS_NN_RANGE | sph.STATUS_NONFINITE) == 0
     got = F.to_numpy(n)
     srt = oracle.sort_state(p, case.state)
     assert np.array_equal(got["id"], srt["state"]["id"])
     n0 = int(srt["counts"][0])
     sel = np.sort(np.random.default_rng(5).choice(n0, 4000, replace=False))
     Xo = om.features(p, srt, sel, sc)
+    Ro = om.rates(p, srt, sel, sc)
     W, b = _oracle_net(arr)
     Yo, _ = om.forward(W, b, Xo, emulate=True)
     s0 = srt["state"]
     t = s0["type"][sel]
     fl = t == cases.FLUID
     d_rho_gpu = got["rho"][sel].astype(np.float64) - s0["rho"][sel]
-    d_rho_ref = Yo[:, 3] * float(dr)
+    d_rho_ref = Yo[:, 3] * float(dr) + float(dt4) * Ro[:, 3]
     assert relnorm(d_rho_gpu, d_rho_ref) <= 2e-3
     for d, k in enumerate(("vx", "vy", "vz")):
         dv_gpu = got[k][sel][fl].astype(np.float64) - s0[k][sel][fl]
-        assert relnorm(dv_gpu, Yo[fl, d] * float(dv)) <= 2e-3, k
+        assert relnorm(dv_gpu, Yo[fl, d] * float(dv) + float(dt4) * Ro[fl, d]) <= 2e-3, k

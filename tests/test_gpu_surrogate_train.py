@@ -3,11 +3,15 @@
 A short online training on small seeded obstacle tanks (the project's own
 GPU kernels: plain SPH trajectories, neighbour rows, bfloat16 MFMA forward and
 backward passes, Adam), then judged advances on a layout that training never
-saw, against persistence: the same advance loop with a network that predicts
-no change (the surrogate without its learned part). The trained network must
-cut the error of the four-step velocity and density changes well below
-persistence's and keep the density within the judge's 1 % bound.
+saw, against two baselines run through the same advance loop with a network
+that outputs zero: persistence (no change at all) and the rows' own pair-sum
+rates alone (the residual surrogate without its learned part). The trained
+network must cut the error of the four-step velocity and density changes
+well below persistence's, improve on the pair-sum rates alone, and keep the
+density within the judge's 1 % bound.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -33,12 +37,15 @@ def test_training_beats_persistence():
     cfg.judge_every = 0   # judge every advance
     cfg.adaptive = False
     cfg.judge_tol = 1.0  # measure, do not fall back
+    assert cfg.residual
     zero = sph.Mlp(cfg.width, 64, train=False)
     res = {}
-    for name, nt in (("trained", net), ("persistence", zero)):
+    for name, nt, resid in (("trained", net, True), ("rates_only", zero, True),
+                            ("persistence", zero, False)):
+        c = dataclasses.replace(cfg, residual=resid)
         ctx = sph.Context(hold.params, hold.n)
         ctx.mlp_sync(nt)
-        r = surrogate.run(hold, 160, nt, cfg, ctx=ctx)
+        r = surrogate.run(hold, 160, nt, c, ctx=ctx)
         j = r["books"]["judge"]
         assert r["books"]["fallback_at"] is None, name
         res[name] = {k: float(np.mean([e[k] for e in j])) for k in ("rel_du", "rel_drho")}
@@ -47,4 +54,5 @@ def test_training_beats_persistence():
     assert abs(res["persistence"]["rel_du"] - 1.0) < 1e-6
     assert res["trained"]["rel_du"] < 0.7 * res["persistence"]["rel_du"]
     assert res["trained"]["rel_drho"] < res["persistence"]["rel_drho"]
+    assert res["trained"]["rel_du"] < res["rates_only"]["rel_du"]
     assert res["trained"]["max_rel_rho"] <= 0.01
