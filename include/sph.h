@@ -100,10 +100,19 @@ typedef struct sph_params {
  *                    for 1 <= q < 2, aD = 1/(pi h^3), q = r/h;
  *   SPH_O_RHO_FLOOR  a boundary particle's density is raised to rho0 after
  *                    each update when it falls below (dynamic boundaries of
- *                    Sec. 2.3; a common practice, not in the paper). */
+ *                    Sec. 2.3; a common practice, not in the paper);
+ *   SPH_O_SYMPLECTIC sph_step integrates with a symplectic kick-drift
+ *                    position-Verlet scheme instead of the Verlet scheme of
+ *                    Sec. 3.3: with dt from the rates at n, a half step
+ *                    r + dt/2 v, v + dt/2 a, rho + dt/2 D, the rates of that
+ *                    half state (same cell tables), then v' = v + dt a_h,
+ *                    r' = r + dt (v + v')/2, rho' = rho (2 - e)/(2 + e) with
+ *                    e = -(D_h/rho_h) dt. Two interactions per step;
+ *                    sph_update is then refused (SPH_E_STATE). */
 enum {
     SPH_O_CUBIC = 1u << 0,
-    SPH_O_RHO_FLOOR = 1u << 1
+    SPH_O_RHO_FLOOR = 1u << 1,
+    SPH_O_SYMPLECTIC = 1u << 2
 };
 
 /* Feature bits of sph_params.features. */

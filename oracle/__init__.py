@@ -66,6 +66,8 @@ def lib():
         L.orc_kernel_w.restype = C.c_double
         L.orc_kernel_f.argtypes = [C.c_double, C.c_double]
         L.orc_kernel_f.restype = C.c_double
+        L.orc_symplectic_half.argtypes = [pp, C.c_int64, C.c_double, u8] + [d] * 18
+        L.orc_symplectic_full.argtypes = [pp, C.c_int64, C.c_double, u8] + [d] * 16
         for f in ("orc_cubic_w", "orc_cubic_f"):
             getattr(L, f).argtypes = [C.c_double, C.c_double]
             getattr(L, f).restype = C.c_double
@@ -354,14 +356,52 @@ def verlet(p: dict, st: dict, n0: int, step: int, dtv: float, acc: dict) -> dict
     return s
 
 
+OPTION_SYMPLECTIC = 4
+
+
+def symplectic_half(p: dict, st: dict, n0: int, dtv: float, acc: dict) -> dict:
+    """Half step of the symplectic variant: a copy of the FP64 sorted state
+    with (r, v, rho) at n + 1/2 (see orc_symplectic_half)."""
+    s = {k: v.copy() for k, v in st.items()}
+    a = {k: np.ascontiguousarray(acc[k], dtype=np.float64) for k in ("ax", "ay", "az", "drho")}
+    lib().orc_symplectic_half(C.byref(make_params(p)), int(n0), float(dtv),
+                              _ptr(st["type"], C.c_uint8),
+                              *[_d(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "rho")],
+                              _d(a["ax"]), _d(a["ay"]), _d(a["az"]), _d(a["drho"]),
+                              *[_d(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "rho")])
+    return s
+
+
+def symplectic_full(p: dict, st: dict, half: dict, n0: int, dtv: float, acc_h: dict) -> dict:
+    """Full step of the symplectic variant from the state at n and the rates
+    of the half state (in place on a copy of ``st``)."""
+    s = {k: v.copy() for k, v in st.items()}
+    a = {k: np.ascontiguousarray(acc_h[k], dtype=np.float64) for k in ("ax", "ay", "az", "drho")}
+    lib().orc_symplectic_full(C.byref(make_params(p)), int(n0), float(dtv),
+                              _ptr(s["type"], C.c_uint8), *[_d(s[k]) for k in F32_FIELDS],
+                              _d(np.ascontiguousarray(half["rho"], dtype=np.float64)),
+                              _d(a["ax"]), _d(a["ay"]), _d(a["az"]), _d(a["drho"]))
+    return s
+
+
 def step(p: dict, st: dict, step_index: int, dt_override: float | None = None) -> dict:
-    """One full time step: sort (a1-a5), interaction (b1-b3), dt (c1), Verlet (c2).
+    """One full time step: sort (a1-a5), interaction (b1-b3), dt (c1), Verlet (c2);
+    with the symplectic option, a half step, the interaction of the half state
+    (same cell tables) and the full step in place of the Verlet update.
 
     Returns dict(state=new sorted FP64 state, srt=sort products, acc=rates,
-    dt=dt used, dt_cfl=CFL dt, pairs=total neighbour pairs)."""
+    dt=dt used, dt_cfl=CFL dt, pairs=total neighbour pairs) and, for the
+    symplectic option, half (the half state) and acc_half (its rates)."""
     srt = sort_state(p, st)
     acc = interact(p, srt)
     dtc = dt(p, srt, acc)
     dtv = dtc if dt_override is None else float(dt_override)
-    new = verlet(p, srt["state"], int(srt["counts"][0]), step_index, dtv, acc)
+    n0 = int(srt["counts"][0])
+    if int(p.get("options", 0)) & OPTION_SYMPLECTIC:
+        half = symplectic_half(p, srt["state"], n0, dtv, acc)
+        acc_h = interact(p, dict(srt, state=half))
+        new = symplectic_full(p, srt["state"], half, n0, dtv, acc_h)
+        return dict(state=new, srt=srt, acc=acc, dt=dtv, dt_cfl=dtc, half=half, acc_half=acc_h,
+                    pairs=int(acc_h["npair"].sum()))
+    new = verlet(p, srt["state"], n0, step_index, dtv, acc)
     return dict(state=new, srt=srt, acc=acc, dt=dtv, dt_cfl=dtc, pairs=int(acc["npair"].sum()))

@@ -42,9 +42,10 @@ typedef struct {
 } orc_params;
 
 /* Variants of the plain step: the cubic spline kernel of Sec. 2.2 in place of
- * Wendland C2, and a density floor rho >= rho0 for boundary particles after
- * each update (a common practice with dynamic boundaries, not in the paper). */
-enum { OPT_CUBIC = 1, OPT_RHO_FLOOR = 2 };
+ * Wendland C2, a density floor rho >= rho0 for boundary particles after each
+ * update (a common practice with dynamic boundaries, not in the paper), and a
+ * symplectic integrator in place of the Verlet scheme of Sec. 3.3. */
+enum { OPT_CUBIC = 1, OPT_RHO_FLOOR = 2, OPT_SYMPLECTIC = 4 };
 
 int orc_abi_version(void) { return 1; }
 
@@ -565,6 +566,77 @@ void orc_verlet(const orc_params *p, int64_t n0, int64_t step, double dt,
         z[i] += dt * v[2] + 0.5 * dt * dt * a[2];
         vxp[i] = v[0]; vyp[i] = v[1]; vzp[i] = v[2];
         vx[i] = vn[0]; vy[i] = vn[1]; vz[i] = vn[2];
+    }
+}
+
+/* ----------------------------------------------- symplectic variant (c2) */
+
+/*
+ * Symplectic position-Verlet step (kick-drift form of Leimkuhler, Reich and
+ * Skeel, as used in SPH codes of the paper's family; an alternative to the
+ * Verlet scheme of Sec. 3.3, not in the paper), with dt from the rates at n:
+ *   half step:  rho_h = rho + dt/2 D,  and for fluid
+ *               r_h = r + dt/2 v,  v_h = v + dt/2 a;
+ *   rates a_h, D_h of the half state (orc_interact on it);
+ *   full step:  for fluid  v' = v + dt a_h,  r' = r + dt (v + v')/2;
+ *               rho' = rho (2 - e) / (2 + e) with e = -(D_h / rho_h) dt
+ *               (the exact integral of drho/rho = (D_h/rho_h) dt over a step,
+ *               to second order, which keeps rho positive);
+ *   then (v_prev, rho_prev) <- (v, rho) at n.
+ * Boundary particles move nothing and update rho (Sec. 2.3); ghosts are not
+ * updated. OPT_RHO_FLOOR applies to the full step's boundary density.
+ */
+void orc_symplectic_half(const orc_params *p, int64_t n0, double dt, const uint8_t *type,
+                         const double *x, const double *y, const double *z, const double *vx,
+                         const double *vy, const double *vz, const double *rho,
+                         const double *ax, const double *ay, const double *az,
+                         const double *drho, double *xh, double *yh, double *zh, double *vxh,
+                         double *vyh, double *vzh, double *rhoh)
+{
+    (void)p;
+    const double hdt = 0.5 * dt;
+    for (int64_t i = 0; i < n0; i++) {
+        xh[i] = x[i]; yh[i] = y[i]; zh[i] = z[i];
+        vxh[i] = vx[i]; vyh[i] = vy[i]; vzh[i] = vz[i];
+        rhoh[i] = rho[i];
+        if (type[i] == T_GHOST) continue;
+        rhoh[i] = rho[i] + hdt * drho[i];
+        if (type[i] != T_FLUID) continue;
+        xh[i] = x[i] + hdt * vx[i];
+        yh[i] = y[i] + hdt * vy[i];
+        zh[i] = z[i] + hdt * vz[i];
+        vxh[i] = vx[i] + hdt * ax[i];
+        vyh[i] = vy[i] + hdt * ay[i];
+        vzh[i] = vz[i] + hdt * az[i];
+    }
+}
+
+void orc_symplectic_full(const orc_params *p, int64_t n0, double dt, const uint8_t *type,
+                         double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                         double *rho, double *vxp, double *vyp, double *vzp, double *rhop,
+                         const double *rhoh, const double *axh, const double *ayh,
+                         const double *azh, const double *drhoh)
+{
+    for (int64_t i = 0; i < n0; i++) {
+        if (type[i] == T_GHOST) continue;
+        const double e = -(drhoh[i] / rhoh[i]) * dt;
+        double r_new = rho[i] * (2.0 - e) / (2.0 + e);
+        if ((p->options & OPT_RHO_FLOOR) && type[i] == T_BOUNDARY && r_new < p->rho0)
+            r_new = p->rho0;
+        rhop[i] = rho[i];
+        rho[i] = r_new;
+        if (type[i] != T_FLUID) continue;
+        double *v[3] = {&vx[i], &vy[i], &vz[i]};
+        double *r[3] = {&x[i], &y[i], &z[i]};
+        double *vp[3] = {&vxp[i], &vyp[i], &vzp[i]};
+        const double a[3] = {axh[i], ayh[i], azh[i]};
+        for (int d = 0; d < 3; d++) {
+            const double v0 = *v[d];
+            const double v1 = v0 + dt * a[d];
+            *r[d] += dt * 0.5 * (v0 + v1);
+            *vp[d] = v0;
+            *v[d] = v1;
+        }
     }
 }
 

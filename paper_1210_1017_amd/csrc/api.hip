@@ -104,7 +104,7 @@ int sph_create(const sph_params *p, sph_ctx **out) {
         return fail(nullptr, SPH_E_INVALID_ARG, "physical parameters must be positive");
     if (p->gamma != 7.0)
         return fail(nullptr, SPH_E_INVALID_ARG, "gamma must be 7 (Tait law of the method)");
-    if ((p->options & ~(int32_t)(SPH_O_CUBIC | SPH_O_RHO_FLOOR)) != 0 ||
+    if ((p->options & ~(int32_t)(SPH_O_CUBIC | SPH_O_RHO_FLOOR | SPH_O_SYMPLECTIC)) != 0 ||
         (p->features & ~(uint32_t)(SPH_F_CELL | SPH_F_FP64)) != 0)
         return fail(nullptr, SPH_E_INVALID_ARG, "unknown option or feature bits");
     if (p->options != 0 && p->features != 0)
@@ -283,6 +283,7 @@ int sph_interact(sph_ctx *c, const sph_soa *sorted, uint32_t n, const sph_rates 
     if (e == hipSuccess) e = launch_interact(c, sorted->type, n, *out, s);
     if (e != hipSuccess) return hip_fail(c, e, "interaction");
     c->have_dt = true;
+    c->dt_in_info = false;
     return SPH_OK;
 }
 
@@ -293,6 +294,8 @@ int sph_update(sph_ctx *c, sph_soa *sorted, const sph_rates *rates, uint32_t n, 
     if (!soa_ok(sorted) || !rates_ok(rates)) return fail(c, SPH_E_INVALID_ARG, "null array");
     if (!c->have_dt || n != c->sorted_n || c->last_path != 0)
         return fail(c, SPH_E_STATE, "sph_update needs a preceding sph_interact of the same n");
+    if (c->kp.options & SPH_O_SYMPLECTIC)
+        return fail(c, SPH_E_STATE, "the symplectic step needs two interactions: use sph_step");
     hipError_t e = launch_update(c, *sorted, rates->ax, rates->ay, rates->az, rates->arho, n, step,
                                  (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "update");
@@ -319,11 +322,22 @@ int sph_step(sph_ctx *c, const sph_soa *cur, sph_soa *next, uint32_t n, uint64_t
     const size_t cap = c->capacity;
     sph_rates rt = {c->rate, c->rate + cap, c->rate + 2 * cap, c->rate + 3 * cap,
                     nullptr, nullptr, nullptr};
-    hipError_t e = launch_interact(c, next->type, n, rt, s, ev ? ev[2] : nullptr);
-    if (e == hipSuccess) e = launch_update(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, step, s);
+    hipError_t e;
+    if (c->kp.options & SPH_O_SYMPLECTIC) {
+        // rates at n (and the CFL limits), half state into the packed inputs,
+        // rates of the half state on the same cell tables, full step
+        e = launch_interact(c, next->type, n, rt, s);
+        if (e == hipSuccess) e = launch_sym_half(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, s);
+        if (e == hipSuccess) e = launch_interact(c, next->type, n, rt, s, ev ? ev[2] : nullptr);
+        if (e == hipSuccess) e = launch_sym_full(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, s);
+    } else {
+        e = launch_interact(c, next->type, n, rt, s, ev ? ev[2] : nullptr);
+        if (e == hipSuccess) e = launch_update(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, step, s);
+    }
     if (ev) (void)hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(c, e, "step");
     c->have_dt = true;
+    c->dt_in_info = (c->kp.options & SPH_O_SYMPLECTIC) != 0;
     return SPH_OK;
 }
 
@@ -363,6 +377,10 @@ int sph_get_dt(sph_ctx *c, float *dt, void *stream) {
         double m64;
         memcpy(&m64, &h.dtmin64_bits, sizeof m64);
         *dt = (float)((double)c->kp.cfl * m64);
+        return SPH_OK;
+    }
+    if (c->dt_in_info) {  // symplectic step: the dt its half step formed and used
+        *dt = h.dt;
         return SPH_OK;
     }
     // the same FP32 product as the update kernel forms: CFL * min limit

@@ -556,8 +556,10 @@ __device__ __forceinline__ void nn_apply_one(const KParams &kp, const sph_soa &s
                                              const NnApply &ap, uint32_t *flags) {
     const uint8_t t = st.type[k];
     if (t == kGhost) return;
+    // rho + dt4 rate + y scale: with no rates (rt = 0) the inner FMA is exact
+    // and the result one rounding of rho + y scale
     const float dr = fmaf(ap.dt4, rt.w, y3 * ap.dr_scale);
-    const float rn = st.rho[k] + dr;
+    const float rn = fmaf(y3, ap.dr_scale, fmaf(ap.dt4, rt.w, st.rho[k]));
     st.rho[k] = rn;
     st.rhop[k] = rn - 0.25f * dr;
     bool ok = isfinite(rn) && fabsf(rn * kp.inv_rho0 - 1.0f) <= ap.rho_tol;
@@ -571,7 +573,7 @@ __device__ __forceinline__ void nn_apply_one(const KParams &kp, const sph_soa &s
         for (int d = 0; d < 3; d++) {
             const float v = vel[d][k];
             const float dv = fmaf(ap.dt4, b[d], y[d] * ap.dv_scale);
-            const float vn = v + dv;
+            const float vn = fmaf(y[d], ap.dv_scale, fmaf(ap.dt4, b[d], v));
             const float xn = pos[d][k] + ap.dt4 * 0.5f * (v + vn);
             pos[d][k] = xn;
             vel[d][k] = vn;

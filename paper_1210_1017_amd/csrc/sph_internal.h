@@ -88,6 +88,7 @@ struct sph_ctx {
     size_t nn_x_rows = 0;
     uint32_t tot_blocks = 0;
     int last_path = 0;            // 0 plain, 1 cell, 2 FP64: which state the tables describe
+    bool dt_in_info = false;      // the last step was symplectic: its dt is info->dt
     // optional per-phase timing of sph_step (events: start, sorted, interacted, updated)
     hipEvent_t *events = nullptr;
     uint32_t ev_slots = 0, ev_used = 0;
@@ -183,6 +184,10 @@ hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, 
                                float dr_scale, float dt4, float rho_tol, hipStream_t stream);
 
 // update.hip
+hipError_t launch_sym_half(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
+                           const float *az, const float *arho, uint32_t n, hipStream_t s);
+hipError_t launch_sym_full(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
+                           const float *az, const float *arho, uint32_t n, hipStream_t s);
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
                          const float *az, const float *arho, uint32_t n, uint64_t step,
                          hipStream_t s);

@@ -56,7 +56,7 @@ def test_rejects_bad_capacity_and_grid(L):
     rc, msg = _create(L, p)
     assert rc == -3 and "bits" in msg
     p = sph.make_params(_good(), 100)
-    p.options = 4  # unknown option bit
+    p.options = 8  # unknown option bit
     assert _create(L, p)[0] == -1
     p = sph.make_params(_good(), 100, features=sph.FEATURE_CELL)
     p.options = sph.OPTION_CUBIC  # the variant paths keep the Wendland kernel

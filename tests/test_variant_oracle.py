@@ -6,7 +6,10 @@ support, monotone decrease) and against its textbook values; its gradient
 factor against a numerical derivative of W and against the divergence
 identity that every normalised kernel satisfies; the interaction with it
 against a finite-difference gradient of W and against momentum conservation.
-The boundary density floor against its definition on hand-made states.
+The boundary density floor against its definition on hand-made states. The
+symplectic integrator against free fall (exact), its order of accuracy on a
+harmonic oscillator and on exponential density growth, the bounded energy
+error of a symplectic map, and the roles of boundary and ghost particles.
 """
 import math
 
@@ -141,3 +144,101 @@ def test_boundary_density_floor(orc):
     assert plain["rho"][2] == fl["rho"][2] == pytest.approx(998.0)  # fluid: no floor
     assert plain["rho"][3] == fl["rho"][3] == 990.0                 # ghost: untouched
     assert fl["rhop"][0] == 1000.5  # the previous value rotates as usual
+
+
+# ------------------------------------------------------- symplectic step
+
+def _sym(p, extra=0):
+    q = dict(p)
+    q["options"] = 4 | extra
+    return q
+
+
+def _one_particle_state(pos, vel, typ=0, rho=1000.0):
+    st = cases._make_state(np.array([pos], dtype=float), np.array([typ]), np.array([rho]),
+                           np.array([vel], dtype=float))
+    return st
+
+
+def test_symplectic_free_fall_exact(orc):
+    """An isolated fluid particle: v' = v + dt g and r' = r + dt v + dt^2 g / 2
+    exactly (the half-step rate equals the full-step rate)."""
+    p = _sym(cases.base_params(0.02))
+    cases.set_grid(p, (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    st = _one_particle_state((0.1, 0.2, 0.3), (0.5, -0.25, 1.0))
+    dtv = 1e-3
+    r = orc.step(p, st, 0, dt_override=dtv)
+    s = r["state"]
+    g = np.array(p["g"])
+    x0, z0 = float(st["x"][0]), float(st["z"][0])  # the FP32 inputs
+    assert abs(s["vz"][0] - (1.0 + dtv * g[2])) <= 1e-15
+    assert abs(s["z"][0] - (z0 + dtv * 1.0 + 0.5 * dtv * dtv * g[2])) <= 1e-15
+    assert abs(s["x"][0] - (x0 + 0.5 * dtv)) <= 1e-15
+    assert s["vzp"][0] == np.float32(1.0) and s["rho"][0] == 1000.0
+
+
+def _oscillator(orc, p, dt, T, omega, rate_from="half"):
+    """Drive the oracle's half and full steps with a = -omega^2 x and
+    D = k rho; returns (x, v, rho) after T."""
+    n = int(round(T / dt))
+    st = orc.to_f64(_one_particle_state((1.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    k = 0.5
+    for _ in range(n):
+        acc = dict(ax=-omega ** 2 * st["x"], ay=np.zeros(1), az=np.zeros(1), drho=k * st["rho"])
+        half = orc.symplectic_half(p, st, 1, dt, acc)
+        src = half if rate_from == "half" else st
+        acc_h = dict(ax=-omega ** 2 * src["x"], ay=np.zeros(1), az=np.zeros(1),
+                     drho=k * src["rho"])
+        st = orc.symplectic_full(p, st, half, 1, dt, acc_h)
+    return float(st["x"][0]), float(st["vx"][0]), float(st["rho"][0]), k
+
+
+def test_symplectic_second_order_and_energy(orc):
+    """Harmonic oscillator x'' = -w^2 x and exponential density rho' = k rho:
+    halving dt cuts the error at T = 2 by 4 (second order) for x and for rho
+    (against exp(kT)); the oscillator's energy stays bounded over 200
+    periods (no drift, as for a symplectic map)."""
+    p = _sym(cases.base_params(0.02))
+    w, T = 3.0, 2.0
+    errs, rerrs = [], []
+    for dt in (0.02, 0.01, 0.005):
+        x, v, rho, k = _oscillator(orc, p, dt, T, w)
+        errs.append(abs(x - math.cos(w * T)))
+        rerrs.append(abs(rho - 1000.0 * math.exp(k * T)))
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert 3.5 < a / b < 4.5, errs
+    for a, b in zip(rerrs[:-1], rerrs[1:]):
+        assert 3.5 < a / b < 4.5, rerrs
+    # a plausible slip: taking the full step's rates from n, not n + 1/2
+    e1 = [abs(_oscillator(orc, p, dt, T, w, "n")[0] - math.cos(w * T)) for dt in (0.01, 0.005)]
+    assert e1[0] / e1[1] < 2.5
+    # long run: energy error bounded and small
+    x, v, _, _ = _oscillator(orc, p, 0.02, 200 * 2 * math.pi / w, w)
+    E = 0.5 * v * v + 0.5 * w * w * x * x
+    assert abs(E / (0.5 * w * w) - 1.0) < 0.01
+
+
+def test_symplectic_boundary_and_ghost_roles(orc):
+    """Boundary particles keep r and v and update rho; ghosts are untouched;
+    the floor option applies to the full step's boundary density."""
+    p = cases.base_params(0.02)
+    st = orc.to_f64(cases._make_state(np.array([[0.0, 0, 0], [1, 1, 1], [2, 2, 2]]),
+                                      np.array([0, 1, 2]), np.array([1000.0, 1000.2, 995.0]),
+                                      np.array([[0.125, 0.25, 0.375]] * 3)))
+    acc = dict(ax=np.full(3, 0.5), ay=np.zeros(3), az=np.zeros(3), drho=np.full(3, -400.0))
+    for opt, floor in ((4, False), (6, True)):
+        q = dict(p)
+        q["options"] = opt
+        half = orc.symplectic_half(q, st, 3, 1e-3, acc)
+        new = orc.symplectic_full(q, st, half, 3, 1e-3, acc)
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            assert new[k][1] == st[k][1] and half[k][1] == st[k][1], k
+        for k in new:
+            assert np.array_equal(new[k][2:], st[k][2:]), k
+        assert half["rho"][1] == pytest.approx(1000.0)
+        r0 = float(st["rho"][1])  # the FP32 input 1000.2
+        e = 400.0 / float(half["rho"][1]) * 1e-3
+        want = r0 * (2 - e) / (2 + e)
+        assert new["rho"][1] == (1000.0 if floor else pytest.approx(want, rel=1e-15))
+        assert new["rhop"][1] == r0
+        assert new["vx"][0] == pytest.approx(0.125 + 0.5e-3) and new["vxp"][0] == 0.125
