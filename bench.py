@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 # continuity sum 2, mu 4, |mu| max 1, c_j 3, viscous term 6, pressure sum 2,
 # force factor 1, three force sums 6.
 FLOP_PER_PAIR = 47
+# The cubic spline's gradient factor in place of Wendland's (1 - q/2, its
+# cube: 4): q 1, 2 - q 1, square 1, reciprocal 1 and product 1, 4 - 3q 2.
+FLOP_PER_PAIR_CUBIC = FLOP_PER_PAIR - 4 + 7
 # FP32 work of one support test of a candidate j: separation 3, r^2 5.
 FLOP_PER_CANDIDATE = 8
 # Compulsory HBM bytes of the interaction per in-domain particle: read x, y, z,
@@ -96,6 +99,54 @@ def copy_probe(mib: int, reps: int) -> None:
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
                       "reps": reps}), flush=True)
+
+
+def variants(case, steps: int, warmup: int = 10) -> dict:
+    """Steps/s and pair interactions/s of the step variants (sph_params.options)
+    on the same workload, each from the initial state; the interaction phase
+    (both interactions and the half step for the symplectic integrator) by
+    HIP events on the step's stream."""
+    import torch
+
+    from paper_1210_1017_amd import sph
+    out = {}
+    n = case.n
+    for name, opts in (("cubic", sph.OPTION_CUBIC), ("symplectic", sph.OPTION_SYMPLECTIC),
+                       ("cubic_symplectic", sph.OPTION_CUBIC | sph.OPTION_SYMPLECTIC)):
+        p = dict(case.params)
+        p["options"] = opts
+        ctx = sph.Context(p, n)
+        a = sph.DeviceState.from_numpy(case.state, capacity=n)
+        b = sph.DeviceState.empty(n)
+        for s in range(warmup):
+            ctx.step(a, b, n, s)
+            a, b = b, a
+        torch.cuda.synchronize()
+        pairs0, cand0 = ctx.pair_total(), ctx.candidate_total()
+        ctx.timing_begin(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(warmup, warmup + steps):
+            ctx.step(a, b, n, s)
+            a, b = b, a
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ph = ctx.timing_read(steps)
+        ctx.timing_begin(0)
+        inter = 2 if opts & sph.OPTION_SYMPLECTIC else 1
+        pairs = ctx.pair_total() - pairs0
+        cand = ctx.candidate_total() - cand0
+        fpp = FLOP_PER_PAIR_CUBIC if opts & sph.OPTION_CUBIC else FLOP_PER_PAIR
+        t_int = float(ph[:, 1].mean()) * 1e-3
+        flop = fpp * pairs / steps + FLOP_PER_CANDIDATE * cand / steps
+        out[name] = {"options": opts, "steps": steps, "ms_per_step": el / steps * 1e3,
+                     "steps_per_s": steps / el, "pair_interactions_per_s": pairs / el,
+                     "interactions_per_step": inter, "interact_phase_ms": t_int * 1e3,
+                     "alu_frac_interact_phase": flop / t_int / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+                     "status": ctx.status()}
+        print(f"[bench] variant {name}: {out[name]}", file=sys.stderr, flush=True)
+        del ctx, a, b
+    return out
 
 
 def _by_id(arrs: dict, ids):
@@ -224,6 +275,9 @@ def main() -> int:
     ap.add_argument("--report-case", default="c4", choices=["c4", "c2"])
     ap.add_argument("--report-steps", type=int, default=10000)
     ap.add_argument("--fp64-steps", type=int, default=10000)
+    ap.add_argument("--variant-steps", type=int, default=200,
+                    help="timed steps of each step variant (cubic kernel, symplectic "
+                         "integrator) added to the JSON line (0: skip)")
     ap.add_argument("--surrogate-steps", type=int, default=1000,
                     help="steps of the surrogate-vs-plain comparison added to the JSON line "
                          "when trained weights are present (0: skip)")
@@ -304,6 +358,8 @@ def main() -> int:
                      "dt_update": float(phases[:, 2].mean())},
         "roofline": roof,
     }
+    if args.variant_steps > 0:
+        out["variants"] = variants(case, args.variant_steps)
     from paper_1210_1017_amd import surrogate
     wpath = surrogate.default_weights()
     if args.surrogate_steps > 0 and os.path.exists(wpath):

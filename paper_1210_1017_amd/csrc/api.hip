@@ -67,7 +67,7 @@ void free_all(sph_ctx *c) {
     for (void *p : vptrs)
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
-                    c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->cell_blockmin, c->pos4, c->vel4,
+                    c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->pos4, c->vel4,
                     c->rate, c->info};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -193,7 +193,6 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     ALLOC(c->digit_tot, 256 * 4);
     ALLOC(c->cell_begin, (size_t)ncells * 4);
     ALLOC(c->cell_end, (size_t)ncells * 4);
-    ALLOC(c->cell_blockmin, (size_t)((ncells + kCellScanBlock - 1) / kCellScanBlock) * 4);
     ALLOC(c->pos4, cap * sizeof(float4));
     ALLOC(c->vel4, cap * sizeof(float4));
     ALLOC(c->rate, cap * 4 * sizeof(float));

@@ -207,135 +207,76 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
 
 // ---------------------------------------------------- counts and ranges
 // Cell tables over the label-0 prefix of the sorted keys (Sec. 3.1 first
-// index of each cell; Sec. 4.4 first and last of a region) and label counts:
-//   k_fill:        begin[c] = EMPTY for every cell;
-//   k_mark:        thread k marks the label boundaries around k (label starts
-//                  lstart[l] = lower_bound(l << Bc)) and, for label 0, the first
-//                  and one-past-last index of k's cell;
-//   k_cells_min:   per block of cells, the minimum begin (EMPTY if all empty);
-//   k_cells_carry: suffix minimum over the blocks (n0 past the last one);
-//   k_cells_apply: an empty cell c gets begin = end = min over cells >= c of
-//                  begin, i.e. lower_bound(c) (begins rise with the cell index);
-//   k_counts:      label counts, and the packing ranges of x-layers 0, 1,
-//                  ncx-2, ncx-1 read off begin[] (each layer is one contiguous
-//                  range of the x-major order, Sec. 4.2-4.3).
-constexpr uint32_t kEmpty = 0xffffffffu;
-
-__global__ __launch_bounds__(256) void k_fill(uint32_t *__restrict__ a, uint32_t n, uint32_t v) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = v;
-}
-
-__global__ __launch_bounds__(256) void k_mark(KParams kp, const uint32_t *__restrict__ sk,
-                                              uint32_t n, DevInfo *__restrict__ info,
-                                              uint32_t *__restrict__ begin,
-                                              uint32_t *__restrict__ end) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > n) return;
-    const uint32_t kc = k < n ? sk[k] : 0u;
-    const int lprev = k == 0 ? -1 : (int)(sk[k - 1] >> kp.cell_bits);
-    const int lcur = k == n ? 4 : (int)(kc >> kp.cell_bits);
-    for (int l = lprev + 1; l <= lcur && l < 4; l++) info->lstart[l] = k;
-    if (k < n && lcur == 0) {
-        const uint32_t c = kc & kp.cell_mask;
-        if (k == 0 || sk[k - 1] != kc) begin[c] = k;
-        if (k + 1 == n || sk[k + 1] != kc) end[c] = k + 1;
-    }
-}
-
-__device__ __forceinline__ uint32_t wave_suffix_min(uint32_t v) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_down(v, o, 64);
-        if (lane + o < 64) v = min(v, t);
-    }
-    return v;
-}
-
-__global__ __launch_bounds__(kCellScanThreads) void k_cells_min(const uint32_t *__restrict__ begin,
-                                                               uint32_t ncells,
-                                                               uint32_t *__restrict__ bmin) {
-    __shared__ uint32_t s_w[kCellScanThreads / 64];
-    const uint32_t base = blockIdx.x * (uint32_t)kCellScanBlock;
-    uint32_t m = kEmpty;
-#pragma unroll
-    for (int r = 0; r < kCellScanItems; r++) {
-        const uint32_t c = base + r * kCellScanThreads + threadIdx.x;
-        if (c < ncells) m = min(m, begin[c]);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kCellScanThreads / 64; w++) m = min(m, s_w[w]);
-        bmin[blockIdx.x] = m;
-    }
-}
-
-// One block: bmin[b] <- min(n0, bmin[b+1], bmin[b+2], ...) (exclusive suffix).
-__global__ __launch_bounds__(256) void k_cells_carry(uint32_t *__restrict__ bmin, uint32_t nb,
-                                                     const DevInfo *__restrict__ info) {
-    __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_carry;
-    const uint32_t n0 = info->lstart[1];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_carry = n0;
-    __syncthreads();
-    // chunks of 256 blocks, from the last chunk down
-    const uint32_t nchunk = (nb + 255) / 256;
-    for (uint32_t ch = nchunk; ch-- > 0;) {
-        const uint32_t b = ch * 256 + tid;
-        const uint32_t v = b < nb ? bmin[b] : kEmpty;
-        const uint32_t wsuf = wave_suffix_min(v);  // min over lanes >= lane
-        if (lane == 0) s_w[w] = wsuf;
-        __syncthreads();
-        uint32_t later = s_carry;  // min over chunks after this one
-        for (int q = w + 1; q < 4; q++) later = min(later, s_w[q]);
-        const uint32_t nxt = __shfl_down(wsuf, 1, 64);
-        const uint32_t excl = min(later, lane < 63 ? nxt : kEmpty);
-        __syncthreads();
-        if (b < nb) bmin[b] = excl;
-        if (tid == 0) {
-            uint32_t all = s_carry;
-            for (int q = 0; q < 4; q++) all = min(all, s_w[q]);
-            s_carry = all;
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(kCellScanThreads) void k_cells_apply(uint32_t *__restrict__ begin,
-                                                                 uint32_t *__restrict__ end,
-                                                                 uint32_t ncells,
-                                                                 const uint32_t *__restrict__ carry) {
-    __shared__ uint32_t s_w[kCellScanThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // thread t owns cells base + t*4 .. base + t*4 + 3 (contiguous, in order)
-    const uint32_t base = blockIdx.x * (uint32_t)kCellScanBlock + (uint32_t)tid * kCellScanItems;
-    uint32_t v[kCellScanItems];
-#pragma unroll
-    for (int r = 0; r < kCellScanItems; r++) v[r] = base + r < ncells ? begin[base + r] : kEmpty;
-    uint32_t tmin = kEmpty;
-#pragma unroll
-    for (int r = 0; r < kCellScanItems; r++) tmin = min(tmin, v[r]);
-    const uint32_t wsuf = wave_suffix_min(tmin);
-    if (lane == 0) s_w[w] = wsuf;
-    __syncthreads();
-    uint32_t after = carry[blockIdx.x];
-    for (int q = w + 1; q < kCellScanThreads / 64; q++) after = min(after, s_w[q]);
-    const uint32_t nxt = __shfl_down(wsuf, 1, 64);
-    after = min(after, lane < 63 ? nxt : kEmpty);  // min over cells after this thread's
-#pragma unroll
-    for (int r = kCellScanItems - 1; r >= 0; r--) {
-        if (v[r] == kEmpty) {
-            if (base + r < ncells) {
-                begin[base + r] = after;
-                end[base + r] = after;
+// index of each cell; Sec. 4.4 first and last of a region) and label counts.
+// Every label-0 key is its cell index and every key of a label l > 0 is at
+// least l << Bc, so one search of the sorted keys gives each bound:
+//   k_tables: thread c < ncells: begin[c] = lower_bound(c), and
+//             end[c - 1] = begin[c]; three more threads: lstart[l] =
+//             lower_bound(l << Bc) for l = 1..3 (lstart[1] = n0 also ends
+//             the last cell). An empty cell gets begin = end = lower_bound(c).
+//             The search starts from the previous table's value (particles
+//             move little between sorts, so the bound is usually a few
+//             places away); the exponential-then-binary search is correct
+//             from any start, including uninitialised tables.
+//   k_counts: label counts, and the packing ranges of x-layers 0, 1,
+//             ncx-2, ncx-1 read off begin[] (each layer is one contiguous
+//             range of the x-major order, Sec. 4.2-4.3).
+__device__ __forceinline__ uint32_t lower_bound_from(const uint32_t *__restrict__ sk, uint32_t n,
+                                                     uint32_t key, uint32_t hint) {
+    hint = hint < n ? hint : n;
+    uint32_t lo, hi;  // answer in [lo, hi]: sk[< lo] < key, hi == n or sk[hi] >= key
+    if (hint < n && sk[hint] < key) {
+        lo = hint + 1;
+        hi = n;
+        for (uint32_t step = 1;; step <<= 1) {
+            const uint32_t q = lo + step - 1;
+            if (q >= n) break;
+            if (sk[q] >= key) {
+                hi = q;
+                break;
             }
-        } else {
-            after = v[r];
+            lo = q + 1;
+        }
+    } else {
+        hi = hint;
+        lo = 0;
+        for (uint32_t step = 1;; step <<= 1) {
+            if (hi < step) break;
+            const uint32_t q = hi - step;
+            if (sk[q] < key) {
+                lo = q + 1;
+                break;
+            }
+            hi = q;
+        }
+    }
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (sk[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_tables(KParams kp, const uint32_t *__restrict__ sk,
+                                                uint32_t n, DevInfo *__restrict__ info,
+                                                uint32_t *__restrict__ begin,
+                                                uint32_t *__restrict__ end) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nc = kp.ncells;
+    if (t < nc) {
+        const uint32_t b = lower_bound_from(sk, n, t, begin[t]);
+        begin[t] = b;
+        if (t > 0) end[t - 1] = b;
+    } else if (t < nc + 3) {
+        const uint32_t l = t - nc + 1;
+        const uint32_t b = lower_bound_from(sk, n, l << kp.cell_bits, info->lstart[l]);
+        info->lstart[l] = b;
+        if (l == 1) {
+            info->lstart[0] = 0;
+            if (nc > 0) end[nc - 1] = b;
         }
     }
 }
@@ -370,16 +311,9 @@ __global__ void k_counts(KParams kp, const uint32_t *__restrict__ begin, uint32_
 }
 
 hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s) {
-    const uint32_t nc = c->ncells;
-    const uint32_t nb = (nc + kCellScanBlock - 1) / kCellScanBlock;
-    hipLaunchKernelGGL(k_fill, dim3((nc + 255) / 256), dim3(256), 0, s, c->cell_begin, nc, kEmpty);
-    hipLaunchKernelGGL(k_mark, dim3((n + 1 + 255) / 256), dim3(256), 0, s, c->kp, c->keys_sorted,
+    const uint32_t threads = c->ncells + 3;
+    hipLaunchKernelGGL(k_tables, dim3((threads + 255) / 256), dim3(256), 0, s, c->kp, c->keys_sorted,
                        n, c->info, c->cell_begin, c->cell_end);
-    hipLaunchKernelGGL(k_cells_min, dim3(nb), dim3(kCellScanThreads), 0, s, c->cell_begin, nc,
-                       c->cell_blockmin);
-    hipLaunchKernelGGL(k_cells_carry, dim3(1), dim3(256), 0, s, c->cell_blockmin, nb, c->info);
-    hipLaunchKernelGGL(k_cells_apply, dim3(nb), dim3(kCellScanThreads), 0, s, c->cell_begin,
-                       c->cell_end, nc, c->cell_blockmin);
     hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, s, c->kp, c->cell_begin, n, c->info);
     return hipGetLastError();
 }

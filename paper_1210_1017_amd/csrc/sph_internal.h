@@ -12,13 +12,13 @@ namespace sph {
 
 enum : uint8_t { kFluid = 0, kBoundary = 1, kGhost = 2 };
 
+#ifndef SPH_SORT_ITEMS
+#define SPH_SORT_ITEMS 8
+#endif
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = SPH_SORT_ITEMS;  // keys per thread of a radix tile
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix tile
 constexpr int kInteractThreads = 256;
-constexpr int kCellScanThreads = 256;
-constexpr int kCellScanItems = 4;
-constexpr int kCellScanBlock = kCellScanThreads * kCellScanItems;  // cells per scan block
 constexpr int kRunBits = 12;                          // offset bits of a neighbour entry
 constexpr uint32_t kRunMax = (1u << kRunBits) - 1u;
 
@@ -70,7 +70,6 @@ struct sph_ctx {
     uint32_t *hist = nullptr;       // 256 * max_tiles, digit-major
     uint32_t *digit_tot = nullptr;  // 256
     uint32_t *cell_begin = nullptr, *cell_end = nullptr;
-    uint32_t *cell_blockmin = nullptr;  // per scan block of cells
     float4 *pos4 = nullptr, *vel4 = nullptr;  // packed (x,y,z,p/rho^2), (vx,vy,vz,rho)
     float *rate = nullptr;                    // 4 * capacity: ax, ay, az, arho
     sph::DevInfo *info = nullptr;

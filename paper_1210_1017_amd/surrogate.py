@@ -179,14 +179,14 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
             ctx.nn_index(B.t["id"], n, where)
             if cfg.meta.get("scaled") is None:
                 # target scales from the data: the mean squares of the unit-scale
-                # targets over the windows of the first half of the first
-                # trajectory (the flow develops from rest), no training before
+                # targets over the windows of the whole first trajectory (the
+                # flow develops from rest), no training before
                 ctx.nn_targets(A, B, where, r, rows, 1.0 / span, 1.0 / span, T, rates=Rt,
                                span=span)
                 t_host = T.cpu().numpy().astype(np.float64)
                 ms_acc.append(float(np.mean(t_host[:, :3] ** 2)))
                 ms_drho.append(float(np.mean(t_host[:, 3] ** 2)))
-                if step < steps_per_traj // 2:
+                if tr == 0 and n_traj > 1:
                     cur = B
                     continue
                 cfg.acc_scale = float(max(np.sqrt(np.mean(ms_acc)), 1e-3))
