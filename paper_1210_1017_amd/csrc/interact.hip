@@ -16,7 +16,7 @@ namespace sph {
 #define SPH_COL_SLACK 24
 #endif
 #ifndef SPH_FLUSH_UNROLL
-#define SPH_FLUSH_UNROLL 2
+#define SPH_FLUSH_UNROLL 4
 #endif
 #define SPH_PRAGMA(x) _Pragma(#x)
 #define SPH_UNROLL(n) SPH_PRAGMA(unroll n)
@@ -94,41 +94,46 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
             const float eta2 = kp.eta2, h = kp.h;
             const float kvis = -kp.alpha * kp.h * kp.c0;  // Pi_ij = kvis (s_i^3 + s_j^3) vr R
 
+            auto pair = [&](const v4f pj, const v4f vj) {
+                const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                float F;  // grad W / (kgrad r_ij)
+                if (kCubic) {
+                    const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h;
+                    const float t = 2.0f - q;
+                    // both sides first, then the choice: the compiler keeps it a
+                    // select (a conditional expression here became a branch)
+                    const float outer = t * t * __builtin_amdgcn_rcpf(q);
+                    const float inner = fmaf(-3.0f, q, 4.0f);
+                    F = q < 1.0f ? inner : outer;
+                } else {
+                    const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
+                    F = t * t * t;
+                }
+                const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+                const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
+                drho = fmaf(F, vr, drho);
+                // one reciprocal for mu = h vr / (r^2 + eta^2) and for the
+                // viscous term -alpha cbar mu / rhobar
+                const float rs = rhoi + vj.w;
+                const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
+                const float vR = vr * R;
+                const float mu = (h * rs) * vR;
+                nu = fmaxf(nu, fabsf(mu));
+                const float sj = vj.w * kp.inv_rho0;
+                const float visc = vr < 0.0f ? kvis * fmaf(sj * sj, sj, si3) * vR : 0.0f;
+                const float f = (Pi + pj.w + visc) * F;
+                axs = fmaf(f, dx, axs);
+                ays = fmaf(f, dy, ays);
+                azs = fmaf(f, dz, azs);
+            };
             auto flush = [&](int cnt) {
                 SPH_UNROLL(SPH_FLUSH_UNROLL)
                 for (int k = 0; k < cnt; k++) {
                     const uint32_t e = s_list[k][tid];
                     const uint32_t j = s_base[e >> kRunBits][tid] + (e & kRunMax);
-                    const v4f pj = __builtin_amdgcn_raw_buffer_load_b128(rp, j * 16u, 0, 0);
-                    const v4f vj = __builtin_amdgcn_raw_buffer_load_b128(rv, j * 16u, 0, 0);
-                    const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    float F;  // grad W / (kgrad r_ij)
-                    if (kCubic) {
-                        const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h;
-                        const float t = 2.0f - q;
-                        const float outer = t * t * __builtin_amdgcn_rcpf(q);
-                        F = q < 1.0f ? fmaf(-3.0f, q, 4.0f) : outer;
-                    } else {
-                        const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
-                        F = t * t * t;
-                    }
-                    const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
-                    const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
-                    drho = fmaf(F, vr, drho);
-                    // one reciprocal for mu = h vr / (r^2 + eta^2) and for the
-                    // viscous term -alpha cbar mu / rhobar
-                    const float rs = rhoi + vj.w;
-                    const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
-                    const float vR = vr * R;
-                    const float mu = (h * rs) * vR;
-                    nu = fmaxf(nu, fabsf(mu));
-                    const float sj = vj.w * kp.inv_rho0;
-                    const float visc = vr < 0.0f ? kvis * fmaf(sj * sj, sj, si3) * vR : 0.0f;
-                    const float f = (Pi + pj.w + visc) * F;
-                    axs = fmaf(f, dx, axs);
-                    ays = fmaf(f, dy, ays);
-                    azs = fmaf(f, dz, azs);
+                    pair(__builtin_amdgcn_raw_buffer_load_b128(rp, j * 16u, 0, 0),
+                         __builtin_amdgcn_raw_buffer_load_b128(rv, j * 16u, 0, 0));
                 }
             };
 
