@@ -39,7 +39,7 @@ __device__ __forceinline__ float nn_kind(uint8_t t) { return t == kBoundary ? -1
 // Sec. 2.2 for the own block and, if asked, for the FP32 rates of the row
 // (pressure acceleration + g for fluid, 0 otherwise; continuity rate).
 struct NnRowLds {
-    uint16_t list[kNnSlots][kNnRowThreads];
+    uint16_t list[kNnSlots + 1][kNnRowThreads];  // + a spare row for appends to a full list
     uint32_t base[9][kNnRowThreads];
 };
 
@@ -73,8 +73,13 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
     const int cz = (int)(cell % ncz), cy = (int)((cell / ncz) % ncy), cx = (int)(cell / (ncz * ncy));
     const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
     const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
-    // pass 1: distance test, list of the first 64 in sorted-index order
-    uint32_t found = 0, listed = 0;
+    // pass 1: distance test, list of the first 64 in sorted-index order. The
+    // append has no branch: the entry is always written to the next free slot
+    // (the spare row once the list is full) and only a hit advances it.
+    uint32_t found = 0;
+    uint16_t *const lp0 = &L.list[0][tid];
+    uint16_t *const lpend = &L.list[kNnSlots][tid];
+    uint16_t *lp = lp0;
     for (int col = 0; col < 9; col++) {
         const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
         uint32_t jb = 0, je = 0;
@@ -94,20 +99,19 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
 #pragma unroll
             for (int u = 0; u < kNnUnroll; u++)  // past the run: in-bounds data or 0, masked below
                 q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
+            const uint32_t lim = len - k0;  // candidates left in the run (>= 1)
 #pragma unroll
             for (int u = 0; u < kNnUnroll; u++) {
                 const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
                 const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                if (k0 + u < len && jb + k0 + u != i && r2 < sc.r2f) {
-                    if (listed < (uint32_t)kNnSlots) {
-                        L.list[listed][tid] = (uint16_t)(((uint32_t)col << kRunBits) + k0 + u);
-                        listed++;
-                    }
-                    found++;
-                }
+                const bool hit = (u < (int)lim) & (jb + k0 + u != i) & (r2 < sc.r2f);
+                *lp = (uint16_t)(((uint32_t)col << kRunBits) + k0 + u);
+                lp += (hit & (lp < lpend)) ? kNnRowThreads : 0;
+                found += hit ? 1u : 0u;
             }
         }
     }
+    const uint32_t listed = (uint32_t)((lp - lp0) / kNnRowThreads);
     // pass 2: slot features and the pair sums
     float apx = 0.f, apy = 0.f, apz = 0.f, dr = 0.f;
     const float inv_2h = 0.5f * kp.inv_h;
