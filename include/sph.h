@@ -337,13 +337,17 @@ int sph_get_dt64(sph_ctx *ctx, double *dt, void *stream);
  *            (u_j - u_i) inv_vel (3), (rho_j - rho_ref) inv_rho, kind_j,
  *            zeros for an empty slot;
  *   own:     (rho_i - rho_ref) inv_rho, u_i inv_vel (3), count_i / 64,
- *            kind_i, ap_i inv_acc (3), dr_i inv_drho, 22 zeros;
+ *            kind_i, ap_i inv_acc (3), dr_i inv_drho,
+ *            (u_i - u_prev_i) inv_dt inv_acc (3),
+ *            (rho_i - rho_prev_i) inv_dt inv_drho, 18 zeros;
  * kind = -1 for boundary particles, +1 otherwise; count_i = neighbours found
  * (before the cut at 64); ap_i = -sum_j m (p_i/rho_i^2 + p_j/rho_j^2)
  * grad_i W_ij and dr_i = sum_j m v_ij . grad_i W_ij over the slots (the
  * pressure part of the momentum equation and the continuity equation of
- * Sec. 2.2, FP32). Each feature is FP32 arithmetic rounded to bfloat16
- * (nearest, ties to even). Ghost rows are zero.
+ * Sec. 2.2, FP32); u_prev, rho_prev are the previous-step values of the
+ * Verlet scheme of Sec. 3.3 (the leapfrog's second sequence, which the next
+ * steps depend on). Each feature is FP32 arithmetic left to right, rounded
+ * to bfloat16 (nearest, ties to even). Ghost rows are zero.
  * Network: 544 -> w -> w -> w -> 4, SiLU after each hidden layer, bfloat16
  * weights and activations with FP32 accumulation on the matrix cores, FP32
  * master weights with Adam. Outputs, scaled: (du_x, du_y, du_z, drho) over
@@ -362,7 +366,8 @@ typedef struct sph_nn_scales {
     float r2f;      /* squared radius of the neighbourhood     */
     float inv_acc;  /* 1 / acceleration scale of ap            */
     float inv_drho; /* 1 / density-rate scale of dr            */
-    float reserved; /* 0                                       */
+    float inv_dt;   /* 1 / time scale of the previous-step
+                       differences (0: those features are 0)  */
 } sph_nn_scales;
 
 /* Network and training workspace; every buffer is caller-owned device

@@ -68,8 +68,8 @@ def kind(t: np.ndarray) -> np.ndarray:
 def features(p: dict, srt: dict, sel, scales) -> np.ndarray:
     """Input rows of the surrogate for the sorted particles ``sel``.
 
-    ``scales`` = (inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho),
-    FP32 numbers. The neighbours of i are the particles of the 27 cells of
+    ``scales`` = (inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho
+    [, inv_dt]), FP32 numbers (inv_dt defaults to 0). The neighbours of i are the particles of the 27 cells of
     Sec. 3.1 whose FP32 squared distance (the expression of the support test
     of Sec. 2.2) is below r2f, in increasing sorted index (``nn_rows``); the
     first 64 fill the slots. Slot s holds
@@ -78,18 +78,24 @@ def features(p: dict, srt: dict, sel, scales) -> np.ndarray:
     each an FP32 difference times an FP32 scale rounded to bfloat16; empty
     slots are zero. The own block is
         (rho_i - rho_ref) inv_rho, u_i inv_vel (3), count_i / 64, kind_i,
-        ap_i inv_acc (3), dr_i inv_drho, 0 ...
-    with count_i the number of neighbours found and (ap_i, dr_i) the pressure
+        ap_i inv_acc (3), dr_i inv_drho,
+        ((u_i - u_prev_i) inv_dt) inv_acc (3), ((rho_i - rho_prev_i) inv_dt) inv_drho,
+        0 ...
+    with count_i the number of neighbours found, (ap_i, dr_i) the pressure
     acceleration and continuity rate of Sec. 2.2 summed over the slots
-    (``nn_sums``, FP64 here). Ghost rows are zero. Returns an FP64 array of
+    (``nn_sums``, FP64 here) and u_prev, rho_prev the previous-step values of
+    the Verlet scheme of Sec. 3.3 (FP32 arithmetic left to right). Ghost rows
+    are zero. Returns an FP64 array of
     bfloat16 values, shape (len(sel), 544)."""
     from . import nn_rows, nn_sums
     s = srt["state"]
     n0 = int(srt["counts"][0])
     sel = np.asarray(sel, dtype=np.int64)
     assert np.all((sel >= 0) & (sel < n0))
-    inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho = (np.float32(v) for v in scales)
-    f = {k: s[k].astype(np.float32) for k in ("x", "y", "z", "vx", "vy", "vz", "rho")}
+    inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho = (np.float32(v) for v in scales[:7])
+    inv_dt = np.float32(scales[7] if len(scales) > 7 else 0.0)
+    f = {k: s[k].astype(np.float32)
+         for k in ("x", "y", "z", "vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop")}
     typ = s["type"]
     nbr, cnt = nn_rows(p, srt, sel, r2f, SLOTS)
     valid = nbr >= 0
@@ -116,6 +122,9 @@ def features(p: dict, srt: dict, sel, scales) -> np.ndarray:
     sums = nn_sums(p, srt, sel, nbr)
     own[:, 6:9] = sums[:, :3] * float(inv_acc)
     own[:, 9] = sums[:, 3] * float(inv_drho)
+    for c, (k, kp_, sc) in enumerate((("vx", "vxp", inv_acc), ("vy", "vyp", inv_acc),
+                                      ("vz", "vzp", inv_acc), ("rho", "rhop", inv_drho))):
+        own[:, 10 + c] = (f[k][sel] - f[kp_][sel]) * inv_dt * sc
     X[typ[sel] == GHOST] = 0.0
     return bf16_round(X)
 

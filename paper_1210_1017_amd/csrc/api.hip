@@ -747,7 +747,7 @@ int sph_nn_features(sph_ctx *c, const sph_soa *sorted, const int32_t *rows, uint
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_pack(c, *sorted, c->sorted_n, s);
     if (e == hipSuccess)
-        e = launch_nn_features(c, sorted->type, rows, nrows, *scales, x, 0, rates, s);
+        e = launch_nn_features(c, *sorted, rows, nrows, *scales, x, 0, rates, s);
     if (e != hipSuccess) return hip_fail(c, e, "features");
     return SPH_OK;
 }
@@ -906,7 +906,7 @@ int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *ne
     }
     if ((r = do_sort(c, cur, next, n, s))) return r;
     float *rates = residual ? c->nn_rate : nullptr;
-    hipError_t e = launch_nn_features(c, next->type, nullptr, n, *scales, c->nn_x, 1, rates, s);
+    hipError_t e = launch_nn_features(c, *next, nullptr, n, *scales, c->nn_x, 1, rates, s);
     if (e == hipSuccess)
         e = launch_nn_mlp_apply(c, *m, *next, c->nn_x, c->nn_y, rates, n, dv_scale, dr_scale,
                                 dt4, rho_tol, s);

@@ -19,7 +19,12 @@ constexpr int kNnRowThreads = 256;
 constexpr uint32_t kNnRsrcWord3 = 0x00020000u;  // buffer resource: 32-bit raw dwords
 
 struct NnScales {
-    float inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho;
+    float inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho, inv_dt;
+};
+
+// previous-step arrays of the sorted state (the own block's differences)
+struct NnPrev {
+    const float *vxp, *vyp, *vzp, *rhop;
 };
 
 typedef float nv4f __attribute__((ext_vector_type(4)));
@@ -50,8 +55,9 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
                                             const uint32_t *__restrict__ sk,
                                             const uint32_t *__restrict__ cbeg,
                                             const uint32_t *__restrict__ cend, uint32_t n,
-                                            uint32_t n0, uint32_t i, NnRowLds &L, bf16 *dst,
-                                            size_t cstride, float4 *rate, uint32_t *flags) {
+                                            uint32_t n0, uint32_t i, const NnPrev &pv,
+                                            NnRowLds &L, bf16 *dst, size_t cstride, float4 *rate,
+                                            uint32_t *flags) {
     // dst: the row's first 16-byte chunk; chunk q lies cstride chunks further
     // (1: rows are contiguous; the row count: chunk-major, chunk q of every
     // row first, so that a wave's 64 lanes store 1 KB contiguously)
@@ -164,6 +170,13 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
     o0[7] = (bf16)(mk * apy * sc.inv_acc);
     o1[0] = (bf16)(mk * apz * sc.inv_acc);
     o1[1] = (bf16)(mk * dr * sc.inv_drho);
+    {
+#pragma clang fp contract(off)
+        o1[2] = (bf16)((vi.x - pv.vxp[i]) * sc.inv_dt * sc.inv_acc);
+        o1[3] = (bf16)((vi.y - pv.vyp[i]) * sc.inv_dt * sc.inv_acc);
+        o1[4] = (bf16)((vi.z - pv.vzp[i]) * sc.inv_dt * sc.inv_acc);
+        o1[5] = (bf16)((vi.w - pv.rhop[i]) * sc.inv_dt * sc.inv_drho);
+    }
     d8[(kNnSlots + 0) * cstride] = o0;
     d8[(kNnSlots + 1) * cstride] = o1;
     d8[(kNnSlots + 2) * cstride] = zero8;
@@ -177,29 +190,31 @@ __global__ __launch_bounds__(kNnRowThreads) void k_nn_features(
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
     const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend, uint32_t n,
     DevInfo *__restrict__ info, const int32_t *__restrict__ rows, uint32_t nrows,
-    bf16 *__restrict__ X, int chunk_major, float4 *__restrict__ rates) {
+    bf16 *__restrict__ X, int chunk_major, float4 *__restrict__ rates, NnPrev pv) {
     __shared__ NnRowLds L;
     const uint32_t r = xcd_block(blockIdx.x, gridDim.x) * kNnRowThreads + threadIdx.x;
     if (r >= nrows) return;
     const uint32_t i = rows ? (uint32_t)rows[r] : r;
     bf16 *dst = chunk_major ? X + (size_t)r * 8 : X + (size_t)r * kNnIn;
-    nn_lane_row(kp, sc, pos4, vel4, type, sk, cbeg, cend, n, info->n_label[0], i, L, dst,
+    nn_lane_row(kp, sc, pos4, vel4, type, sk, cbeg, cend, n, info->n_label[0], i, pv, L, dst,
                 chunk_major ? (size_t)nrows : 1, rates ? rates + r : nullptr, &info->flags);
 }
 
 static NnScales nn_scales(const sph_nn_scales &s) {
-    return NnScales{s.inv_len, s.inv_vel, s.rho_ref, s.inv_rho, s.r2f, s.inv_acc, s.inv_drho};
+    return NnScales{s.inv_len, s.inv_vel, s.rho_ref, s.inv_rho,
+                    s.r2f,     s.inv_acc, s.inv_drho, s.inv_dt};
 }
 
-hipError_t launch_nn_features(sph_ctx *c, const uint8_t *type, const int32_t *rows,
+hipError_t launch_nn_features(sph_ctx *c, const sph_soa &sorted, const int32_t *rows,
                               uint32_t nrows, const sph_nn_scales &s, void *X, int chunk_major,
                               float *rates, hipStream_t st) {
     if (nrows == 0) return hipSuccess;
     const uint32_t n = c->sorted_n;
     hipLaunchKernelGGL(k_nn_features, dim3((nrows + kNnRowThreads - 1) / kNnRowThreads),
-                       dim3(kNnRowThreads), 0, st, c->kp, nn_scales(s), c->pos4, c->vel4, type,
-                       c->keys_sorted, c->cell_begin, c->cell_end, n, c->info, rows, nrows,
-                       (bf16 *)X, chunk_major, (float4 *)rates);
+                       dim3(kNnRowThreads), 0, st, c->kp, nn_scales(s), c->pos4, c->vel4,
+                       sorted.type, c->keys_sorted, c->cell_begin, c->cell_end, n, c->info, rows,
+                       nrows, (bf16 *)X, chunk_major, (float4 *)rates,
+                       NnPrev{sorted.vxp, sorted.vyp, sorted.vzp, sorted.rhop});
     return hipGetLastError();
 }
 

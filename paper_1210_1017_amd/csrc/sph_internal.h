@@ -149,7 +149,7 @@ hipError_t launch_totals_d(sph_ctx *c, const sph_dstate &st, uint32_t n, double 
 
 // mlp.hip (learned surrogate)
 constexpr int kMlpSplits = 32;  // split-K slices of a weight-gradient GEMM, at most
-hipError_t launch_nn_features(sph_ctx *c, const uint8_t *type, const int32_t *rows,
+hipError_t launch_nn_features(sph_ctx *c, const sph_soa &sorted, const int32_t *rows,
                               uint32_t nrows, const sph_nn_scales &s, void *X, int chunk_major,
                               float *rates, hipStream_t st);
 hipError_t launch_gemm(const void *A, const void *B, float *C, int M, int N, int K,

@@ -83,7 +83,7 @@ class Counts(C.Structure):
 class NnScales(C.Structure):
     _fields_ = [("inv_len", C.c_float), ("inv_vel", C.c_float), ("rho_ref", C.c_float),
                 ("inv_rho", C.c_float), ("r2f", C.c_float), ("inv_acc", C.c_float),
-                ("inv_drho", C.c_float), ("reserved", C.c_float)]
+                ("inv_drho", C.c_float), ("inv_dt", C.c_float)]
 
 
 _P4 = C.c_void_p * 4
@@ -476,7 +476,7 @@ class Context:
 
     def nn_features(self, srt: DeviceState, rows, nrows: int, scales, X, rates=None,
                     stream=None):
-        sc = NnScales(*[float(v) for v in scales[:7]])
+        sc = NnScales(*[float(v) for v in scales[:8]])
         self._check(self.L.sph_nn_features(self.h, C.byref(srt.soa()),
                                            None if rows is None else _addr(rows), nrows,
                                            C.byref(sc), _addr(X),
@@ -519,7 +519,7 @@ class Context:
     def nn_advance(self, net: "Mlp", cur: DeviceState, nxt: DeviceState, n: int, scales,
                    dv_scale: float, dr_scale: float, dt4: float, rho_tol: float,
                    residual: bool = False, stream=None):
-        sc = NnScales(*[float(v) for v in scales[:7]])
+        sc = NnScales(*[float(v) for v in scales[:8]])
         self._check(self.L.sph_nn_advance(self.h, C.byref(net.struct()), C.byref(cur.soa()),
                                           C.byref(nxt.soa()), n, C.byref(sc), dv_scale, dr_scale,
                                           dt4, rho_tol, int(bool(residual)),

@@ -48,14 +48,17 @@ class NnConfig:
     judge_tol: float = 0.01       # max |rho_sur - rho_sph| / rho_sph before fallback
     keep_judged: bool = True      # continue from the judge's plain result (a periodic correction)
     residual: bool = False        # targets are the rates beyond the rows' own pair-sum rates
+    prev_feat: bool = False       # own block carries the previous-step differences of the Verlet scheme
     meta: dict = field(default_factory=dict)
 
     def scales(self, params: dict) -> tuple:
-        """(inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho) of the
-        input rows, as FP32 numbers."""
+        """(inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho, inv_dt)
+        of the input rows, as FP32 numbers; inv_dt = c0 / (CFL h), the inverse
+        of the CFL time step at rest, or 0 without previous-step features."""
         rho0, h = float(params["rho0"]), float(params["h"])
+        inv_dt = float(params["c0"]) / (float(params["cfl"]) * h) if self.prev_feat else 0.0
         v = (1.0 / h, 1.0 / self.vel_scale, rho0, 1.0 / (rho0 * self.rho_feat),
-             (self.radius * h) ** 2, 1.0 / self.acc_feat, 1.0 / self.drho_feat)
+             (self.radius * h) ** 2, 1.0 / self.acc_feat, 1.0 / self.drho_feat, inv_dt)
         return tuple(float(np.float32(x)) for x in v)
 
 
@@ -102,7 +105,8 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
           width: int = 128, case_fn=cases.obstacle_tank, log=print,
           time_budget_s: float | None = None, noise_u: float = 0.02,
           noise_rho: float = 2.0, wcol=(1.0, 1.0, 1.0, 2.0), rollout_prob: float = 0.5,
-          rollout_max: int = 3, rollout_after: int = 500, residual: bool = True):
+          rollout_max: int = 3, rollout_after: int = 500, residual: bool = False,
+          prev_feat: bool = True):
     """Online training: for each of n_traj seeded layouts, run plain SPH for
     steps_per_traj steps; every window_every steps, take the sorted state A,
     build the input rows of `rows` randomly drawn particles, run 4 more plain
@@ -117,9 +121,11 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
     network being trained (sph_nn_advance) instead of plain steps, so that
     the targets also cover SPH's response to the network's own errors.
     With residual, the targets are (B - A) / (4 dt) minus the rows' pair-sum
-    rates (sph_nn_features' rates output). Returns (net, cfg, history)."""
+    rates (sph_nn_features' rates output). With prev_feat the rows carry the
+    previous-step differences of the Verlet scheme (on which the next four
+    steps depend). Returns (net, cfg, history)."""
     import torch
-    cfg = NnConfig(width=width, residual=bool(residual))
+    cfg = NnConfig(width=width, residual=bool(residual), prev_feat=bool(prev_feat))
     net = None
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)

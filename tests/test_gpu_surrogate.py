@@ -29,10 +29,22 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GRAD_TOL = 5e-3
-def _scales(p):
-    """(inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho)"""
+def _scales(p, inv_dt=0.0):
+    """(inv_len, inv_vel, rho_ref, inv_rho, r2f, inv_acc, inv_drho, inv_dt)"""
     return (np.float32(1.0 / p["h"]), np.float32(2.0), np.float32(1000.0), np.float32(0.1),
-            np.float32((1.85 * p["h"]) ** 2), np.float32(0.1), np.float32(1e-3))
+            np.float32((1.85 * p["h"]) ** 2), np.float32(0.1), np.float32(1e-3),
+            np.float32(inv_dt))
+
+
+def _with_prev(case, seed):
+    """The case with previous-step values that differ from the current ones
+    (seeded), so that the own block's previous-step differences are live."""
+    rng = np.random.default_rng(seed)
+    st = {k: v.copy() for k, v in case.state.items()}
+    for k in ("vx", "vy", "vz"):
+        st[k + "p"] = (st[k] + rng.uniform(-2e-3, 2e-3, size=st[k].shape)).astype(np.float32)
+    st["rhop"] = (st["rho"] + rng.uniform(-0.3, 0.3, size=st["rho"].shape)).astype(np.float32)
+    return cases.Case(case.name + "+prev", dict(case.params), st, case.pos64)
 
 
 def _bf16_dev(a):
@@ -69,6 +81,7 @@ FEATURE_CASES = {
     "small_tank": lambda: cases.perturb(cases.small_tank(), 3),
     "dense_cloud": lambda: cases.random_cloud(1500, 0.02, (0.22, 0.22, 0.22), seed=5),
     "small_slab": lambda: cases.perturb(cases.small_slab(), 4),
+    "tank_prev": lambda: _with_prev(cases.perturb(cases.small_tank(), 3), 11),
 }
 
 
@@ -79,7 +92,7 @@ def test_features_bit_exact(name):
     announce(f"nn features {name} n={n}")
     ctx, _, out = _sorted_gpu(case)
     n0 = ctx.counts()["n_label"][0]
-    sc = _scales(p)
+    sc = _scales(p, 1.0 / 6e-5 if name.endswith("prev") else 0.0)
     X = torch.empty(max(n0, 1), sph.NN_IN, dtype=torch.bfloat16, device="cuda")
     R = torch.empty(max(n0, 1), 4, dtype=torch.float32, device="cuda")
     ctx.nn_features(out, None, n0, sc, X, rates=R)
@@ -90,6 +103,8 @@ def test_features_bit_exact(name):
     want = om.features(p, srt, np.arange(n0), sc)
     got = _f32(X[:n0])
     _compare_rows(got, want, name)
+    if name.endswith("prev"):   # the previous-step block is live
+        assert np.abs(want[:, 522:526]).max() > 0.1
     # FP32 sums of a few dozen terms against FP64, normwise within the
     # single-step bound, relative to the pressure part (ap = rate - g for
     # fluid) and to the continuity rate
@@ -310,11 +325,11 @@ def test_apply_and_status():
     assert ctx.status() & sph.STATUS_NN_RANGE
 
 
-def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False):
+def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False, inv_dt=0.0):
     """The unfused chain (features, forward, apply) and the fused advance from
     the same state; returns both states and the unfused outputs."""
     p, n = case.params, case.n
-    sc = _scales(p)
+    sc = _scales(p, inv_dt)
     ctx = sph.Context(p, n)
     ctx.mlp_sync(net)
     cur = sph.DeviceState.from_numpy(case.state)
@@ -333,13 +348,14 @@ def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False):
 
 
 @pytest.mark.parametrize("residual", [False, True])
-@pytest.mark.parametrize("name", ["small_tank", "small_slab"])
+@pytest.mark.parametrize("name", ["small_tank", "small_slab", "tank_prev"])
 def test_fused_advance_matches_unfused(name, residual):
     case = FEATURE_CASES[name]()
     n = case.n
     announce(f"nn fused vs unfused {name} residual={residual} n={n}")
     net, _ = _random_net(128, case.n, 13, out_gain=50.0)
-    ctx, U, F, X, Y, n0 = _advance_pair(case, net, residual=residual)
+    ctx, U, F, X, Y, n0 = _advance_pair(case, net, residual=residual,
+                                        inv_dt=1.0 / 6e-5 if name.endswith("prev") else 0.0)
     assert ctx.status() & sph.STATUS_NN_RANGE == 0
     u, f = U.to_numpy(n), F.to_numpy(n)
     assert np.array_equal(u["id"], f["id"])

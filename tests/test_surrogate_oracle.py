@@ -156,10 +156,23 @@ def test_features_hand_computed(orc, mlp):
             assert slots[slot, 7] == 1.0 and slots[slot, 1] > 0.2
     assert not slots[3:].any()
     assert own[:6].tolist() == [0.0, 1.0, 0.0, -0.5, 3 / 64, 1.0]
-    assert not own[10:].any()
+    assert not own[10:].any()   # previous-step values equal the current ones
     # the ghost's row is zero, the boundary particle's kind is -1
     assert not mlp.features(p, srt, [order[3]], sc).any()
     assert mlp.features(p, srt, [order[2]], sc)[0, 512 + 5] == -1.0
+    # previous-step differences: u - u_prev = (0.25, -0.5, 0), rho - rho_prev
+    # = 2 for particle i; with inv_dt = 1000 they read
+    # (0.25 * 1000 * 0.1, -0.5 * 1000 * 0.1, 0, 2 * 1000 * 1e-3) = (25, -50, 0, 2)
+    st2 = {k: v.copy() for k, v in st.items()}
+    i0 = int(np.nonzero(st2["id"] == 0)[0][0])
+    st2["vxp"][i0] = st2["vx"][i0] - np.float32(0.25)
+    st2["vyp"][i0] = st2["vy"][i0] + np.float32(0.5)
+    st2["rhop"][i0] = st2["rho"][i0] - np.float32(2.0)
+    srt2 = orc.sort_state(p, st2)
+    own2 = mlp.features(p, srt2, [i], sc + (1000.0,))[0, 512:]
+    assert own2[10:14].tolist() == [25.0, -50.0, 0.0, 2.0]
+    assert not own2[14:].any() and own2[:10].tolist() == own[:10].tolist()
+    assert not mlp.features(p, srt2, [i], sc)[0, 512 + 10:].any()   # inv_dt = 0
 
 
 def test_nn_sums_equal_interaction_for_a_static_cluster(orc):
