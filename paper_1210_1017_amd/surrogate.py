@@ -106,7 +106,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
           time_budget_s: float | None = None, noise_u: float = 0.02,
           noise_rho: float = 2.0, wcol=(1.0, 1.0, 1.0, 2.0), rollout_prob: float = 0.5,
           rollout_max: int = 3, rollout_after: int = 500, residual: bool = False,
-          prev_feat: bool = True):
+          prev_feat: bool = False):
     """Online training: for each of n_traj seeded layouts, run plain SPH for
     steps_per_traj steps; every window_every steps, take the sorted state A,
     build the input rows of `rows` randomly drawn particles, run 4 more plain

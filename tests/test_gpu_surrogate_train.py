@@ -50,10 +50,10 @@ def _measure(cfg):
 
 
 def test_training_beats_persistence():
-    announce("surrogate short training (whole change, previous-step features)")
+    announce("surrogate short training (whole change)")
     net, cfg, hist = _train(False)
     print("loss", hist["loss"], flush=True)
-    assert cfg.prev_feat and not cfg.residual
+    assert not cfg.residual
     assert np.all(np.isfinite(hist["loss"])) and hist["loss"][-1] < hist["loss"][0]
     hold = _tiny(4242)
     cfg = _measure(cfg)
