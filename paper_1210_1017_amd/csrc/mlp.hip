@@ -3,7 +3,7 @@
 // forward and backward passes of the MLP, the element-wise pieces around them
 // (bias, SiLU, loss, column sums, Adam), training targets, the application of
 // a prediction to the state, the error of a surrogate state against plain SPH,
-// and one fused kernel (rows + network + application) for the advance.
+// and the persistent network kernel of the advance (weights in registers).
 #include "sph_device.h"
 
 namespace sph {
