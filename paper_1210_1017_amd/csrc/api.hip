@@ -247,10 +247,11 @@ int sph_sort_kv(sph_ctx *c, const uint32_t *keys, const int32_t *vals, uint32_t 
 }
 
 static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n, hipStream_t s) {
-    hipError_t e = launch_keys(c->kp, *in, n, c->keys_a, c->vals_a, s);
+    // keys with the first digit histogram; the gather also forms the counts
+    hipError_t e = launch_keys_hist(c, *in, n, s);
     if (e == hipSuccess) e = radix_sort(c, c->keys_a, c->vals_a, c->keys_sorted, c->perm, n,
-                                        c->cell_bits + 2, s);
-    if (e == hipSuccess) e = launch_tables(c, n, s);
+                                        c->cell_bits + 2, s, true);
+    if (e == hipSuccess) e = launch_tables(c, n, s, false);
     if (e == hipSuccess) e = launch_gather(c, *in, *out, n, s);
     if (e != hipSuccess) return hip_fail(c, e, "sort step");
     c->sorted_n = n;

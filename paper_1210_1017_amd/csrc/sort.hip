@@ -19,6 +19,43 @@ __global__ __launch_bounds__(256) void k_keys(KParams kp, const float *__restric
     vals[i] = (int32_t)i;
 }
 
+// Keys fused with the digit histogram of the first radix pass (one radix
+// tile per block, as k_radix_hist): saves a kernel and a pass over the keys.
+__global__ __launch_bounds__(kSortThreads) void k_keys_hist(KParams kp, const float *__restrict__ x,
+                                                            const float *__restrict__ y,
+                                                            const float *__restrict__ z,
+                                                            const uint8_t *__restrict__ type,
+                                                            uint32_t n, uint32_t ntiles,
+                                                            uint32_t *__restrict__ keys,
+                                                            int32_t *__restrict__ vals,
+                                                            uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t idx = base + r * kSortThreads + tid;
+        if (idx < n) {
+            const uint32_t key = cell_key(kp, x[idx], y[idx], z[idx], type[idx]);
+            keys[idx] = key;
+            vals[idx] = (int32_t)idx;
+            atomicAdd(&h[key & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+hipError_t launch_keys_hist(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
+    hipLaunchKernelGGL(k_keys_hist, dim3(ntiles), dim3(kSortThreads), 0, s, c->kp, in.x, in.y,
+                       in.z, in.type, n, ntiles, c->keys_a, c->vals_a, c->hist);
+    return hipGetLastError();
+}
+
 hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_t *keys,
                        int32_t *vals, hipStream_t s) {
     if (n == 0) return hipSuccess;
@@ -173,7 +210,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 
 hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_in,
                       uint32_t *keys_out, int32_t *vals_out, uint32_t n, int key_bits,
-                      hipStream_t s) {
+                      hipStream_t s, bool first_hist_done) {
     if (n == 0) return hipSuccess;
     const int passes = (key_bits + 7) / 8;
     const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
@@ -191,8 +228,9 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
             vdst = (vsrc == c->vals_a) ? c->vals_b : c->vals_a;
         }
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, n, shift,
-                           ntiles, c->hist);
+        if (p > 0 || !first_hist_done)
+            hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, n,
+                               shift, ntiles, c->hist);
         hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, c->hist, ntiles,
                            c->digit_tot);
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, vsrc,
@@ -281,9 +319,9 @@ __global__ __launch_bounds__(256) void k_tables(KParams kp, const uint32_t *__re
     }
 }
 
-__global__ void k_counts(KParams kp, const uint32_t *__restrict__ begin, uint32_t n,
-                         DevInfo *__restrict__ info) {
-    const int t = threadIdx.x;
+// Thread t < 9 of one block: label counts and packing ranges.
+__device__ __forceinline__ void table_counts(const KParams &kp, const uint32_t *__restrict__ begin,
+                                             uint32_t n, DevInfo *__restrict__ info, int t) {
     const uint32_t n0 = info->lstart[1];
     if (t < 4) info->n_label[t] = (t < 3 ? info->lstart[t + 1] : n) - info->lstart[t];
     if (t < 8) {
@@ -310,11 +348,17 @@ __global__ void k_counts(KParams kp, const uint32_t *__restrict__ begin, uint32_
     }
 }
 
-hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s) {
+__global__ void k_counts(KParams kp, const uint32_t *__restrict__ begin, uint32_t n,
+                         DevInfo *__restrict__ info) {
+    table_counts(kp, begin, n, info, (int)threadIdx.x);
+}
+
+hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s, bool counts) {
     const uint32_t threads = c->ncells + 3;
     hipLaunchKernelGGL(k_tables, dim3((threads + 255) / 256), dim3(256), 0, s, c->kp, c->keys_sorted,
                        n, c->info, c->cell_begin, c->cell_end);
-    hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, s, c->kp, c->cell_begin, n, c->info);
+    if (counts)
+        hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, s, c->kp, c->cell_begin, n, c->info);
     return hipGetLastError();
 }
 
@@ -328,13 +372,17 @@ __device__ __forceinline__ void reset_step_reductions(DevInfo *info) {
 // Reorder every state array by the sorted permutation (Sec. 3.1: all arrays
 // are ordered according to the sorted IDs) and write the packed interaction
 // inputs (x, y, z, p/rho^2) and (vx, vy, vz, rho).
+// Block 0 also forms the label counts and packing ranges from the cell
+// tables (no separate kernel).
 __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa out,
                                                 const int32_t *__restrict__ perm, uint32_t n,
                                                 float4 *__restrict__ pos4,
                                                 float4 *__restrict__ vel4,
+                                                const uint32_t *__restrict__ cbegin,
                                                 DevInfo *__restrict__ info) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) reset_step_reductions(info);
+    if (k < 9) table_counts(kp, cbegin, n, info, (int)k);
     if (k >= n) return;
     const uint32_t s = (uint32_t)perm[k];
     const float x = in.x[s], y = in.y[s], z = in.z[s];
@@ -353,7 +401,7 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
 hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_gather, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, in,
-                       out, c->perm, n, c->pos4, c->vel4, c->info);
+                       out, c->perm, n, c->pos4, c->vel4, c->cell_begin, c->info);
     return hipGetLastError();
 }
 

@@ -101,12 +101,13 @@ struct sph_ctx {
 namespace sph {
 
 // sort.hip
+hipError_t launch_keys_hist(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s);
 hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_t *keys,
                        int32_t *vals, hipStream_t s);
 hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_in,
                       uint32_t *keys_out, int32_t *vals_out, uint32_t n, int key_bits,
-                      hipStream_t s);
-hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s);
+                      hipStream_t s, bool first_hist_done = false);
+hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s, bool counts = true);
 hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
                          hipStream_t s);
 hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s);
