@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact_cell(
             const float zm = pi.z + cs, zp = pi.z - cs;  // i's z relative to cells z-1, z+1
 
             auto flush = [&](int cnt) {
-#pragma unroll 2
+#pragma unroll 4
                 for (int k = 0; k < cnt; k++) {
                     const uint32_t e = s_list[k][tid];
                     const uint32_t col = e >> kRunBits, kk = e & kRunMax;
@@ -314,10 +314,10 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact_cell(
                         const float ziz = kk < kb1 ? zm : (kk < kb2 ? pi.z : zp);
                         const float dx = pix - q[u].x, dy = piy - q[u].y, dz = ziz - q[u].z;
                         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        if (kk < len && r2 < kp.r2max) {
-                            *lp = (uint16_t)(((uint32_t)col << kRunBits) + kk);
-                            lp += kInteractThreads;
-                        }
+                        // branch-free append: always written, kept only by a hit
+                        const bool hit = (kk < len) & (r2 < kp.r2max);
+                        *lp = (uint16_t)(((uint32_t)col << kRunBits) + kk);
+                        lp += hit ? kInteractThreads : 0;
                     }
                     if (lp >= lpcap) {
                         const int cnt = (int)((lp - lp0) / kInteractThreads);

@@ -124,6 +124,29 @@ def test_sort_state_bit_exact(name):
     assert sum(cnt["n_label"]) == n
 
 
+def test_tables_from_stale_bounds():
+    """The cell-table search starts from the previous sort's bounds: one
+    context sorts a full tank, then a third of it (every bound moves), then a
+    shuffled full tank, then nothing; every table stays bit-exact."""
+    case = cases.perturb(cases.small_tank(), 5)
+    p, n = case.params, case.n
+    announce(f"tables from stale bounds n={n}")
+    ctx = _ctx(p, n)
+    rng = np.random.default_rng(21)
+    part = {k: v[np.sort(rng.choice(n, n // 3, replace=False))].copy() for k, v in case.state.items()}
+    part["id"] = np.arange(n // 3, dtype=np.int32)
+    shuf = cases.shuffle(case, 22).state
+    for st in (case.state, part, shuf, {k: v[:0].copy() for k, v in case.state.items()}):
+        m = st["x"].shape[0]
+        _, out = gpu_sort(ctx, st, m)
+        torch.cuda.synchronize()
+        srt = oracle.sort_state(p, st)
+        b, e = ctx.cell_tables()
+        assert np.array_equal(sph.u32(b), srt["begin"]), m
+        assert np.array_equal(sph.u32(e), srt["end"]), m
+        assert ctx.counts()["n_label"] == srt["counts"].tolist()
+
+
 def test_sort_outside_grid_and_nan():
     case = cases.small_tank()
     st = {k: v.copy() for k, v in case.state.items()}
