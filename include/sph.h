@@ -207,13 +207,16 @@ int sph_interact(sph_ctx *ctx, const sph_soa *sorted, uint32_t n, const sph_rate
 
 /* Verlet update (Sec. 3.3) of the in-domain particles of `sorted` in place,
  * with the rates in `rates` and the dt of the last sph_interact. `step` is
- * the step counter (an Euler step when step % euler_every == 0). */
+ * the step counter (an Euler step when step % euler_every == 0). Refused
+ * (SPH_E_STATE) on a context with SPH_O_SYMPLECTIC. */
 int sph_update(sph_ctx *ctx, sph_soa *sorted, const sph_rates *rates, uint32_t n,
                uint64_t step, void *stream);
 
 /* One whole time step: sph_sort(cur -> next), interaction into the context's
- * own rate buffers, dt, Verlet update of next. On return `next` holds the new
- * state (sorted); `cur` is left as it was. No host synchronisation. */
+ * own rate buffers, dt, Verlet update of next (with SPH_O_SYMPLECTIC: the
+ * half step, a second interaction and the full step instead). On return
+ * `next` holds the new state (sorted); `cur` is left as it was. No host
+ * synchronisation. */
 int sph_step(sph_ctx *ctx, const sph_soa *cur, sph_soa *next, uint32_t n, uint64_t step,
              void *stream);
 
