@@ -170,7 +170,7 @@ __device__ __forceinline__ void nn_lane_row(const KParams &kp, const NnScales &s
     o0[7] = (bf16)(mk * apy * sc.inv_acc);
     o1[0] = (bf16)(mk * apz * sc.inv_acc);
     o1[1] = (bf16)(mk * dr * sc.inv_drho);
-    {
+    if (sc.inv_dt != 0.0f) {  // previous-step differences (uniform: a scale of the launch)
 #pragma clang fp contract(off)
         o1[2] = (bf16)((vi.x - pv.vxp[i]) * sc.inv_dt * sc.inv_acc);
         o1[3] = (bf16)((vi.y - pv.vyp[i]) * sc.inv_dt * sc.inv_acc);
