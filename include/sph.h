@@ -444,28 +444,38 @@ int sph_mlp_backward(sph_ctx *ctx, sph_mlp *net, const void *x, uint32_t rows, c
 int sph_mlp_adam(sph_ctx *ctx, sph_mlp *net, float lr, float beta1, float beta2, float eps,
                  uint32_t t, void *stream);
 
+/* Flags of sph_nn_apply and sph_nn_advance. */
+enum {
+    SPH_NN_RESIDUAL = 1,   /* advance: add dt4 x the rows' pair-sum rates       */
+    SPH_NN_CARRY_PREV = 2  /* previous-step arrays keep their difference to the
+                              current values (prev = new - (old - prev_old))
+                              instead of being set one step back along the
+                              change                                            */
+};
+
 /* Apply network outputs y (FP32 [nrows][4], row r = sorted particle r) to
  * the sorted state over a span dt4 of four steps, with rates (FP32
  * [nrows][4] of sph_nn_features, or NULL for zeros): fluid u += dt4
  * rates[0..2] + y[0..2] dv_scale, x += dt4 (u_old + u_new)/2; fluid and
  * boundary rho += dt4 rates[3] + y[3] dr_scale; ghosts untouched. The
  * previous-step arrays are set to one step back along the same change (new -
- * change/4), so a following Verlet step continues the leapfrog. A
+ * change/4), or with SPH_NN_CARRY_PREV in flags keep their difference to the
+ * current values, so a following Verlet step continues the leapfrog. A
  * non-finite result or |rho/rho0 - 1| > rho_tol sets SPH_S_NN_RANGE. */
 int sph_nn_apply(sph_ctx *ctx, sph_soa *sorted, const float *y, const float *rates,
                  uint32_t nrows, float dv_scale, float dr_scale, float dt4, float rho_tol,
-                 void *stream);
+                 int flags, void *stream);
 
 /* One surrogate advance: sort cur into next (as sph_sort), build every
  * particle's input row (into buffers the context allocates on the first call:
  * capacity x SPH_NN_IN bfloat16 rows, 4 FP32 rates and 4 FP32 outputs per
  * particle), then one kernel runs the network (width 128) on tiles of 64 rows
  * and the result is applied to next as sph_nn_apply does, with the rows'
- * rates if residual != 0 (a network trained on targets with rates) and
- * without them otherwise. */
+ * rates if flags has SPH_NN_RESIDUAL (a network trained on targets with
+ * rates) and without them otherwise, and with SPH_NN_CARRY_PREV as there. */
 int sph_nn_advance(sph_ctx *ctx, const sph_mlp *net, const sph_soa *cur, sph_soa *next,
                    uint32_t n, const sph_nn_scales *scales, float dv_scale, float dr_scale,
-                   float dt4, float rho_tol, int residual, void *stream);
+                   float dt4, float rho_tol, int flags, void *stream);
 
 /* Training noise: adds to the velocity and density of every fluid particle
  * k < n (and to their previous-step values, so a Verlet step sees the same

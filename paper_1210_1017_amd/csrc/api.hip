@@ -862,14 +862,17 @@ int sph_mlp_adam(sph_ctx *c, sph_mlp *m, float lr, float beta1, float beta2, flo
 }
 
 int sph_nn_apply(sph_ctx *c, sph_soa *sorted, const float *y, const float *rates, uint32_t nrows,
-                 float dv_scale, float dr_scale, float dt4, float rho_tol, void *stream) {
+                 float dv_scale, float dr_scale, float dt4, float rho_tol, int flags,
+                 void *stream) {
     int r = enter(c);
     if (r) return r;
     if (!soa_ok(sorted) || (nrows && !y)) return fail(c, SPH_E_INVALID_ARG, "null argument");
     if (!c->have_sort || c->last_path != 0 || nrows > c->sorted_n)
         return fail(c, SPH_E_STATE, "sph_nn_apply needs a preceding sph_sort of >= nrows");
+    if (flags & ~(int)(SPH_NN_RESIDUAL | SPH_NN_CARRY_PREV))
+        return fail(c, SPH_E_INVALID_ARG, "unknown surrogate flag bits");
     hipError_t e = launch_nn_apply(c, *sorted, y, rates, nrows, dv_scale, dr_scale, dt4, rho_tol,
-                                   (hipStream_t)stream);
+                                   (flags & SPH_NN_CARRY_PREV) ? 1 : 0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "apply");
     c->have_dt = false;
     return SPH_OK;
@@ -877,7 +880,7 @@ int sph_nn_apply(sph_ctx *c, sph_soa *sorted, const float *y, const float *rates
 
 int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *next, uint32_t n,
                    const sph_nn_scales *scales, float dv_scale, float dr_scale, float dt4,
-                   float rho_tol, int residual, void *stream) {
+                   float rho_tol, int flags, void *stream) {
     int r = enter(c);
     if (r) return r;
     if ((r = mlp_check(c, m, false))) return r;
@@ -887,6 +890,8 @@ int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *ne
     if (n > c->capacity) return fail(c, SPH_E_CAPACITY, "n = %u > capacity %u", n, c->capacity);
     if (!soa_ok(cur) || !soa_ok(next) || !scales)
         return fail(c, SPH_E_INVALID_ARG, "null argument");
+    if (flags & ~(int)(SPH_NN_RESIDUAL | SPH_NN_CARRY_PREV))
+        return fail(c, SPH_E_INVALID_ARG, "unknown surrogate flag bits");
     if (cur->x == next->x || cur->rho == next->rho || cur->type == next->type || cur->id == next->id)
         return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
     hipStream_t s = (hipStream_t)stream;
@@ -906,11 +911,11 @@ int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *ne
         c->nn_x_rows = c->capacity;
     }
     if ((r = do_sort(c, cur, next, n, s))) return r;
-    float *rates = residual ? c->nn_rate : nullptr;
+    float *rates = (flags & SPH_NN_RESIDUAL) ? c->nn_rate : nullptr;
     hipError_t e = launch_nn_features(c, *next, nullptr, n, *scales, c->nn_x, 1, rates, s);
     if (e == hipSuccess)
         e = launch_nn_mlp_apply(c, *m, *next, c->nn_x, c->nn_y, rates, n, dv_scale, dr_scale,
-                                dt4, rho_tol, s);
+                                dt4, rho_tol, (flags & SPH_NN_CARRY_PREV) ? 1 : 0, s);
     if (e != hipSuccess) return hip_fail(c, e, "surrogate advance");
     c->have_dt = false;
     return SPH_OK;

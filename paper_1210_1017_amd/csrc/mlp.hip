@@ -566,6 +566,7 @@ hipError_t launch_nn_targets(const sph_soa &a, const sph_soa &b, const int32_t *
 
 struct NnApply {
     float dv_scale, dr_scale, dt4, rho_tol;
+    int carry;  // SPH_NN_CARRY_PREV: keep each previous-step difference
 };
 
 // Applies output (y0..y3) and the row's rates rt (zeros: none) to sorted
@@ -578,9 +579,10 @@ __device__ __forceinline__ void nn_apply_one(const KParams &kp, const sph_soa &s
     // rho + dt4 rate + y scale: with no rates (rt = 0) the inner FMA is exact
     // and the result one rounding of rho + y scale
     const float dr = fmaf(ap.dt4, rt.w, y3 * ap.dr_scale);
-    const float rn = fmaf(y3, ap.dr_scale, fmaf(ap.dt4, rt.w, st.rho[k]));
+    const float rho = st.rho[k];
+    const float rn = fmaf(y3, ap.dr_scale, fmaf(ap.dt4, rt.w, rho));
+    st.rhop[k] = ap.carry ? rn - (rho - st.rhop[k]) : rn - 0.25f * dr;
     st.rho[k] = rn;
-    st.rhop[k] = rn - 0.25f * dr;
     bool ok = isfinite(rn) && fabsf(rn * kp.inv_rho0 - 1.0f) <= ap.rho_tol;
     if (t == kFluid) {
         float *pos[3] = {st.x, st.y, st.z};
@@ -596,7 +598,7 @@ __device__ __forceinline__ void nn_apply_one(const KParams &kp, const sph_soa &s
             const float xn = pos[d][k] + ap.dt4 * 0.5f * (v + vn);
             pos[d][k] = xn;
             vel[d][k] = vn;
-            velp[d][k] = vn - 0.25f * dv;
+            velp[d][k] = ap.carry ? vn - (v - velp[d][k]) : vn - 0.25f * dv;
             ok = ok && isfinite(vn) && isfinite(xn);
         }
     }
@@ -617,9 +619,9 @@ __global__ __launch_bounds__(256) void k_nn_apply(KParams kp, sph_soa st,
 
 hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, const float *rates,
                            uint32_t nrows, float dv_scale, float dr_scale, float dt4,
-                           float rho_tol, hipStream_t s) {
+                           float rho_tol, int carry, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
-    const NnApply ap{dv_scale, dr_scale, dt4, rho_tol};
+    const NnApply ap{dv_scale, dr_scale, dt4, rho_tol, carry};
     hipLaunchKernelGGL(k_nn_apply, grid1(nrows), dim3(256), 0, s, c->kp, st, Y,
                        (const float4 *)rates, nrows, ap, c->info);
     return hipGetLastError();
@@ -920,7 +922,8 @@ __global__ __launch_bounds__(kMlpThreads, 1) void k_nn_mlp(FusedNet net,
 
 hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
                                float *Y, const float *rates, uint32_t nrows, float dv_scale,
-                               float dr_scale, float dt4, float rho_tol, hipStream_t stream) {
+                               float dr_scale, float dt4, float rho_tol, int carry,
+                               hipStream_t stream) {
     if (nrows == 0) return hipSuccess;
     const FusedNet net{(const bf16 *)m.wb[0], (const bf16 *)m.wb[1], (const bf16 *)m.wb[2],
                        (const bf16 *)m.wb[3], m.b[0], m.b[1], m.b[2], m.b[3]};
@@ -933,7 +936,8 @@ hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, 
                        nrows, Y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_nn_apply(c, st, Y, rates, nrows, dv_scale, dr_scale, dt4, rho_tol, stream);
+    return launch_nn_apply(c, st, Y, rates, nrows, dv_scale, dr_scale, dt4, rho_tol, carry,
+                           stream);
 }
 
 }  // namespace sph

@@ -173,7 +173,7 @@ hipError_t launch_nn_targets(const sph_soa &a, const sph_soa &b, const int32_t *
                              float inv_dv, float inv_dr, float *T, hipStream_t s);
 hipError_t launch_nn_apply(sph_ctx *c, const sph_soa &st, const float *Y, const float *rates,
                            uint32_t nrows, float dv_scale, float dr_scale, float dt4,
-                           float rho_tol, hipStream_t s);
+                           float rho_tol, int carry, hipStream_t s);
 hipError_t launch_nn_perturb(const sph_soa &st, uint32_t n, uint32_t seed, float sigma_u,
                              float sigma_rho, hipStream_t s);
 hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
@@ -181,7 +181,8 @@ hipError_t launch_nn_judge(const sph_soa &S, const sph_soa &R, const sph_soa &B,
                            double *part, double *out, hipStream_t s);
 hipError_t launch_nn_mlp_apply(sph_ctx *c, const sph_mlp &m, const sph_soa &st, const void *X,
                                float *Y, const float *rates, uint32_t nrows, float dv_scale,
-                               float dr_scale, float dt4, float rho_tol, hipStream_t stream);
+                               float dr_scale, float dt4, float rho_tol, int carry,
+                               hipStream_t stream);
 
 // update.hip
 hipError_t launch_sym_half(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,

@@ -23,6 +23,7 @@ SPH_OK = 0
 STATUS_NONFINITE, STATUS_DT, STATUS_RUN_OVERFLOW, STATUS_EXCLUDED = 1, 2, 4, 8
 STATUS_NN_RANGE, STATUS_NN_LIST = 16, 32
 NN_SLOTS, NN_IN, NN_OUT, NN_LAYERS = 64, 544, 4, 4
+NN_RESIDUAL, NN_CARRY_PREV = 1, 2
 
 
 class SphError(RuntimeError):
@@ -156,7 +157,7 @@ def lib() -> C.CDLL:
         L.sph_mlp_forward.argtypes = [vp, P(MlpStruct), vp, u32, vp, vp]
         L.sph_mlp_backward.argtypes = [vp, P(MlpStruct), vp, u32, vp, P(f32), vp]
         L.sph_mlp_adam.argtypes = [vp, P(MlpStruct), f32, f32, f32, f32, u32, vp]
-        L.sph_nn_apply.argtypes = [vp, P(SoA), vp, vp, u32, f32, f32, f32, f32, vp]
+        L.sph_nn_apply.argtypes = [vp, P(SoA), vp, vp, u32, f32, f32, f32, f32, i32, vp]
         L.sph_nn_advance.argtypes = [vp, P(MlpStruct), P(SoA), P(SoA), u32, P(NnScales), f32,
                                      f32, f32, f32, i32, vp]
         L.sph_nn_perturb.argtypes = [vp, P(SoA), u32, u32, f32, f32, vp]
@@ -511,18 +512,22 @@ class Context:
                                         int(t), _stream_ptr(stream)))
 
     def nn_apply(self, srt: DeviceState, Y, nrows: int, dv_scale: float, dr_scale: float,
-                 dt4: float, rho_tol: float, rates=None, stream=None):
+                 dt4: float, rho_tol: float, rates=None, carry_prev: bool = False, stream=None):
         self._check(self.L.sph_nn_apply(self.h, C.byref(srt.soa()), _addr(Y),
                                         None if rates is None else _addr(rates), nrows,
-                                        dv_scale, dr_scale, dt4, rho_tol, _stream_ptr(stream)))
+                                        dv_scale, dr_scale, dt4, rho_tol,
+                                        NN_CARRY_PREV if carry_prev else 0,
+                                        _stream_ptr(stream)))
 
     def nn_advance(self, net: "Mlp", cur: DeviceState, nxt: DeviceState, n: int, scales,
                    dv_scale: float, dr_scale: float, dt4: float, rho_tol: float,
-                   residual: bool = False, stream=None):
+                   residual: bool = False, carry_prev: bool = False, stream=None):
         sc = NnScales(*[float(v) for v in scales[:8]])
         self._check(self.L.sph_nn_advance(self.h, C.byref(net.struct()), C.byref(cur.soa()),
                                           C.byref(nxt.soa()), n, C.byref(sc), dv_scale, dr_scale,
-                                          dt4, rho_tol, int(bool(residual)),
+                                          dt4, rho_tol,
+                                          (NN_RESIDUAL if residual else 0)
+                                          | (NN_CARRY_PREV if carry_prev else 0),
                                           _stream_ptr(stream)))
 
     def nn_perturb(self, st: DeviceState, n: int, seed: int, sigma_u: float, sigma_rho: float,

@@ -49,6 +49,7 @@ class NnConfig:
     keep_judged: bool = True      # continue from the judge's plain result (a periodic correction)
     residual: bool = False        # targets are the rates beyond the rows' own pair-sum rates
     prev_feat: bool = False       # own block carries the previous-step differences of the Verlet scheme
+    carry_prev: bool = False      # advances keep each particle's previous-step difference
     meta: dict = field(default_factory=dict)
 
     def scales(self, params: dict) -> tuple:
@@ -106,7 +107,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
           time_budget_s: float | None = None, noise_u: float = 0.02,
           noise_rho: float = 2.0, wcol=(1.0, 1.0, 1.0, 2.0), rollout_prob: float = 0.5,
           rollout_max: int = 3, rollout_after: int = 500, residual: bool = False,
-          prev_feat: bool = False):
+          prev_feat: bool = False, carry_prev: bool = False):
     """Online training: for each of n_traj seeded layouts, run plain SPH for
     steps_per_traj steps; every window_every steps, take the sorted state A,
     build the input rows of `rows` randomly drawn particles, run 4 more plain
@@ -123,9 +124,12 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
     With residual, the targets are (B - A) / (4 dt) minus the rows' pair-sum
     rates (sph_nn_features' rates output). With prev_feat the rows carry the
     previous-step differences of the Verlet scheme (on which the next four
-    steps depend). Returns (net, cfg, history)."""
+    steps depend); with carry_prev the advances (rollouts and later runs)
+    keep those differences instead of resetting them along the change.
+    Returns (net, cfg, history)."""
     import torch
-    cfg = NnConfig(width=width, residual=bool(residual), prev_feat=bool(prev_feat))
+    cfg = NnConfig(width=width, residual=bool(residual), prev_feat=bool(prev_feat),
+                   carry_prev=bool(carry_prev))
     net = None
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
@@ -168,7 +172,8 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
                 for _ in range(int(noise_rng.integers(1, rollout_max + 1))):
                     nxt = _others(bufs, cur)[0]
                     ctx.nn_advance(net, cur, nxt, n, scales, span * cfg.acc_scale,
-                                   span * cfg.drho_scale, span, 1.0, residual=cfg.residual)
+                                   span * cfg.drho_scale, span, 1.0, residual=cfg.residual,
+                                   carry_prev=cfg.carry_prev)
                     cur, step = nxt, step + K_STEPS
             # window: sorted copy A, input rows, 4 plain steps to B
             A = _others(bufs, cur)[0]
@@ -292,7 +297,7 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
         S = others(cur)[0]
         span = K_STEPS * dt
         ctx.nn_advance(net, cur, S, n, scales, span * cfg.acc_scale, span * cfg.drho_scale, span,
-                       cfg.rho_band, residual=cfg.residual)
+                       cfg.rho_band, residual=cfg.residual, carry_prev=cfg.carry_prev)
         bad = ctx.status() & (sph.STATUS_NN_RANGE | sph.STATUS_NONFINITE)
         do_judge = judge and since_judge >= interval
         since_judge = 0 if do_judge else since_judge + 1

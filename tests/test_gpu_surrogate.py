@@ -320,12 +320,24 @@ def test_apply_and_status():
     tol = 1.01 * ulp32(rn) + 0.51 * ulp32(inner)
     assert np.all(np.abs(f64(after["rho"][:n0][ng]) - rn[ng]) <= tol[ng])
     assert np.array_equal(after["rho"][:n0][~ng], before["rho"][:n0][~ng])
+    # carried previous-step differences: prev' = new - (old - prev)
+    before = after
+    ctx.nn_apply(S, torch.from_numpy(Y).cuda(), n0, dv, dr, dt4, 1.0, carry_prev=True)
+    torch.cuda.synchronize()
+    after = S.to_numpy(n)
+    for k in ("vx", "vy", "vz", "rho"):
+        sel = fl if k != "rho" else ng
+        diff = f64(before[k][:n0]) - f64(before[k + "p"][:n0])
+        want = f64(after[k][:n0]) - diff
+        big = np.maximum(np.abs(f64(after[k][:n0])), np.abs(diff))
+        assert np.all(np.abs(f64(after[k + "p"][:n0][sel]) - want[sel]) <= 1.01 * ulp32(big[sel])), k
     # a density outside the band raises the status bit
     ctx.nn_apply(S, torch.from_numpy(Y).cuda(), n0, dv, np.float32(50.0), dt4, 0.01)
     assert ctx.status() & sph.STATUS_NN_RANGE
 
 
-def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False, inv_dt=0.0):
+def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False, inv_dt=0.0,
+                  carry=False):
     """The unfused chain (features, forward, apply) and the fused advance from
     the same state; returns both states and the unfused outputs."""
     p, n = case.params, case.n
@@ -341,8 +353,8 @@ def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False, inv_dt=0
     R = torch.empty(n0, 4, device="cuda") if residual else None
     ctx.nn_features(U, None, n0, sc, X, rates=R)
     ctx.mlp_forward(net, X, n0, Y)
-    ctx.nn_apply(U, Y, n0, dv, dr, dt4, 1.0, rates=R)
-    ctx.nn_advance(net, cur, F, n, sc, dv, dr, dt4, 1.0, residual=residual)
+    ctx.nn_apply(U, Y, n0, dv, dr, dt4, 1.0, rates=R, carry_prev=carry)
+    ctx.nn_advance(net, cur, F, n, sc, dv, dr, dt4, 1.0, residual=residual, carry_prev=carry)
     torch.cuda.synchronize()
     return ctx, U, F, X, Y, n0
 
@@ -354,8 +366,9 @@ def test_fused_advance_matches_unfused(name, residual):
     n = case.n
     announce(f"nn fused vs unfused {name} residual={residual} n={n}")
     net, _ = _random_net(128, case.n, 13, out_gain=50.0)
+    prev = name.endswith("prev")
     ctx, U, F, X, Y, n0 = _advance_pair(case, net, residual=residual,
-                                        inv_dt=1.0 / 6e-5 if name.endswith("prev") else 0.0)
+                                        inv_dt=1.0 / 6e-5 if prev else 0.0, carry=prev)
     assert ctx.status() & sph.STATUS_NN_RANGE == 0
     u, f = U.to_numpy(n), F.to_numpy(n)
     assert np.array_equal(u["id"], f["id"])
