@@ -152,14 +152,19 @@ def test_cubic_dam_break_runs_and_conserves():
     assert np.all(got["rho"][got["type"] == cases.BOUNDARY] >= np.float32(p["rho0"]))
 
 
-@pytest.mark.parametrize("opts", [sph.OPTION_SYMPLECTIC,
-                                  sph.OPTION_SYMPLECTIC | sph.OPTION_CUBIC | sph.OPTION_RHO_FLOOR])
-def test_symplectic_step_matches_oracle(opts):
+@pytest.mark.parametrize("opts,state", [
+    (sph.OPTION_SYMPLECTIC, "c1"),
+    (sph.OPTION_SYMPLECTIC | sph.OPTION_CUBIC | sph.OPTION_RHO_FLOOR, "c1"),
+    (sph.OPTION_SYMPLECTIC, "slab"),
+])
+def test_symplectic_step_matches_oracle(opts, state):
     """One symplectic sph_step (two interactions) from an FP32 state against
-    the oracle's half step, half-state interaction and full step."""
-    case = cases.perturb(cases.case_c1(), 6)
+    the oracle's half step, half-state interaction and full step; the slab
+    state has ghosts (untouched) and migrants (sorted behind the domain)."""
+    case = (cases.perturb(cases.case_c1(), 6) if state == "c1"
+            else cases.perturb(cases.small_slab(), 7))
     p, n = _with(case, opts), case.n
-    announce(f"symplectic step opts={opts} n={n}")
+    announce(f"symplectic step opts={opts} {state} n={n}")
     ctx = sph.Context(p, n)
     cur = sph.DeviceState.from_numpy(case.state, capacity=n)
     nxt = sph.DeviceState.empty(n)
