@@ -4,7 +4,8 @@
   configuration that bench.py times (sph_step) and through the separate
   entry points: sort products bit-exact, the full interaction against the
   full FP64 oracle (normwise 1e-4, per-particle neighbour counts exact),
-  the updated state at sampled particles.
+  the updated state at sampled particles; the same for the cubic-spline
+  interaction and the symplectic step.
 * 8.8M-particle slab with ghosts and migrants: raw (key, id) pairs and the
   whole sorted state, tables and packing ranges bit-exact; interaction on
   sampled particles that the oracle computes one by one.
@@ -85,6 +86,57 @@ def test_c2_step_sampled(c2):
     for k in ("x", "y", "z"):
         assert np.all(np.abs(got[k][sel] - ref[k]) <= 2 * ulp32(ref[k]) + 1e-3 * np.abs(ref[k] - s0[k]))
     assert fl.sum() > 10000
+    assert ctx.status() & (sph.STATUS_NONFINITE | sph.STATUS_DT | sph.STATUS_RUN_OVERFLOW) == 0
+
+
+def test_c2_cubic_full_interaction(c2):
+    """The cubic-spline interaction at the benchmark workload against the full
+    FP64 oracle with the same option."""
+    p, n = dict(c2.params, options=sph.OPTION_CUBIC), c2.n
+    announce(f"c2 cubic interact n={n}")
+    ctx = sph.Context(p, n)
+    _, out = gpu_sort(ctx, c2.state, n)
+    rates = sph.make_rates(n)
+    ctx.interact(out, n, rates)
+    torch.cuda.synchronize()
+    srt = oracle.sort_state(p, c2.state)
+    g = {k: v.cpu().numpy() for k, v in rates.items()}
+    err, acc = interact_compare(p, srt, g)
+    print("c2 cubic", err, flush=True)
+    for k, v in err.items():
+        assert v <= TOL, (k, v)
+    assert ctx.pairs() == int(acc["npair"].sum())
+
+
+def test_c2_symplectic_step_sampled(c2):
+    """One symplectic sph_step at the benchmark workload: the oracle's half
+    step of every particle, the half-state interaction and the full step on
+    sampled particles."""
+    p, n = dict(c2.params, options=sph.OPTION_SYMPLECTIC), c2.n
+    announce(f"c2 symplectic step sampled n={n}")
+    ctx = sph.Context(p, n)
+    cur = sph.DeviceState.from_numpy(c2.state, capacity=n)
+    nxt = sph.DeviceState.empty(n)
+    ctx.step(cur, nxt, n, 0)
+    torch.cuda.synchronize()
+    got = nxt.to_numpy(n)
+    dt = float(ctx.dt())
+    srt = oracle.sort_state(p, c2.state)
+    assert np.array_equal(got["id"], srt["state"]["id"])
+    n0 = int(srt["counts"][0])
+    acc = oracle.interact(p, srt)
+    half = oracle.symplectic_half(p, srt["state"], n0, dt, acc)
+    sel = _sample(n0, 20000, 2)
+    acc_h = oracle.interact(p, dict(srt, state=half), sel=sel)
+    s0 = {k: v[sel] for k, v in srt["state"].items()}
+    ref = oracle.symplectic_full(p, s0, {k: v[sel] for k, v in half.items()}, len(sel), dt, acc_h)
+    for k in ("vx", "vy", "vz", "rho"):
+        inc_ref = ref[k] - s0[k]
+        inc_gpu = got[k][sel].astype(np.float64) - s0[k]
+        excess = np.maximum(np.abs(inc_gpu - inc_ref) - ulp32(ref[k]), 0.0)
+        assert np.linalg.norm(excess) <= 1e-3 * np.linalg.norm(inc_ref), k
+    for k in ("x", "y", "z"):
+        assert np.all(np.abs(got[k][sel] - ref[k]) <= 2 * ulp32(ref[k]) + 1e-3 * np.abs(ref[k] - s0[k]))
     assert ctx.status() & (sph.STATUS_NONFINITE | sph.STATUS_DT | sph.STATUS_RUN_OVERFLOW) == 0
 
 
