@@ -7,13 +7,13 @@
 namespace sph {
 
 #ifndef SPH_INTERACT_CAP
-#define SPH_INTERACT_CAP 64
+#define SPH_INTERACT_CAP 76
 #endif
 #ifndef SPH_TEST_UNROLL
 #define SPH_TEST_UNROLL 8
 #endif
 #ifndef SPH_COL_SLACK
-#define SPH_COL_SLACK 24
+#define SPH_COL_SLACK 32
 #endif
 #ifndef SPH_FLUSH_UNROLL
 #define SPH_FLUSH_UNROLL 4
