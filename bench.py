@@ -101,6 +101,45 @@ def copy_probe(mib: int, reps: int) -> None:
                       "reps": reps}), flush=True)
 
 
+def machine_probe(reps: int) -> dict:
+    """What this GPU reaches with the library's own build flags: an FP32 FMA
+    loop (non-packed) and a 16-byte streaming copy (sph_probe_fma /
+    sph_probe_copy), next to torch's device copy. Context for the roofline
+    fractions, which stay quoted against the published peaks."""
+    import torch
+    from paper_1210_1017_amd import sph
+    blocks_fma, iters = 2048, 8192
+    out = torch.empty(blocks_fma * 256, dtype=torch.float32, device="cuda")
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    t_fma = timed(lambda: sph.probe_fma(out, blocks_fma, iters))
+    t_copy = timed(lambda: sph.probe_copy(src, dst, 1024))
+    t_torch = timed(lambda: dst.copy_(src))
+    if not torch.equal(dst, src):
+        raise RuntimeError("copy probe: destination differs from source")
+    fma = 16.0 * iters * blocks_fma * 256 / t_fma / 1e12
+    copy = 2.0 * nbytes / t_copy / 1e9
+    return {"fma_tflops": fma, "fma_frac_of_nonpacked_peak": fma / PEAK_FP32_NONPACKED_TFLOPS,
+            "copy_gbs": copy, "copy_frac_of_hbm_peak": copy / PEAK_HBM_GBS,
+            "torch_copy_gbs": 2.0 * nbytes / t_torch / 1e9,
+            "fma": f"{blocks_fma} x 256 lanes x {iters} iterations of 8 independent FP32 FMAs",
+            "copy": "1 GiB read + 1 GiB written, 16-byte vectors, 4 per lane per pass, 1024 x 256 lanes",
+            "reps": reps}
+
+
 def variants(case, steps: int, warmup: int = 10) -> dict:
     """Steps/s and pair interactions/s of the step variants (sph_params.options)
     on the same workload, each from the initial state; the interaction phase
@@ -278,6 +317,9 @@ def main() -> int:
     ap.add_argument("--variant-steps", type=int, default=200,
                     help="timed steps of each step variant (cubic kernel, symplectic "
                          "integrator) added to the JSON line (0: skip)")
+    ap.add_argument("--probe-reps", type=int, default=10,
+                    help="repeats of the machine probes (FMA loop, streaming copy) added "
+                         "to the JSON line (0: skip)")
     ap.add_argument("--surrogate-steps", type=int, default=1000,
                     help="steps of the surrogate-vs-plain comparison added to the JSON line "
                          "when trained weights are present (0: skip)")
@@ -358,6 +400,9 @@ def main() -> int:
                      "dt_update": float(phases[:, 2].mean())},
         "roofline": roof,
     }
+    if args.probe_reps > 0:
+        out["machine"] = machine_probe(args.probe_reps)
+        roof["frac_measured_fma"] = achieved / out["machine"]["fma_tflops"]
     if args.variant_steps > 0:
         out["variants"] = variants(case, args.variant_steps)
     from paper_1210_1017_amd import surrogate

@@ -167,7 +167,8 @@ int sph_abi_version(void);
 const char *sph_error_string(int code);
 
 /* Last error message recorded on ctx (empty string if none); ctx may be NULL
- * for errors of sph_create. The pointer stays valid until the next call. */
+ * for errors of sph_create and of the machine probes. The pointer stays valid
+ * until the next call. */
 const char *sph_last_error(const sph_ctx *ctx);
 
 /* Validate params, bind the current HIP device and allocate all scratch for
@@ -248,6 +249,26 @@ int sph_timing_read(sph_ctx *ctx, float *ms, uint32_t max_steps, uint32_t *count
  * of the cell tables (ncells each) into caller buffers. */
 int sph_copy_keys(sph_ctx *ctx, uint32_t *keys_out, uint32_t n, void *stream);
 int sph_copy_cell_tables(sph_ctx *ctx, uint32_t *begin_out, uint32_t *end_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Machine probes (no context). The published MI355X peaks are what the
+ * roofline fractions are quoted against; these two kernels measure what the
+ * running GPU reaches with the same build flags, as context for them.
+ *
+ * sph_probe_fma: `blocks` workgroups of 256 lanes; each lane runs `iters`
+ * iterations of 8 independent FP32 fused multiply-adds (non-packed, 16 FLOP
+ * per lane per iteration) and writes one float to out[blocks * 256]
+ * (device, caller-owned), which keeps the work. Needs 1 <= blocks <= 2^20
+ * and iters >= 1.
+ * sph_probe_copy: copies `bytes` from src to dst (device, caller-owned,
+ * 16-byte aligned, not overlapping; bytes a multiple of 16, at most 2^40)
+ * with 16-byte loads and stores in a grid-stride loop over `blocks`
+ * workgroups of 256 lanes (1 <= blocks <= 2^20).
+ * Both are asynchronous on `stream`; time them with events. Invalid
+ * arguments give SPH_E_INVALID_ARG and a launch failure SPH_E_HIP, with the
+ * message in sph_last_error(NULL). */
+int sph_probe_fma(float *out, uint32_t blocks, int32_t iters, void *stream);
+int sph_probe_copy(const void *src, void *dst, uint64_t bytes, uint32_t blocks, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Precision variant. The same step (sort, interaction, dt, Verlet) on a state

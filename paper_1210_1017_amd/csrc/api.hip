@@ -495,6 +495,31 @@ int sph_copy_cell_tables(sph_ctx *c, uint32_t *begin_out, uint32_t *end_out, voi
     return e == hipSuccess ? SPH_OK : hip_fail(c, e, "copy cell tables");
 }
 
+// ------------------------------------------------------------ machine probes
+
+int sph_probe_fma(float *out, uint32_t blocks, int32_t iters, void *stream) {
+    g_create_err.clear();
+    if (!out || blocks == 0 || blocks > (1u << 20) || iters < 1)
+        return fail(nullptr, SPH_E_INVALID_ARG,
+                    "probe_fma: needs out, 1 <= blocks <= 2^20 and iters >= 1");
+    hipError_t e = launch_probe_fma(out, blocks, iters, (hipStream_t)stream);
+    return e == hipSuccess ? SPH_OK : hip_fail(nullptr, e, "probe_fma");
+}
+
+int sph_probe_copy(const void *src, void *dst, uint64_t bytes, uint32_t blocks, void *stream) {
+    g_create_err.clear();
+    if (!src || !dst || bytes % 16 != 0 || bytes > (1ull << 40) || blocks == 0 ||
+        blocks > (1u << 20) || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
+        return fail(nullptr, SPH_E_INVALID_ARG,
+                    "probe_copy: needs 16-byte aligned buffers, bytes a multiple of 16 "
+                    "(at most 2^40) and 1 <= blocks <= 2^20");
+    const uintptr_t a = (uintptr_t)src, d = (uintptr_t)dst;
+    if (bytes && a < d + bytes && d < a + bytes)
+        return fail(nullptr, SPH_E_INVALID_ARG, "probe_copy: source and destination overlap");
+    hipError_t e = launch_probe_copy(src, dst, bytes, blocks, (hipStream_t)stream);
+    return e == hipSuccess ? SPH_OK : hip_fail(nullptr, e, "probe_copy");
+}
+
 // ------------------------------------------------------------ variants
 
 static bool cstate_ok(const sph_cstate *s) {

@@ -189,6 +189,11 @@ hipError_t launch_sym_half(sph_ctx *c, const sph_soa &st, const float *ax, const
                            const float *az, const float *arho, uint32_t n, hipStream_t s);
 hipError_t launch_sym_full(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
                            const float *az, const float *arho, uint32_t n, hipStream_t s);
+
+// machine probes (probe.hip)
+hipError_t launch_probe_fma(float *out, uint32_t blocks, int iters, hipStream_t s);
+hipError_t launch_probe_copy(const void *src, void *dst, uint64_t bytes, uint32_t blocks,
+                             hipStream_t s);
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
                          const float *az, const float *arho, uint32_t n, uint64_t step,
                          hipStream_t s);

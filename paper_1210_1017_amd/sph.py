@@ -162,8 +162,33 @@ def lib() -> C.CDLL:
                                      f32, f32, f32, i32, vp]
         L.sph_nn_perturb.argtypes = [vp, P(SoA), u32, u32, f32, f32, vp]
         L.sph_nn_judge.argtypes = [vp, P(SoA), P(SoA), P(SoA), vp, vp, u32, P(C.c_double), vp]
+        L.sph_probe_fma.argtypes = [vp, u32, C.c_int32, vp]
+        L.sph_probe_copy.argtypes = [vp, vp, u64, u32, vp]
         _lib = L
     return _lib
+
+
+def _probe_check(rc: int):
+    if rc != 0:
+        L = lib()
+        raise SphError(rc, f"{L.sph_error_string(rc).decode()}: {L.sph_last_error(None).decode()}")
+
+
+def probe_fma(out, blocks: int, iters: int, stream=None):
+    """sph_probe_fma: 16 * iters FP32 FLOP per lane over blocks x 256 lanes;
+    ``out`` is a float32 device tensor of at least blocks * 256 elements."""
+    if out.dtype.itemsize != 4 or out.numel() < blocks * 256 or not out.is_cuda:
+        raise ValueError("out must be a float32 device tensor of blocks * 256 elements")
+    _probe_check(lib().sph_probe_fma(_addr(out), blocks, iters, _stream_ptr(stream)))
+
+
+def probe_copy(src, dst, blocks: int, stream=None):
+    """sph_probe_copy of all of ``src`` (a device tensor) into ``dst``."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("dst must be a device tensor at least as large as src")
+    _probe_check(lib().sph_probe_copy(_addr(src), _addr(dst), nbytes, blocks,
+                                      _stream_ptr(stream)))
 
 
 def header_functions() -> list[str]:

@@ -82,3 +82,20 @@ def test_null_arguments(L):
     assert L.sph_sort(None, None, None, 0, None) == -1
     assert L.sph_step(None, None, None, 0, 0, None) == -1
     assert L.sph_get_dt(None, None, None) == -1
+
+
+def test_probes_reject_bad_arguments(L):
+    """The machine probes validate before any launch (fake, never dereferenced
+    addresses: every call below is refused on the host)."""
+    a, b = C.c_void_p(1 << 20), C.c_void_p(1 << 30)
+    assert L.sph_probe_fma(None, 1, 1, None) == -1
+    assert L.sph_probe_fma(a, 0, 1, None) == -1
+    assert L.sph_probe_fma(a, (1 << 20) + 1, 1, None) == -1
+    assert L.sph_probe_fma(a, 1, 0, None) == -1
+    assert "iters" in L.sph_last_error(None).decode()
+    assert L.sph_probe_copy(None, b, 16, 1, None) == -1
+    assert L.sph_probe_copy(a, b, 24, 1, None) == -1                  # not a multiple of 16
+    assert L.sph_probe_copy(C.c_void_p((1 << 20) + 4), b, 16, 1, None) == -1  # misaligned
+    assert L.sph_probe_copy(a, C.c_void_p((1 << 20) + 64), 128, 1, None) == -1  # overlap
+    assert "overlap" in L.sph_last_error(None).decode()
+    assert L.sph_probe_copy(a, b, 16, 0, None) == -1
