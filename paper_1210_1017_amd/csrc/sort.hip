@@ -149,12 +149,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     uint32_t key[kSortItems];
     int32_t val[kSortItems];
     uint32_t rank[kSortItems];
+    // all of the tile's loads first: the ranking rounds below are separated
+    // by barriers, which loads are not moved across
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + tid;
         const bool valid = idx < n;
         key[r] = valid ? kin[idx] : 0xffffffffu;
         val[r] = valid ? vin[idx] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t idx = base + r * kSortThreads + tid;
+        const bool valid = idx < n;
         const uint32_t d = (key[r] >> shift) & 255u;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
