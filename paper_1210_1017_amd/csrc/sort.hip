@@ -70,8 +70,10 @@ hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_
 //   scan:    per digit, exclusive scan over tiles, and the digit total;
 //   scatter: per tile, a stable rank of each key among the tile's keys with
 //            the same digit (wave ballots over the 8 digit bits give the
-//            lanes holding the same digit), a reorder through LDS by digit,
-//            and coalesced runs written to their global positions.
+//            lanes holding the same digit; one count per round, wave and
+//            digit, then one prefix per digit over the tile), a reorder
+//            through LDS by digit, and coalesced runs written to their global
+//            positions.
 // Stability: keys are ranked in input order (round, wave, lane), so equal
 // keys keep their relative order in every pass.
 
@@ -124,14 +126,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     int32_t *__restrict__ vout, uint32_t n, int shift, uint32_t ntiles,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot) {
+    constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t s_k[kSortTile];
     __shared__ int32_t s_v[kSortTile];
-    __shared__ uint32_t s_cnt[kSortThreads / 64][256];
-    __shared__ uint32_t s_run[256];
+    __shared__ uint32_t s_cnt[kSortItems][NW][256];  // per (round, wave, digit) count, then prefix
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_glob[256];
-    __shared__ uint32_t s_w[kSortThreads / 64];
-    constexpr int NW = kSortThreads / 64;
+    __shared__ uint32_t s_w[NW];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t tile = blockIdx.x;
@@ -140,17 +141,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     // global start of each digit's run for this tile
     const uint32_t gbase = block_excl_scan<kSortThreads>(tot[tid], s_w);
     s_glob[tid] = gbase + hist[(uint32_t)tid * ntiles + tile];
-    s_run[tid] = 0;
 #pragma unroll
-    for (int k = 0; k < NW; k++) s_cnt[k][tid] = 0;
-    __syncthreads();
+    for (int r = 0; r < kSortItems; r++)
+#pragma unroll
+        for (int k = 0; k < NW; k++) s_cnt[r][k][tid] = 0;
 
-    const unsigned long long lt = (1ull << lane) - 1ull;
+    // all of the tile's loads first
     uint32_t key[kSortItems];
     int32_t val[kSortItems];
     uint32_t rank[kSortItems];
-    // all of the tile's loads first: the ranking rounds below are separated
-    // by barriers, which loads are not moved across
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + tid;
@@ -158,10 +157,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         key[r] = valid ? kin[idx] : 0xffffffffu;
         val[r] = valid ? vin[idx] : 0;
     }
+    __syncthreads();
+    // rank among the wave's lanes with the same digit in this round (ballots
+    // over the 8 digit bits); the first such lane records the count
+    const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
-        const uint32_t idx = base + r * kSortThreads + tid;
-        const bool valid = idx < n;
+        const bool valid = base + r * kSortThreads + tid < n;
         const uint32_t d = (key[r] >> shift) & 255u;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -170,32 +172,29 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             const unsigned long long m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t wr = (uint32_t)__popcll(peers & lt);
-        if (valid && wr == 0) s_cnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t pre = s_run[d];
+        rank[r] = (uint32_t)__popcll(peers & lt);
+        if (valid && rank[r] == 0) s_cnt[r][w][d] = (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit (one thread each): exclusive prefix over (round, wave), the
+    // input order of the tile, so equal digits keep their order
+    uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < NW; k++)
-            if (k < w) pre += s_cnt[k][d];
-        rank[r] = pre + wr;
-        __syncthreads();
-        uint32_t add = 0;
+    for (int r = 0; r < kSortItems; r++)
 #pragma unroll
         for (int k = 0; k < NW; k++) {
-            add += s_cnt[k][tid];
-            s_cnt[k][tid] = 0;
+            const uint32_t c = s_cnt[r][k][tid];
+            s_cnt[r][k][tid] = run;
+            run += c;
         }
-        s_run[tid] += add;
-        __syncthreads();
-    }
-    s_off[tid] = block_excl_scan<kSortThreads>(s_run[tid], s_w);
+    s_off[tid] = block_excl_scan<kSortThreads>(run, s_w);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + tid;
         if (idx < n) {
             const uint32_t d = (key[r] >> shift) & 255u;
-            const uint32_t pos = s_off[d] + rank[r];
+            const uint32_t pos = s_off[d] + s_cnt[r][w][d] + rank[r];
             s_k[pos] = key[r];
             s_v[pos] = val[r];
         }
