@@ -34,11 +34,24 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_hist(KParams kp, const fl
     h[tid] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
-#pragma unroll 4
+    // all of the thread's positions and types first (clamped index: in bounds
+    // for every lane), then the keys
+    float px[kSortItems], py[kSortItems], pz[kSortItems];
+    uint8_t pt[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t idx = base + r * kSortThreads + tid;
+        const uint32_t ic = idx < n ? idx : n - 1u;
+        px[r] = x[ic];
+        py[r] = y[ic];
+        pz[r] = z[ic];
+        pt[r] = type[ic];
+    }
+#pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + tid;
         if (idx < n) {
-            const uint32_t key = cell_key(kp, x[idx], y[idx], z[idx], type[idx]);
+            const uint32_t key = cell_key(kp, px[r], py[r], pz[r], pt[r]);
             keys[idx] = key;
             vals[idx] = (int32_t)idx;
             atomicAdd(&h[key & 255u], 1u);

@@ -41,16 +41,20 @@ __device__ __forceinline__ uint32_t cell_key(const KParams &kp, float px, float 
     const float tx = (px - kp.ox) * kp.inv_cs;
     const float ty = (py - kp.oy) * kp.inv_cs;
     const float tz = (pz - kp.oz) * kp.inv_cs;
-    const bool inside = (tx >= 0.0f && tx < (float)kp.ncx) && (ty >= 0.0f && ty < (float)kp.ncy) &&
-                        (tz >= 0.0f && tz < (float)kp.ncz);
-    if (!inside) return 3u << kp.cell_bits;
-    const uint32_t cx = (uint32_t)(int)floorf(tx), cy = (uint32_t)(int)floorf(ty),
-                   cz = (uint32_t)(int)floorf(tz);
+    // no short-circuit and no early return: every input is needed up front,
+    // so a caller's loads of x, y, z and type are issued together instead of
+    // one after another behind branches
+    const bool inside = (tx >= 0.0f) & (tx < (float)kp.ncx) & (ty >= 0.0f) &
+                        (ty < (float)kp.ncy) & (tz >= 0.0f) & (tz < (float)kp.ncz);
+    // clamped only so that the conversions of an outside (or NaN) coordinate
+    // stay defined; inside particles are unchanged by the clamp
+    const uint32_t cx = (uint32_t)(int)floorf(fminf(fmaxf(tx, 0.0f), (float)(kp.ncx - 1)));
+    const uint32_t cy = (uint32_t)(int)floorf(fminf(fmaxf(ty, 0.0f), (float)(kp.ncy - 1)));
+    const uint32_t cz = (uint32_t)(int)floorf(fminf(fmaxf(tz, 0.0f), (float)(kp.ncz - 1)));
     const uint32_t cell = (cx * (uint32_t)kp.ncy + cy) * (uint32_t)kp.ncz + cz;
-    uint32_t label = 0;
-    if (kp.slab_mode && type != kGhost)
-        label = px < kp.slab_xlo ? 1u : (px >= kp.slab_xhi ? 2u : 0u);
-    return (label << kp.cell_bits) | cell;
+    const uint32_t lab = px < kp.slab_xlo ? 1u : (px >= kp.slab_xhi ? 2u : 0u);
+    const uint32_t label = (kp.slab_mode && type != kGhost) ? lab : 0u;
+    return inside ? (label << kp.cell_bits) | cell : 3u << kp.cell_bits;
 }
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin. Renumber them
