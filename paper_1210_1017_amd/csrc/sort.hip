@@ -99,11 +99,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
     h[tid] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
-#pragma unroll 4
+    uint32_t k[kSortItems];  // all loads first (clamped index), then the counts
+#pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + tid;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+        k[r] = keys[idx < n ? idx : n - 1u];
     }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++)
+        if (base + r * kSortThreads + tid < n) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
 }
