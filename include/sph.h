@@ -56,8 +56,12 @@ enum {
 enum {
     SPH_S_NONFINITE = 1u << 0,    /* non-finite position/velocity/density after an update */
     SPH_S_DT = 1u << 1,           /* dt not finite or not positive                        */
-    SPH_S_RUN_OVERFLOW = 1u << 2, /* a 3-cell neighbour run held > 4095 particles: the
-                                     excess was skipped, results invalid                  */
+    SPH_S_RUN_OVERFLOW = 1u << 2, /* cell + offset interaction or surrogate rows: a
+                                     3-cell neighbour run held more than 4096 particles
+                                     (their 12-bit run offsets): the excess was skipped,
+                                     results of that call invalid. The plain interaction
+                                     addresses candidates by full indices and searches
+                                     any run completely                                   */
     SPH_S_EXCLUDED = 1u << 3,     /* some particles lie outside the cell grid (label 3)   */
     SPH_S_NN_RANGE = 1u << 4,     /* surrogate: a result was non-finite or its density
                                      left the allowed band (sph_nn_apply, sph_nn_advance) */
@@ -118,7 +122,9 @@ enum {
 /* Feature bits of sph_params.features. */
 enum {
     SPH_F_CELL = 1u << 0, /* cell + offset position path (sph_cstate, sph_c*)  */
-    SPH_F_FP64 = 1u << 1  /* FP64 reference path (sph_dstate, sph_d*)          */
+    SPH_F_FP64 = 1u << 1, /* FP64 reference path (sph_dstate, sph_d*)          */
+    SPH_F_SURROGATE = 1u << 2 /* rows, outputs and rates of sph_nn_advance:
+                                 capacity x (SPH_NN_IN x 2 + 32) bytes         */
 };
 
 /* Structure-of-arrays particle state; every pointer is a device array of
@@ -488,9 +494,11 @@ int sph_nn_apply(sph_ctx *ctx, sph_soa *sorted, const float *y, const float *rat
                  int flags, void *stream);
 
 /* One surrogate advance: sort cur into next (as sph_sort), build every
- * particle's input row (into buffers the context allocates on the first call:
- * capacity x SPH_NN_IN bfloat16 rows, 4 FP32 rates and 4 FP32 outputs per
- * particle), then one kernel runs the network (width 128) on tiles of 64 rows
+ * particle's input row (into buffers sph_create allocated for a context with
+ * the SPH_F_SURROGATE feature: capacity x SPH_NN_IN bfloat16 rows, 4 FP32
+ * rates and 4 FP32 outputs per particle; without the feature the call fails
+ * with SPH_E_STATE and allocates nothing), then one kernel runs the network
+ * (width 128) on tiles of 64 rows
  * and the result is applied to next as sph_nn_apply does, with the rows'
  * rates if flags has SPH_NN_RESIDUAL (a network trained on targets with
  * rates) and without them otherwise, and with SPH_NN_CARRY_PREV as there. */

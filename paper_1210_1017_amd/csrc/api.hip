@@ -105,11 +105,11 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     if (p->gamma != 7.0)
         return fail(nullptr, SPH_E_INVALID_ARG, "gamma must be 7 (Tait law of the method)");
     if ((p->options & ~(int32_t)(SPH_O_CUBIC | SPH_O_RHO_FLOOR | SPH_O_SYMPLECTIC)) != 0 ||
-        (p->features & ~(uint32_t)(SPH_F_CELL | SPH_F_FP64)) != 0)
+        (p->features & ~(uint32_t)(SPH_F_CELL | SPH_F_FP64 | SPH_F_SURROGATE)) != 0)
         return fail(nullptr, SPH_E_INVALID_ARG, "unknown option or feature bits");
     if (p->options != 0 && p->features != 0)
         return fail(nullptr, SPH_E_INVALID_ARG,
-                    "the cell and FP64 paths keep the Wendland kernel: options must be 0");
+                    "the cell, FP64 and surrogate paths keep the Wendland kernel: options must be 0");
     for (int a = 0; a < 3; a++)
         if (p->ncell[a] < 1 || !isfinite(p->origin[a]) || !isfinite(p->g[a]))
             return fail(nullptr, SPH_E_INVALID_ARG, "bad grid or gravity on axis %d", a);
@@ -205,6 +205,12 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     if (p->features & SPH_F_FP64) {
         ALLOC(c->p64, cap * sizeof(double));
         ALLOC(c->drate, 4 * cap * sizeof(double));
+    }
+    if (p->features & SPH_F_SURROGATE) {
+        // rows, network outputs and pair-sum rates of every particle for sph_nn_advance
+        ALLOC(c->nn_x, cap * SPH_NN_IN * 2);
+        ALLOC(c->nn_y, cap * SPH_NN_OUT * sizeof(float));
+        ALLOC(c->nn_rate, cap * 4 * sizeof(float));
     }
 #undef ALLOC
     if (e == hipSuccess) e = hipMemset(c->info, 0, sizeof(DevInfo));
@@ -920,21 +926,9 @@ int sph_nn_advance(sph_ctx *c, const sph_mlp *m, const sph_soa *cur, sph_soa *ne
     if (cur->x == next->x || cur->rho == next->rho || cur->type == next->type || cur->id == next->id)
         return fail(c, SPH_E_INVALID_ARG, "cur and next must not share arrays");
     hipStream_t s = (hipStream_t)stream;
-    if (c->nn_x_rows < c->capacity) {
-        // rows and outputs of every particle: allocated once per context, on first use
-        if (c->nn_x) (void)hipFree(c->nn_x);
-        if (c->nn_y) (void)hipFree(c->nn_y);
-        if (c->nn_rate) (void)hipFree(c->nn_rate);
-        c->nn_x = nullptr;
-        c->nn_y = nullptr;
-        c->nn_rate = nullptr;
-        c->nn_x_rows = 0;
-        hipError_t e = hipMalloc(&c->nn_x, (size_t)c->capacity * SPH_NN_IN * 2);
-        if (e == hipSuccess) e = hipMalloc((void **)&c->nn_y, (size_t)c->capacity * SPH_NN_OUT * 4);
-        if (e == hipSuccess) e = hipMalloc((void **)&c->nn_rate, (size_t)c->capacity * 16);
-        if (e != hipSuccess) return hip_fail(c, e, "surrogate row buffer");
-        c->nn_x_rows = c->capacity;
-    }
+    if (!(c->features & SPH_F_SURROGATE))
+        return fail(c, SPH_E_STATE,
+                    "sph_nn_advance needs a context created with the SPH_F_SURROGATE feature");
     if ((r = do_sort(c, cur, next, n, s))) return r;
     float *rates = (flags & SPH_NN_RESIDUAL) ? c->nn_rate : nullptr;
     hipError_t e = launch_nn_features(c, *next, nullptr, n, *scales, c->nn_x, 1, rates, s);

@@ -6,30 +6,36 @@
 
 namespace sph {
 
-#ifndef SPH_INTERACT_CAP
-#define SPH_INTERACT_CAP 76
+#ifndef SPH_INTERACT_ENT
+#define SPH_INTERACT_ENT 19
 #endif
 #ifndef SPH_TEST_UNROLL
 #define SPH_TEST_UNROLL 8
 #endif
-#ifndef SPH_COL_SLACK
-#define SPH_COL_SLACK 32
+#ifndef SPH_ENT_SLACK
+#define SPH_ENT_SLACK 3
 #endif
-#ifndef SPH_FLUSH_UNROLL
-#define SPH_FLUSH_UNROLL 4
+#ifndef SPH_TEST_PIPE
+#define SPH_TEST_PIPE 0
 #endif
-#define SPH_PRAGMA(x) _Pragma(#x)
-#define SPH_UNROLL(n) SPH_PRAGMA(unroll n)
-constexpr int kCap = SPH_INTERACT_CAP;   // neighbour entries buffered per lane before a flush
-// At each run boundary the whole wave flushes together if any lane has more
-// than kCap - kColSlack entries (a converged flush); inside a run a lane
-// flushes alone only if it reaches kCap (rare with a suitable slack).
-constexpr int kColSlack = SPH_COL_SLACK;
-constexpr int kUnroll = SPH_TEST_UNROLL; // candidates loaded together in the support test
-constexpr int kSlots = kCap + kUnroll;   // list slots (a group of candidates may overrun kCap)
+#ifndef SPH_INTERACT_WAVES_PER_EU
+#define SPH_INTERACT_WAVES_PER_EU 4
+#endif
+// Hit-mask entries per lane: a lane's list holds up to kEnt - 1 entries and
+// one sentinel slot.
+constexpr int kEnt = SPH_INTERACT_ENT;
+// At each run boundary the whole wave flushes together if any lane could not
+// take kEntSlack more entries (a converged flush); inside a run a lane
+// flushes alone only if its list fills (a run longer than 32 kEntSlack
+// candidates).
+constexpr int kEntSlack = SPH_ENT_SLACK;
+constexpr int kUnroll = SPH_TEST_UNROLL;  // candidates loaded together in the support test
+static_assert(32 % kUnroll == 0, "a hit mask covers whole groups of candidates");
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9 buffer resource: 32-bit raw dwords
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v3f __attribute__((ext_vector_type(3)));
+typedef uint32_t v3u __attribute__((ext_vector_type(3)));
 
 // One lane per particle i of the label-0 prefix (Sec. 3.2: one thread per
 // particle, neighbours in its own cell and the 26 adjacent ones). With an
@@ -38,26 +44,35 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 //
 // Two phases per lane keep the wave converged on the expensive part:
 //   test:    every candidate of the 9 runs gets the FP32 support test
-//            |r_ij|^2 < 4h^2 (groups of kUnroll bounds-checked buffer loads in
-//            flight); hits are appended to the lane's own list in LDS as
-//            16-bit (run, offset) entries;
-//   compute: the pair terms are evaluated for the listed neighbours only.
+//            |r_ij|^2 < 4h^2 (groups of kUnroll bounds-checked buffer loads
+//            in flight). The outcome is shifted into a 32-bit hit mask, one
+//            bit per candidate (the sign of r_ij^2 - 4h^2, which is exact);
+//            every 32 candidates of a run (and at its end) the mask and the
+//            index of its first candidate go to the lane's list in LDS if any
+//            bit is set;
+//   compute: the pair terms are evaluated for the set bits only, each lane
+//            walking its own list; a lane whose list is used up evaluates its
+//            own particle (the sentinel entry), which adds exactly zero.
 // The list is flushed early if it fills (dense regions), so any neighbour
-// count is handled. The gradient constant and the mass are applied once per
-// particle after the sums: grad_i W_ij = kgrad G(q) r_ij with
+// count and any run length are handled. The gradient constant and the mass
+// are applied once per particle after the sums: grad_i W_ij = kgrad G(q) r_ij
+// with
 //   Wendland C2:   G = (1 - q/2)^3,                         kgrad = -5 aD / h^2;
 //   cubic spline:  G = 4 - 3q (q < 1), (2 - q)^2 / q (q >= 1), kgrad = -3 aD / (4 h^2)
 // (the two aD of the kernels' definitions differ).
 template <bool kCubic>
-__global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
+__global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_eu(
+    SPH_INTERACT_WAVES_PER_EU, SPH_INTERACT_WAVES_PER_EU))) void k_interact(
     KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4, uint32_t n,
     const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
     const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend,
     DevInfo *__restrict__ info, float *__restrict__ oax, float *__restrict__ oay,
     float *__restrict__ oaz, float *__restrict__ orho, float *__restrict__ opress,
     float *__restrict__ onu, uint32_t *__restrict__ onpair) {
-    __shared__ uint16_t s_list[kSlots][kInteractThreads];
-    __shared__ uint32_t s_base[9][kInteractThreads];
+    // entry = (byte offset 16 j of the first candidate of the mask, hit mask
+    // with the first candidate in bit 31); [slot][lane]: a wave's 64 lanes
+    // touch 512 consecutive bytes
+    __shared__ uint2 s_ent[kEnt][kInteractThreads];
     __shared__ float s_rdt[kInteractThreads / 64];
     __shared__ uint32_t s_rnp[kInteractThreads / 64];
     __shared__ uint32_t s_rnc[kInteractThreads / 64];
@@ -114,42 +129,80 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
                 const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
                 drho = fmaf(F, vr, drho);
                 // one reciprocal for mu = h vr / (r^2 + eta^2) and for the
-                // viscous term -alpha cbar mu / rhobar
+                // viscous term -alpha cbar mu / rhobar; h (in nu) and kvis
+                // (in the force factor) are applied outside the product
                 const float rs = rhoi + vj.w;
                 const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
                 const float vR = vr * R;
-                const float mu = (h * rs) * vR;
-                nu = fmaxf(nu, fabsf(mu));
+                nu = fmaxf(nu, fabsf(rs * vR));  // |mu| / h
                 const float sj = vj.w * kp.inv_rho0;
-                const float visc = vr < 0.0f ? kvis * fmaf(sj * sj, sj, si3) * vR : 0.0f;
-                const float f = (Pi + pj.w + visc) * F;
+                const float visc = vr < 0.0f ? fmaf(sj * sj, sj, si3) * vR : 0.0f;  // Pi / kvis
+                const float f = fmaf(kvis, visc, Pi + pj.w) * F;
                 axs = fmaf(f, dx, axs);
                 ays = fmaf(f, dy, ays);
                 azs = fmaf(f, dz, azs);
             };
-            auto flush = [&](int cnt) {
-                SPH_UNROLL(SPH_FLUSH_UNROLL)
-                for (int k = 0; k < cnt; k++) {
-                    const uint32_t e = s_list[k][tid];
-                    const uint32_t j = s_base[e >> kRunBits][tid] + (e & kRunMax);
-                    pair(__builtin_amdgcn_raw_buffer_load_b128(rp, j * 16u, 0, 0),
-                         __builtin_amdgcn_raw_buffer_load_b128(rv, j * 16u, 0, 0));
+
+            // compute phase over the cnt entries of the lane's list holding
+            // nhit set bits. The sentinel (16 i, bit 31) after the last entry
+            // stands in for every position past the end, so a group of four
+            // never needs a mask. The next group's indices are drawn from the
+            // masks while the current group's neighbour data is in flight.
+            auto flush = [&](uint32_t cnt, uint32_t nhit) {
+                s_ent[cnt][tid] = make_uint2(i * 16u, 0x80000000u);
+                uint32_t pk = 0, cb = 0, cj = 0;
+                uint2 nx = s_ent[0][tid];
+                auto draw = [&](uint32_t (&jj)[4]) {
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const bool empty = cb == 0u;  // take the prefetched entry
+                        cb = empty ? nx.y : cb;
+                        cj = empty ? nx.x : cj;
+                        pk = min(pk + (empty ? 1u : 0u), cnt);
+                        nx = s_ent[pk][tid];
+                        const uint32_t off = (uint32_t)__builtin_clz(cb);
+                        jj[u] = cj + (off << 4);  // byte offset of j
+                        cb &= 0x7fffffffu >> off;
+                    }
+                };
+                uint32_t jn[4];
+                draw(jn);
+                for (uint32_t t = 0; t < nhit; t += 4) {
+                    v4f qp[4], qv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        qp[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, jn[u], 0, 0);
+                        qv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, jn[u], 0, 0);
+                    }
+                    draw(jn);
+#pragma unroll
+                    for (int u = 0; u < 4; u++) pair(qp[u], qv[u]);
                 }
             };
 
             // The list keeps i itself (found in its own run): the self pair has
             // r_ij = v_ij = 0 and adds exactly zero to every sum and to nu, so
-            // it costs one list entry instead of a j != i test per candidate.
-            uint16_t *const lp0 = &s_list[0][tid];
-            uint16_t *const lpcap = &s_list[kCap][tid];
-            uint16_t *lp = lp0;  // next free slot of this lane's list (stride: one slot row)
+            // it costs one bit instead of a j != i test per candidate.
+            uint32_t lp = 0;    // entries in the lane's list
+            uint32_t nhit = 0;  // set bits in them
             uint32_t listed = 0;
+            auto put = [&](uint32_t j16, uint32_t b) {
+                s_ent[lp][tid] = make_uint2(j16, b);
+                lp += b != 0u ? 1u : 0u;
+                nhit += (uint32_t)__builtin_popcount(b);
+                if (lp >= (uint32_t)(kEnt - 1)) {  // full: this lane alone
+                    flush(lp, nhit);
+                    listed += nhit;
+                    lp = 0;
+                    nhit = 0;
+                }
+            };
             for (int col = 0; col < 9; col++) {
-                if (kColSlack > 0 && __any(lp > lpcap - (size_t)kColSlack * kInteractThreads)) {
-                    const int cnt = (int)((lp - lp0) / kInteractThreads);
-                    flush(cnt);
-                    listed += cnt;
-                    lp = lp0;
+                if (__any(lp > (uint32_t)(kEnt - 1 - kEntSlack))) {
+                    flush(lp, nhit);
+                    listed += nhit;
+                    lp = 0;
+                    nhit = 0;
                 }
                 const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
                 uint32_t jb = 0, je = 0;
@@ -158,43 +211,67 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact(
                     jb = cbeg[c0 + zlo];
                     je = cend[c0 + zhi];
                 }
-                if (je - jb > kRunMax + 1u) {
-                    atomicOr(&info->flags, (uint32_t)SPH_S_RUN_OVERFLOW);
-                    je = jb + kRunMax + 1u;
-                }
-                s_base[col][tid] = jb;
                 const uint32_t len = je - jb;
                 ncand += len;
                 const uint32_t voff = jb * 16u;
-                // k0 is the same for every lane (the group counter of the wave), so
-                // the list entry (col << 12) + k0 + u is wave-uniform as well.
-                for (uint32_t k0 = 0; k0 < len; k0 += kUnroll) {
-                    v4f q[kUnroll];
+                uint32_t bits = 0;
+                uint32_t k0 = 0;
+                // k0 is the same for every lane still in its run (the group
+                // counter of the wave): the loads take it as a scalar offset
+                auto load = [&](v3f (&q)[kUnroll], uint32_t k) {
 #pragma unroll
                     for (int u = 0; u < kUnroll; u++)  // past the run: in-bounds data or 0
-                        q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
-                    // append without a branch: the entry is always written to the
-                    // free slot, which only a hit consumes
-                    const uint32_t lim = len - k0;  // candidates left in the run (>= 1)
+                        q[u] = __builtin_bit_cast(
+                            v3f, __builtin_amdgcn_raw_buffer_load_b96(rp, voff, (int)(k * 16u + 16u * u), 0));
+                };
+                auto test = [&](const v3f (&q)[kUnroll], uint32_t k) {
 #pragma unroll
                     for (int u = 0; u < kUnroll; u++) {
                         const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
                         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        const bool hit = (u < (int)lim) & (r2 < kp.r2max);
-                        *lp = (uint16_t)(((uint32_t)col << kRunBits) + k0 + u);
-                        lp += hit ? kInteractThreads : 0;
+                        // bits = bits << 1 | (r2 < 4h^2): the sign of the
+                        // difference of two floats decides the comparison exactly
+                        bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(r2 - kp.r2max), 31);
                     }
-                    if (lp >= lpcap) {
-                        const int cnt = (int)((lp - lp0) / kInteractThreads);
-                        flush(cnt);
-                        listed += cnt;
-                        lp = lp0;
+                    if ((k & 31u) == 32u - kUnroll) {  // 32 candidates tested
+                        const uint32_t c0 = k + kUnroll - 32u;
+                        const uint32_t v = len - c0;  // of which inside the run
+                        put(voff + c0 * 16u, v >= 32u ? bits : bits & ~(0xffffffffu >> v));
+                        bits = 0;
                     }
+                };
+#if SPH_TEST_PIPE
+                // two groups in flight: the next group's loads are issued
+                // before the current group is tested
+                v3f qa[kUnroll], qb[kUnroll];
+                if (len) load(qa, 0);
+                for (; k0 < len; k0 += 2 * kUnroll) {
+                    if (k0 + kUnroll < len) load(qb, k0 + kUnroll);
+                    test(qa, k0);
+                    if (k0 + kUnroll >= len) {
+                        k0 += kUnroll;
+                        break;
+                    }
+                    if (k0 + 2 * kUnroll < len) load(qa, k0 + 2 * kUnroll);
+                    test(qb, k0 + kUnroll);
+                }
+#else
+                for (; k0 < len; k0 += kUnroll) {
+                    v3f q[kUnroll];
+                    load(q, k0);
+                    test(q, k0);
+                }
+#endif
+                const uint32_t tail = k0 & 31u;  // candidates tested since the last mask
+                if (tail) {
+                    const uint32_t c0 = k0 - tail;
+                    const uint32_t v = len - c0;  // 1 .. tail
+                    put(voff + c0 * 16u, (bits << (32u - tail)) & ~(0xffffffffu >> v));
                 }
             }
-            const int cnt = (int)((lp - lp0) / kInteractThreads);
-            flush(cnt);
-            npair = listed + cnt - 1u;  // minus the self entry
+            flush(lp, nhit);
+            npair = listed + nhit - 1u;  // minus the self entry
+            nu *= h;
         }
         const float m = kp.mass, mk = kp.mass * (kCubic ? kp.kgrad_cubic : kp.kgrad);
         float ax = 0.f, ay = 0.f, az = 0.f, ar = 0.f;

@@ -81,10 +81,9 @@ struct sph_ctx {
     double *tot_part = nullptr;   // 8 doubles per totals block
     double *nn_part = nullptr;    // 8 doubles per surrogate-judge block
     double *nn_out = nullptr;     // 8 doubles: judge result
-    void *nn_x = nullptr;         // surrogate input rows of sph_nn_advance (lazily allocated)
+    void *nn_x = nullptr;         // surrogate input rows of sph_nn_advance (SPH_F_SURROGATE)
     float *nn_y = nullptr;        // its network outputs, 4 per row
     float *nn_rate = nullptr;     // the rows' pair-sum rates, 4 per row
-    size_t nn_x_rows = 0;
     uint32_t tot_blocks = 0;
     int last_path = 0;            // 0 plain, 1 cell, 2 FP64: which state the tables describe
     bool dt_in_info = false;      // the last step was symplectic: its dt is info->dt

@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("slab_xlo", C.c_double), ("slab_xhi", C.c_double),
                 ("capacity", C.c_uint32), ("features", C.c_uint32)]
 
-FEATURE_CELL, FEATURE_FP64 = 1, 2
+FEATURE_CELL, FEATURE_FP64, FEATURE_SURROGATE = 1, 2, 4
 OPTION_CUBIC, OPTION_RHO_FLOOR, OPTION_SYMPLECTIC = 1, 2, 4
 CSTATE_FIELDS = ("cell", "ox", "oy", "oz", "vx", "vy", "vz", "rho", "vxp", "vyp", "vzp", "rhop",
                  "type", "id")

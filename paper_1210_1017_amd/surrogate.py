@@ -143,7 +143,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
     for tr in range(n_traj):
         case = case_fn(seed * 100003 + tr)
         n, p = case.n, case.params
-        ctx = sph.Context(p, n)
+        ctx = sph.Context(p, n, sph.FEATURE_SURROGATE)
         if net is None:
             net = sph.Mlp(width, rows, train=True)
             net.init(seed)
@@ -257,7 +257,7 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
     Returns the final device state, wall time and books."""
     import torch
     n, p = case.n, case.params
-    ctx = ctx or sph.Context(p, n)
+    ctx = ctx or sph.Context(p, n, sph.FEATURE_SURROGATE)
     cur = sph.DeviceState.from_numpy(case.state)
     bufs = [sph.DeviceState.empty(n) for _ in range(4)]
     ctx.clear_status()
@@ -371,7 +371,7 @@ def report(steps: int = 1000, weights: str | None = None, judge_every: int | Non
     import torch
     case = cases.case_c2(obstacle_seed=obstacle_seed)
     n = case.n
-    ctx = sph.Context(case.params, n)
+    ctx = sph.Context(case.params, n, sph.FEATURE_SURROGATE)
     net, cfg = load(weights or default_weights(), ctx)
     if judge_every:
         cfg.judge_every = judge_every

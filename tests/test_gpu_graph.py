@@ -85,3 +85,55 @@ def test_step_graph_replays_match_eager(options):
         assert ctx_g.counts()["n_label"] == n_label
         assert ctx_g.status() & (sph.STATUS_NONFINITE | sph.STATUS_DT) == 0
     del g
+
+
+def test_first_nn_advance_captured_in_graph():
+    """A context created with SPH_F_SURROGATE holds every buffer of
+    sph_nn_advance from sph_create on, so its very first call can be captured:
+    the replays of that capture give the bits of an eager advance from the
+    same state (each replay starts from the same cur, as the eager call did).
+    Without the feature the advance is refused and allocates nothing."""
+    from test_gpu_surrogate import _random_net, _scales
+
+    case = cases.perturb(cases.case_c1(), 6)
+    p, n = case.params, case.n
+    announce(f"graph capture of the first nn_advance n={n}")
+    net, _ = _random_net(128, 64, 23, out_gain=20.0)
+    sc = _scales(p)
+    dv, dr, dt4 = np.float32(0.02), np.float32(2.0), np.float32(4e-4)
+
+    plain = sph.Context(p, n)
+    plain.mlp_sync(net)
+    cur0 = sph.DeviceState.from_numpy(case.state, capacity=n)
+    out0 = sph.DeviceState.empty(n)
+    with pytest.raises(RuntimeError, match="SPH_F_SURROGATE"):
+        plain.nn_advance(net, cur0, out0, n, sc, dv, dr, dt4, 1.0)
+    del plain
+
+    ctx_e = sph.Context(p, n, sph.FEATURE_SURROGATE)
+    ctx_e.mlp_sync(net)
+    ctx_e.nn_advance(net, cur0, out0, n, sc, dv, dr, dt4, 1.0)
+    torch.cuda.synchronize()
+    ref = out0.to_numpy(n)
+    ref_status = ctx_e.status()
+
+    ctx_g = sph.Context(p, n, sph.FEATURE_SURROGATE)
+    ctx_g.mlp_sync(net)
+    cur = sph.DeviceState.from_numpy(case.state, capacity=n)
+    out = sph.DeviceState.empty(n)
+    torch.cuda.synchronize()
+    before = out.to_numpy(n)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        ctx_g.nn_advance(net, cur, out, n, sc, dv, dr, dt4, 1.0, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    _same_bits(out.to_numpy(n), before)  # capturing runs nothing
+    for _ in range(REPLAYS):
+        g.replay()
+        torch.cuda.synchronize()
+        _same_bits(out.to_numpy(n), ref)
+        assert ctx_g.status() == ref_status
+    del g

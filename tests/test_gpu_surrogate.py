@@ -342,7 +342,7 @@ def _advance_pair(case, net, dv=0.02, dr=2.0, dt4=2e-4, residual=False, inv_dt=0
     the same state; returns both states and the unfused outputs."""
     p, n = case.params, case.n
     sc = _scales(p, inv_dt)
-    ctx = sph.Context(p, n)
+    ctx = sph.Context(p, n, sph.FEATURE_SURROGATE)
     ctx.mlp_sync(net)
     cur = sph.DeviceState.from_numpy(case.state)
     U, F = sph.DeviceState.empty(n), sph.DeviceState.empty(n)
@@ -416,7 +416,7 @@ def test_fused_advance_c2_sampled_vs_oracle():
     announce(f"nn fused advance c2 n={n}")
     net, arr = _random_net(128, 64, 19, out_gain=50.0)
     sc = _scales(p)
-    ctx = sph.Context(p, n)
+    ctx = sph.Context(p, n, sph.FEATURE_SURROGATE)
     ctx.mlp_sync(net)
     cur = sph.DeviceState.from_numpy(case.state)
     F = sph.DeviceState.empty(n)

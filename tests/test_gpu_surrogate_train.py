@@ -26,7 +26,7 @@ def _tiny(seed):
 
 
 def _judged(net, cfg, case):
-    ctx = sph.Context(case.params, case.n)
+    ctx = sph.Context(case.params, case.n, sph.FEATURE_SURROGATE)
     ctx.mlp_sync(net)
     r = surrogate.run(case, 160, net, cfg, ctx=ctx)
     j = r["books"]["judge"]
