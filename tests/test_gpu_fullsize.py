@@ -185,12 +185,15 @@ def test_c3_sort_state_ranges_and_sampled_interaction(c3):
 
 
 def test_c4_cell_step_subblock_vs_oracle():
-    """The 38.5M-particle precision-variant workload: one cell + offset
-    interaction on the whole state, compared with the FP64 oracle on a cube of
-    64 lattice spacings (its particles, with a halo of 4h as neighbours)."""
-    case = cases.case_c4()
+    """The 38.5M-particle precision-variant workload in developed flow (fluid
+    v ~ U(-0.5, 0.5) m/s, rho x (1 +- 0.5 %), so continuity, artificial
+    viscosity and nu are live): one cell + offset interaction and one cell
+    step (Euler form) on the whole state, compared with the FP64 oracle on a
+    cube of 64 lattice spacings (its particles, with a halo of 4h as
+    neighbours; the oracle steps with the GPU's dt)."""
+    case = cases.perturb(cases.case_c4(), 6)
     p, n = case.params, case.n
-    announce(f"c4 cell interaction + oracle sub-block n={n}")
+    announce(f"c4 cell interaction + step, oracle sub-block n={n}")
     F = sph.FEATURE_CELL
     ctx = sph.Context(p, n, F)
     t64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
@@ -207,6 +210,7 @@ def test_c4_cell_step_subblock_vs_oracle():
     ids_sorted = cb.t["id"][:n].cpu().numpy()
     pos_by_id = np.empty((n, 3))
     pos_by_id[ids_sorted] = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+    del x, y, z
     dp = p["dp"]
     lo = np.array([60 * dp, 200 * dp, 60 * dp])
     inner, outer = cases.sub_block(case, lo, 64 * dp, 4.0 * p["h"])
@@ -227,6 +231,7 @@ def test_c4_cell_step_subblock_vs_oracle():
     where[ids_sorted] = np.arange(n)
     gi = where[ids]
     g = {k: v[:n].cpu().numpy()[gi] for k, v in rates.items()}
+    del rates
     t = srt["state"]["type"][sel]
     fl = t == cases.FLUID
     gv = np.array(p["g"])
@@ -234,7 +239,55 @@ def test_c4_cell_step_subblock_vs_oracle():
     a_gpu = np.stack([g["ax"], g["ay"], g["az"]], 1)[fl].astype(np.float64) - gv
     errs = {"a_minus_g": relnorm(a_gpu, a_ref), "drho": relnorm(g["arho"], acc["drho"]),
             "p": relnorm(g["press"], acc["p"]), "nu": relnorm(g["nu"], acc["nu"])}
-    print("c4 sub-block", len(sel), errs, int(g["npair"].sum()), int(acc["npair"].sum()), flush=True)
+    norms = {"drho_rms": float(np.sqrt(np.mean(acc["drho"] ** 2))),
+             "nu_rms": float(np.sqrt(np.mean(acc["nu"] ** 2)))}
+    print("c4 sub-block rates", len(sel), errs, norms, int(g["npair"].sum()),
+          int(acc["npair"].sum()), flush=True)
+    # developed flow: the continuity and viscosity terms are far from zero
+    # (kg/m^3/s and m/s respectively)
+    assert norms["drho_rms"] > 1.0 and norms["nu_rms"] > 1e-3
+    assert np.count_nonzero(acc["nu"]) > 0.9 * len(sel)
     for k, v in errs.items():
         assert v <= TOL, (k, v)
     assert abs(int(g["npair"].sum()) - int(acc["npair"].sum())) <= 1e-4 * acc["npair"].sum() + 2
+
+    # one full cell step (sort, interaction, dt, Euler update) of the whole state
+    ctx.cstep(ca, cb, n, 0)
+    torch.cuda.synchronize()
+    dt = float(np.float32(ctx.dt()))
+    x, y, z = ctx.cstate_positions(cb, n)
+    ids_new = cb.t["id"][:n].cpu().numpy()
+    where[ids_new] = np.arange(n)
+    gi = where[ids]
+    got = {"x": x.cpu().numpy()[gi], "y": y.cpu().numpy()[gi], "z": z.cpu().numpy()[gi]}
+    del x, y, z
+    for k in ("vx", "vy", "vz", "rho"):
+        got[k] = cb.t[k][:n].cpu().numpy()[gi].astype(np.float64)
+    ref = oracle.verlet(subp, srt["state"], int(srt["counts"][0]), 0, dt, acc_full(subp, srt, sel, acc))
+    s0 = srt["state"]
+    serr = {}
+    for k in ("x", "y", "z", "vx", "vy", "vz", "rho"):
+        inc_ref = ref[k][sel] - s0[k][sel]
+        inc_gpu = got[k] - s0[k][sel]
+        if k in ("x", "y", "z"):
+            bound = 2.0 * ulp32(p["h"]) + 1e-3 * np.abs(inc_ref)
+            assert np.all(np.abs(got[k] - ref[k][sel]) <= bound), k
+        excess = np.maximum(np.abs(inc_gpu - inc_ref) - ulp32(ref[k][sel]), 0.0)
+        serr[k] = float(np.linalg.norm(excess) / np.linalg.norm(inc_ref))
+        assert np.linalg.norm(inc_ref) > 0.0, k
+    print("c4 sub-block step", serr, "dt", dt, flush=True)
+    for k, v in serr.items():
+        assert v <= 1e-3, (k, v)
+    assert ctx.status() & (sph.STATUS_NONFINITE | sph.STATUS_DT) == 0
+
+
+def acc_full(p, srt, sel, acc):
+    """Rates of the selected sorted particles spread over the whole sorted
+    label-0 range (zeros elsewhere), as oracle.verlet takes them."""
+    n0 = int(srt["counts"][0])
+    out = {}
+    for k in ("ax", "ay", "az", "drho"):
+        a = np.zeros(n0)
+        a[sel] = acc[k]
+        out[k] = a
+    return out
