@@ -66,25 +66,58 @@ def _traffic(kernel_src, launches_key: str):
     return rec.get("bytes_per_launch")
 
 
+def _json_default(o):
+    """numpy scalars in the JSON lines."""
+    if hasattr(o, "item"):
+        return o.item()
+    raise TypeError(f"not JSON serialisable: {type(o).__name__}")
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(case, seconds: float) -> dict:
     """The FP64 oracle as it stands, full steps of the same workload from its
-    initial state, until about ``seconds`` of wall time have passed."""
+    initial state: about ``seconds`` of wall time on all host threads (the
+    reported value), then the first step again on one thread (at least one
+    step, about a third of ``seconds`` at most beyond it)."""
     import oracle
-    st = case.state
-    pairs = 0
-    steps = 0
-    t0 = time.perf_counter()
-    while steps < 3 or (time.perf_counter() - t0 < seconds and steps < 200):
-        r = oracle.step(case.params, st, steps)
-        st = r["state"]
-        pairs += r["pairs"]
-        steps += 1
-    el = time.perf_counter() - t0
-    return {"value": pairs / el, "unit": "pair interactions/s", "cores": oracle.threads(),
+
+    def timed(budget, min_steps):
+        st = case.state
+        pairs = steps = 0
+        t0 = time.perf_counter()
+        while steps < min_steps or (time.perf_counter() - t0 < budget and steps < 200):
+            r = oracle.step(case.params, st, steps)
+            st = r["state"]
+            pairs += r["pairs"]
+            steps += 1
+        return pairs, steps, time.perf_counter() - t0
+
+    all_threads = oracle.threads()
+    pairs, steps, el = timed(seconds, 3)
+    oracle.set_threads(1)
+    try:
+        p1, s1, e1 = timed(seconds / 3.0, 1)
+    finally:
+        oracle.set_threads(all_threads)
+    return {"value": pairs / el, "unit": "pair interactions/s", "cores": all_threads,
             "kind": "oracle",
             "sample": f"{steps} full FP64 oracle steps of the same workload from its initial "
-                      f"state ({pairs} pair interactions in {el:.2f} s; OpenMP over particles)",
-            "steps_per_s": steps / el}
+                      f"state ({pairs} pair interactions in {el:.2f} s; OpenMP over particles, "
+                      f"{all_threads} threads)",
+            "steps_per_s": steps / el, "cpu_model": _cpu_model(),
+            "host_cpus": os.cpu_count(),
+            "one_thread": {"value": p1 / e1, "steps": s1, "seconds": e1,
+                           "steps_per_s": s1 / e1}}
 
 
 def copy_probe(mib: int, reps: int) -> None:
@@ -300,6 +333,124 @@ def precision_report(args) -> dict:
     return out
 
 
+def slab_bench(args) -> dict:
+    """One GPU's sub-domain at its real shape: slab 1 of a 4-slab x
+    decomposition of the dam break at dp = 1.3 mm (8,000,525 fluid particles,
+    walls, ghost strips of width 2h on both x faces), in developed flow
+    (v ~ U(-0.5, 0.5) m/s, rho x (1 +- 0.5 %)). Before each step a migration
+    injector stands in for the neighbouring sub-domains (Sec. 4.2): 0.25 % of
+    the fluid per face (20,001 particles), drawn with PCG64(5 + step) from the
+    fluid of the layer next to the face, is moved across the face by U(0, dp);
+    after the step (sort with migration labels, interaction, update) the
+    outgoing ranges of the sort (Sec. 4.3) are wrapped back in through the
+    opposite face (x -/+ the slab width), so the particle count is exactly
+    conserved, which is asserted every step. Kernel time per step comes from
+    HIP events on the step's stream; the injector runs between steps and is
+    timed apart from them."""
+    import numpy as np
+    import torch
+
+    from paper_1210_1017_amd import cases, sph
+
+    t0 = time.perf_counter()
+    case = cases.perturb(cases.slab_c3(), 6)
+    p, n = case.params, case.n
+    cnt = case.counts()
+    print(f"[slab] {case.name}: {n} particles {cnt}, generated in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    xlo, xhi = p["slab_xlo"], p["slab_xhi"]
+    width, cs, dp = xhi - xlo, 2.0 * p["h"], p["dp"]
+    nmig = int(round(0.0025 * cnt["fluid"]))
+    ctx = sph.Context(p, n)
+    a = sph.DeviceState.from_numpy(case.state, capacity=n)
+    b = sph.DeviceState.empty(n)
+
+    def inject(st, step):
+        rng = np.random.Generator(np.random.PCG64(5 + step))
+        x, typ = st.t["x"][:n], st.t["type"][:n]
+        fl = typ == cases.FLUID
+        moved = 0
+        for lo, hi, sign in ((xlo, xlo + cs, -1.0), (xhi - cs, xhi, 1.0)):
+            idx = torch.nonzero(fl & (x >= lo) & (x < hi)).squeeze(1)
+            pick = rng.choice(idx.numel(), size=nmig, replace=False)
+            u = rng.uniform(0.0, dp, size=nmig)
+            face = xlo if sign < 0 else xhi
+            sel = idx[torch.from_numpy(pick).cuda()]
+            x[sel] = torch.from_numpy((face + sign * u).astype(np.float32)).cuda()
+            moved += nmig
+        return moved
+
+    def wrap(st, c):
+        x = st.t["x"]
+        (l0, l1), (r0, r1) = c["out_lo"], c["out_hi"]
+        if l1 > l0:
+            x[l0:l1] += width
+        if r1 > r0:
+            x[r0:r1] -= width
+        return (l1 - l0) + (r1 - r0)
+
+    books = {"migrated_out": 0, "wrapped": 0}
+
+    def run(k, s0):
+        tin = 0.0
+        for s in range(s0, s0 + k):
+            t1 = time.perf_counter()
+            books["migrated_out"] += inject(a_b[0], s)
+            torch.cuda.synchronize()
+            tin += time.perf_counter() - t1
+            ctx.step(a_b[0], a_b[1], n, s)
+            c = ctx.counts()  # synchronises
+            t1 = time.perf_counter()
+            if sum(c["n_label"]) != n or c["n_label"][3] != 0:
+                raise RuntimeError(f"step {s}: particle count not conserved: {c['n_label']}")
+            if c["n_label"][1] < nmig or c["n_label"][2] < nmig:
+                raise RuntimeError(f"step {s}: injected migrants missing: {c['n_label']}")
+            books["wrapped"] += wrap(a_b[1], c)
+            torch.cuda.synchronize()
+            tin += time.perf_counter() - t1
+            a_b.reverse()
+        return tin
+
+    a_b = [a, b]
+    run(args.warmup, 0)
+    pairs0, cand0 = ctx.pair_total(), ctx.candidate_total()
+    ctx.timing_begin(args.steps)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    t_inj = run(args.steps, args.warmup)
+    t_wall = time.perf_counter() - t_wall
+    ph = ctx.timing_read(args.steps)
+    ctx.timing_begin(0)
+    pairs = ctx.pair_total() - pairs0
+    cand = ctx.candidate_total() - cand0
+    c = ctx.counts()
+    status = ctx.status()
+    kern_ms = float(ph.sum(axis=1).mean())
+    t_int = float(ph[:, 1].mean()) * 1e-3
+    pairs_per_launch = pairs / args.steps
+    flop = FLOP_PER_PAIR * pairs_per_launch + FLOP_PER_CANDIDATE * cand / args.steps
+    achieved = flop / t_int / 1e12
+    out = {"workload": case.name, "particles": n, "fluid": cnt["fluid"],
+           "boundary": cnt["boundary"], "ghost": cnt["ghost"], "steps": args.steps,
+           "warmup": args.warmup, "migrants_per_face_per_step": nmig,
+           "ms_per_step_kernels": kern_ms, "steps_per_s_kernels": 1e3 / kern_ms,
+           "pair_interactions_per_s_kernels": pairs / (ph.sum() * 1e-3),
+           "phase_ms": {"sort": float(ph[:, 0].mean()), "interact": float(ph[:, 1].mean()),
+                        "dt_update": float(ph[:, 2].mean())},
+           "wall_ms_per_step_with_injector": t_wall / args.steps * 1e3,
+           "injector_ms_per_step": t_inj / args.steps * 1e3,
+           "interact": {"bound": "alu", "achieved_tflops": achieved,
+                        "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                        "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                        "pairs_per_launch": pairs_per_launch,
+                        "candidates_per_launch": cand / args.steps,
+                        "hbm_gbs_algorithmic":
+                            BYTES_PER_PARTICLE_INTERACT * c["n_label"][0] / t_int / 1e9},
+           "last_counts": c, "migrated_out": books["migrated_out"], "wrapped": books["wrapped"],
+           "dt_last": float(ctx.dt()), "status": int(status)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +463,9 @@ def main() -> int:
     ap.add_argument("--precision-report", action="store_true",
                     help="run the precision-variant report (cell + offset and FP64 paths) and exit")
     ap.add_argument("--report-case", default="c4", choices=["c4", "c2"])
+    ap.add_argument("--slab", action="store_true",
+                    help="time one GPU's slab of a 4-slab decomposition (8.8M particles) with "
+                         "the per-step migration injector, print its JSON line and exit")
     ap.add_argument("--report-steps", type=int, default=10000)
     ap.add_argument("--fp64-steps", type=int, default=10000)
     ap.add_argument("--variant-steps", type=int, default=200,
@@ -329,6 +483,9 @@ def main() -> int:
         return 0
     if args.copy_probe:
         copy_probe(args.copy_probe, 5)
+        return 0
+    if args.slab:
+        print(json.dumps(slab_bench(args), default=_json_default), flush=True)
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU "

@@ -124,6 +124,13 @@ def threads() -> int:
     return int(lib().orc_threads())
 
 
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops from now on (timing only)."""
+    L = lib()
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads(int(n))
+
+
 def to_f64(state: dict) -> dict:
     """Exact upcast of an FP32 state to the oracle's FP64 state."""
     out = {k: np.ascontiguousarray(state[k], dtype=np.float64) for k in F32_FIELDS}

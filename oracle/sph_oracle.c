@@ -58,6 +58,17 @@ int orc_threads(void)
 #endif
 }
 
+/* Threads of the following parallel loops (for timing the oracle at one
+ * thread and at all host cores; no effect on any result). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- keys (a1) */
 
 /* Bits of a linear cell index: smallest b with 2^b >= number of cells. */
