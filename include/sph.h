@@ -198,6 +198,21 @@ int sph_cell_bits(const sph_ctx *ctx);
 int sph_sort_kv(sph_ctx *ctx, const uint32_t *keys, const int32_t *vals, uint32_t *keys_out,
                 int32_t *vals_out, uint32_t n, int key_bits, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * stable sort as sph_sort_kv, bit-identical results, without a context. Its
+ * scratch (one key/value ping-pong pair and the radix histograms, about
+ * 17 MB) is a fixed device array of the library, which every GPU it runs on
+ * holds until the process ends; the call allocates nothing. n is at most
+ * SPH_SORT_NOALLOC_MAX: larger n fails with SPH_E_CAPACITY. Every call on one
+ * GPU uses that GPU's single array, so calls that overlap on one GPU (on
+ * different streams or host threads) race and must be serialised by the
+ * caller. Runs on the current HIP device; errors are reported through
+ * sph_last_error(NULL). n = 0 does nothing. */
+#define SPH_SORT_NOALLOC_MAX (1u << 21)
+int sph_sort_kv_noalloc(const uint32_t *keys, const int32_t *vals, uint32_t *keys_out,
+                        int32_t *vals_out, uint32_t n, int key_bits, void *stream);
+
 /* Sort step (Sec. 3.1, 4.2-4.3): cell key + migration label per particle,
  * stable radix sort, reorder of every SoA array of `in` into `out`, cell
  * begin/end tables over the label-0 prefix (an empty cell c has

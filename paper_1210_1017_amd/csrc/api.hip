@@ -75,6 +75,16 @@ void free_all(sph_ctx *c) {
 
 }  // namespace
 
+int sph::set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_create_err = buf;
+    return code;
+}
+
 extern "C" {
 
 int sph_abi_version(void) { return SPH_ABI_VERSION; }

@@ -266,6 +266,36 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
     return hipSuccess;
 }
 
+// The same passes with explicit buffers: one scratch pair (ks, vs) and the
+// output. The last pass writes the output; the passes before it alternate
+// between the scratch pair and the output so that no pass writes onto its own
+// source (the input is only read).
+hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
+                           int32_t *vals_out, uint32_t n, int key_bits, uint32_t *ks,
+                           int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int passes = (key_bits + 7) / 8;
+    const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
+    const uint32_t *ksrc = keys_in;
+    const int32_t *vsrc = vals_in;
+    for (int p = 0; p < passes; p++) {
+        const bool to_out = ((passes - 1 - p) & 1) == 0;
+        uint32_t *kdst = to_out ? keys_out : ks;
+        int32_t *vdst = to_out ? vals_out : vs;
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, n, shift,
+                           ntiles, hist);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, hist, ntiles, tot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, vsrc,
+                           kdst, vdst, n, shift, ntiles, hist, tot);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        ksrc = kdst;
+        vsrc = vdst;
+    }
+    return hipSuccess;
+}
+
 // ---------------------------------------------------- counts and ranges
 // Cell tables over the label-0 prefix of the sorted keys (Sec. 3.1 first
 // index of each cell; Sec. 4.4 first and last of a region) and label counts.

@@ -106,6 +106,9 @@ hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_
 hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_in,
                       uint32_t *keys_out, int32_t *vals_out, uint32_t n, int key_bits,
                       hipStream_t s, bool first_hist_done = false);
+hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
+                           int32_t *vals_out, uint32_t n, int key_bits, uint32_t *ks,
+                           int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s);
 hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s, bool counts = true);
 hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
                          hipStream_t s);
@@ -146,6 +149,9 @@ hipError_t launch_update_d(sph_ctx *c, const sph_dstate &st, const sph_drates &r
                            uint64_t step, hipStream_t s);
 hipError_t launch_totals_d(sph_ctx *c, const sph_dstate &st, uint32_t n, double *out_host,
                            hipStream_t s);
+
+// api.hip: record a message for sph_last_error(NULL) and return code
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
 // mlp.hip (learned surrogate)
 constexpr int kMlpSplits = 32;  // split-K slices of a weight-gradient GEMM, at most

@@ -121,6 +121,7 @@ def lib() -> C.CDLL:
         L.sph_destroy.restype = None
         L.sph_cell_bits.argtypes = [vp]
         L.sph_sort_kv.argtypes = [vp, vp, vp, vp, vp, u32, i32, vp]
+        L.sph_sort_kv_noalloc.argtypes = [vp, vp, vp, vp, u32, i32, vp]
         L.sph_sort.argtypes = [vp, P(SoA), P(SoA), u32, vp]
         L.sph_interact.argtypes = [vp, P(SoA), u32, P(Rates), vp]
         L.sph_update.argtypes = [vp, P(SoA), P(Rates), u32, u64, vp]
@@ -180,6 +181,16 @@ def probe_fma(out, blocks: int, iters: int, stream=None):
     if out.dtype.itemsize != 4 or out.numel() < blocks * 256 or not out.is_cuda:
         raise ValueError("out must be a float32 device tensor of blocks * 256 elements")
     _probe_check(lib().sph_probe_fma(_addr(out), blocks, iters, _stream_ptr(stream)))
+
+
+SORT_NOALLOC_MAX = 1 << 21
+
+
+def sort_kv_noalloc(keys, vals, keys_out, vals_out, n: int, key_bits: int, stream=None):
+    """sph_sort_kv_noalloc: the stable key-value sort without a context and
+    without allocation (scratch in a fixed device array; n <= SORT_NOALLOC_MAX)."""
+    _probe_check(lib().sph_sort_kv_noalloc(_addr(keys), _addr(vals), _addr(keys_out),
+                                           _addr(vals_out), n, key_bits, _stream_ptr(stream)))
 
 
 def probe_copy(src, dst, blocks: int, stream=None):
