@@ -15,11 +15,11 @@ namespace sph {
 #ifndef SPH_ENT_SLACK
 #define SPH_ENT_SLACK 3
 #endif
-#ifndef SPH_TEST_PIPE
-#define SPH_TEST_PIPE 0
+#ifndef SPH_STAGE
+#define SPH_STAGE 768
 #endif
 #ifndef SPH_INTERACT_WAVES_PER_EU
-#define SPH_INTERACT_WAVES_PER_EU 4
+#define SPH_INTERACT_WAVES_PER_EU 3
 #endif
 // Hit-mask entries per lane: a lane's list holds up to kEnt - 1 entries and
 // one sentinel slot.
@@ -30,6 +30,7 @@ constexpr int kEnt = SPH_INTERACT_ENT;
 // candidates).
 constexpr int kEntSlack = SPH_ENT_SLACK;
 constexpr int kUnroll = SPH_TEST_UNROLL;  // candidates loaded together in the support test
+constexpr int kStage = SPH_STAGE;  // candidate positions a block stages in LDS per column offset
 static_assert(32 % kUnroll == 0, "a hit mask covers whole groups of candidates");
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9 buffer resource: 32-bit raw dwords
 
@@ -69,13 +70,18 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
     DevInfo *__restrict__ info, float *__restrict__ oax, float *__restrict__ oay,
     float *__restrict__ oaz, float *__restrict__ orho, float *__restrict__ opress,
     float *__restrict__ onu, uint32_t *__restrict__ onpair) {
+    constexpr int kWaves = kInteractThreads / 64;
     // entry = (byte offset 16 j of the first candidate of the mask, hit mask
     // with the first candidate in bit 31); [slot][lane]: a wave's 64 lanes
     // touch 512 consecutive bytes
     __shared__ uint2 s_ent[kEnt][kInteractThreads];
-    __shared__ float s_rdt[kInteractThreads / 64];
-    __shared__ uint32_t s_rnp[kInteractThreads / 64];
-    __shared__ uint32_t s_rnc[kInteractThreads / 64];
+    // positions of the block's candidates of one column offset (the index
+    // range spanned by the 256 lanes' runs), padded for a group past the end
+    __shared__ float4 s_stage[kStage + kUnroll];
+    __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+    __shared__ float s_rdt[kWaves];
+    __shared__ uint32_t s_rnp[kWaves];
+    __shared__ uint32_t s_rnc[kWaves];
 
     const int tid = threadIdx.x;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -83,197 +89,230 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
     const uint32_t i = blk * kInteractThreads + tid;
     const bool inrange = i < n0;
     const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;
+    const bool act = ti != kGhost;  // this lane searches (in range and not a ghost)
     float dtmin = INFINITY;
     uint32_t npair = 0, ncand = 0;
 
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), vi = pi;
     if (inrange) {
-        const float4 pi = pos4[i], vi = vel4[i];
-        const float rhoi = vi.w, Pi = pi.w;
-        const float si = rhoi * kp.inv_rho0;
-        const float si3 = si * si * si;
-        const float ci = kp.c0 * si3;
-        float axs = 0.f, ays = 0.f, azs = 0.f, drho = 0.f, nu = 0.f;
-        if (ti != kGhost) {
-            const __amdgpu_buffer_rsrc_t rp =
-                __builtin_amdgcn_make_buffer_rsrc((void *)pos4, 0, (int)(n * 16u), kRsrcWord3);
-            const __amdgpu_buffer_rsrc_t rv =
-                __builtin_amdgcn_make_buffer_rsrc((void *)vel4, 0, (int)(n * 16u), kRsrcWord3);
-            const uint32_t cell = sk[i] & kp.cell_mask;
-            const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
-            const int cz = (int)(cell % ncz);
-            const int cy = (int)((cell / ncz) % ncy);
-            const int cx = (int)(cell / (ncz * ncy));
-            const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
-            const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
-            const float hinv2 = -0.5f * kp.inv_h;
-            const float eta2 = kp.eta2, h = kp.h;
-            const float kvis = -kp.alpha * kp.h * kp.c0;  // Pi_ij = kvis (s_i^3 + s_j^3) vr R
+        pi = pos4[i];
+        vi = vel4[i];
+    }
+    const float rhoi = vi.w, Pi = pi.w;
+    const float si = rhoi * kp.inv_rho0;
+    const float si3 = si * si * si;
+    const float ci = kp.c0 * si3;
+    float axs = 0.f, ays = 0.f, azs = 0.f, drho = 0.f, nu = 0.f;
+    const __amdgpu_buffer_rsrc_t rp =
+        __builtin_amdgcn_make_buffer_rsrc((void *)pos4, 0, (int)(n * 16u), kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rv =
+        __builtin_amdgcn_make_buffer_rsrc((void *)vel4, 0, (int)(n * 16u), kRsrcWord3);
+    const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
+    int cx = 0, cy = 0, cz = 0;
+    if (act) {
+        const uint32_t cell = sk[i] & kp.cell_mask;
+        cz = (int)(cell % ncz);
+        cy = (int)((cell / ncz) % ncy);
+        cx = (int)(cell / (ncz * ncy));
+    }
+    const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
+    const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
+    const float hinv2 = -0.5f * kp.inv_h;
+    const float eta2 = kp.eta2, h = kp.h;
+    const float kvis = -kp.alpha * kp.h * kp.c0;  // Pi_ij = kvis (s_i^3 + s_j^3) vr R
 
-            auto pair = [&](const v4f pj, const v4f vj) {
-                const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                float F;  // grad W / (kgrad r_ij)
-                if (kCubic) {
-                    const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h;
-                    const float t = 2.0f - q;
-                    // both sides first, then the choice: the compiler keeps it a
-                    // select (a conditional expression here became a branch)
-                    const float outer = t * t * __builtin_amdgcn_rcpf(q);
-                    const float inner = fmaf(-3.0f, q, 4.0f);
-                    F = q < 1.0f ? inner : outer;
-                } else {
-                    const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
-                    F = t * t * t;
-                }
-                const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
-                const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
-                drho = fmaf(F, vr, drho);
-                // one reciprocal for mu = h vr / (r^2 + eta^2) and for the
-                // viscous term -alpha cbar mu / rhobar; h (in nu) and kvis
-                // (in the force factor) are applied outside the product
-                const float rs = rhoi + vj.w;
-                const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
-                const float vR = vr * R;
-                nu = fmaxf(nu, fabsf(rs * vR));  // |mu| / h
-                const float sj = vj.w * kp.inv_rho0;
-                const float visc = vr < 0.0f ? fmaf(sj * sj, sj, si3) * vR : 0.0f;  // Pi / kvis
-                const float f = fmaf(kvis, visc, Pi + pj.w) * F;
-                axs = fmaf(f, dx, axs);
-                ays = fmaf(f, dy, ays);
-                azs = fmaf(f, dz, azs);
-            };
-
-            // compute phase over the cnt entries of the lane's list holding
-            // nhit set bits. The sentinel (16 i, bit 31) after the last entry
-            // stands in for every position past the end, so a group of four
-            // never needs a mask. The next group's indices are drawn from the
-            // masks while the current group's neighbour data is in flight.
-            auto flush = [&](uint32_t cnt, uint32_t nhit) {
-                s_ent[cnt][tid] = make_uint2(i * 16u, 0x80000000u);
-                uint32_t pk = 0, cb = 0, cj = 0;
-                uint2 nx = s_ent[0][tid];
-                auto draw = [&](uint32_t (&jj)[4]) {
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const bool empty = cb == 0u;  // take the prefetched entry
-                        cb = empty ? nx.y : cb;
-                        cj = empty ? nx.x : cj;
-                        pk = min(pk + (empty ? 1u : 0u), cnt);
-                        nx = s_ent[pk][tid];
-                        const uint32_t off = (uint32_t)__builtin_clz(cb);
-                        jj[u] = cj + (off << 4);  // byte offset of j
-                        cb &= 0x7fffffffu >> off;
-                    }
-                };
-                uint32_t jn[4];
-                draw(jn);
-                for (uint32_t t = 0; t < nhit; t += 4) {
-                    v4f qp[4], qv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        qp[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, jn[u], 0, 0);
-                        qv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, jn[u], 0, 0);
-                    }
-                    draw(jn);
-#pragma unroll
-                    for (int u = 0; u < 4; u++) pair(qp[u], qv[u]);
-                }
-            };
-
-            // The list keeps i itself (found in its own run): the self pair has
-            // r_ij = v_ij = 0 and adds exactly zero to every sum and to nu, so
-            // it costs one bit instead of a j != i test per candidate.
-            uint32_t lp = 0;    // entries in the lane's list
-            uint32_t nhit = 0;  // set bits in them
-            uint32_t listed = 0;
-            auto put = [&](uint32_t j16, uint32_t b) {
-                s_ent[lp][tid] = make_uint2(j16, b);
-                lp += b != 0u ? 1u : 0u;
-                nhit += (uint32_t)__builtin_popcount(b);
-                if (lp >= (uint32_t)(kEnt - 1)) {  // full: this lane alone
-                    flush(lp, nhit);
-                    listed += nhit;
-                    lp = 0;
-                    nhit = 0;
-                }
-            };
-            for (int col = 0; col < 9; col++) {
-                if (__any(lp > (uint32_t)(kEnt - 1 - kEntSlack))) {
-                    flush(lp, nhit);
-                    listed += nhit;
-                    lp = 0;
-                    nhit = 0;
-                }
-                const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
-                uint32_t jb = 0, je = 0;
-                if (X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
-                    const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
-                    jb = cbeg[c0 + zlo];
-                    je = cend[c0 + zhi];
-                }
-                const uint32_t len = je - jb;
-                ncand += len;
-                const uint32_t voff = jb * 16u;
-                uint32_t bits = 0;
-                uint32_t k0 = 0;
-                // k0 is the same for every lane still in its run (the group
-                // counter of the wave): the loads take it as a scalar offset
-                auto load = [&](v3f (&q)[kUnroll], uint32_t k) {
-#pragma unroll
-                    for (int u = 0; u < kUnroll; u++)  // past the run: in-bounds data or 0
-                        q[u] = __builtin_bit_cast(
-                            v3f, __builtin_amdgcn_raw_buffer_load_b96(rp, voff, (int)(k * 16u + 16u * u), 0));
-                };
-                auto test = [&](const v3f (&q)[kUnroll], uint32_t k) {
-#pragma unroll
-                    for (int u = 0; u < kUnroll; u++) {
-                        const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
-                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        // bits = bits << 1 | (r2 < 4h^2): the sign of the
-                        // difference of two floats decides the comparison exactly
-                        bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(r2 - kp.r2max), 31);
-                    }
-                    if ((k & 31u) == 32u - kUnroll) {  // 32 candidates tested
-                        const uint32_t c0 = k + kUnroll - 32u;
-                        const uint32_t v = len - c0;  // of which inside the run
-                        put(voff + c0 * 16u, v >= 32u ? bits : bits & ~(0xffffffffu >> v));
-                        bits = 0;
-                    }
-                };
-#if SPH_TEST_PIPE
-                // two groups in flight: the next group's loads are issued
-                // before the current group is tested
-                v3f qa[kUnroll], qb[kUnroll];
-                if (len) load(qa, 0);
-                for (; k0 < len; k0 += 2 * kUnroll) {
-                    if (k0 + kUnroll < len) load(qb, k0 + kUnroll);
-                    test(qa, k0);
-                    if (k0 + kUnroll >= len) {
-                        k0 += kUnroll;
-                        break;
-                    }
-                    if (k0 + 2 * kUnroll < len) load(qa, k0 + 2 * kUnroll);
-                    test(qb, k0 + kUnroll);
-                }
-#else
-                for (; k0 < len; k0 += kUnroll) {
-                    v3f q[kUnroll];
-                    load(q, k0);
-                    test(q, k0);
-                }
-#endif
-                const uint32_t tail = k0 & 31u;  // candidates tested since the last mask
-                if (tail) {
-                    const uint32_t c0 = k0 - tail;
-                    const uint32_t v = len - c0;  // 1 .. tail
-                    put(voff + c0 * 16u, (bits << (32u - tail)) & ~(0xffffffffu >> v));
-                }
-            }
-            flush(lp, nhit);
-            npair = listed + nhit - 1u;  // minus the self entry
-            nu *= h;
+    auto pair = [&](const v4f pj, const v4f vj) {
+        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        float F;  // grad W / (kgrad r_ij)
+        if (kCubic) {
+            const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h;
+            const float t = 2.0f - q;
+            // both sides first, then the choice: the compiler keeps it a
+            // select (a conditional expression here became a branch)
+            const float outer = t * t * __builtin_amdgcn_rcpf(q);
+            const float inner = fmaf(-3.0f, q, 4.0f);
+            F = q < 1.0f ? inner : outer;
+        } else {
+            const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
+            F = t * t * t;
         }
-        const float m = kp.mass, mk = kp.mass * (kCubic ? kp.kgrad_cubic : kp.kgrad);
+        const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+        const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
+        drho = fmaf(F, vr, drho);
+        // one reciprocal for mu = h vr / (r^2 + eta^2) and for the
+        // viscous term -alpha cbar mu / rhobar; h (in nu) and kvis
+        // (in the force factor) are applied outside the product
+        const float rs = rhoi + vj.w;
+        const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
+        const float vR = vr * R;
+        nu = fmaxf(nu, fabsf(rs * vR));  // |mu| / h
+        const float sj = vj.w * kp.inv_rho0;
+        const float visc = vr < 0.0f ? fmaf(sj * sj, sj, si3) * vR : 0.0f;  // Pi / kvis
+        const float f = fmaf(kvis, visc, Pi + pj.w) * F;
+        axs = fmaf(f, dx, axs);
+        ays = fmaf(f, dy, ays);
+        azs = fmaf(f, dz, azs);
+    };
+
+    // compute phase over the cnt entries of the lane's list holding
+    // nhit set bits. The sentinel (16 i, bit 31) after the last entry
+    // stands in for every position past the end, so a group of four
+    // never needs a mask. The next group's indices are drawn from the
+    // masks while the current group's neighbour data is in flight.
+    auto flush = [&](uint32_t cnt, uint32_t nhit) {
+        s_ent[cnt][tid] = make_uint2(i * 16u, 0x80000000u);
+        uint32_t pk = 0, cb = 0, cj = 0;
+        uint2 nx = s_ent[0][tid];
+        auto draw = [&](uint32_t (&jj)[4]) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const bool empty = cb == 0u;  // take the prefetched entry
+                cb = empty ? nx.y : cb;
+                cj = empty ? nx.x : cj;
+                pk = min(pk + (empty ? 1u : 0u), cnt);
+                nx = s_ent[pk][tid];
+                const uint32_t off = (uint32_t)__builtin_clz(cb);
+                jj[u] = cj + (off << 4);  // byte offset of j
+                cb &= 0x7fffffffu >> off;
+            }
+        };
+        uint32_t jn[4];
+        draw(jn);
+        for (uint32_t t = 0; t < nhit; t += 4) {
+            v4f qp[4], qv[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                qp[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, jn[u], 0, 0);
+                qv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, jn[u], 0, 0);
+            }
+            draw(jn);
+#pragma unroll
+            for (int u = 0; u < 4; u++) pair(qp[u], qv[u]);
+        }
+    };
+
+    // The list keeps i itself (found in its own run): the self pair has
+    // r_ij = v_ij = 0 and adds exactly zero to every sum and to nu, so
+    // it costs one bit instead of a j != i test per candidate.
+    uint32_t lp = 0;    // entries in the lane's list
+    uint32_t nhit = 0;  // set bits in them
+    uint32_t listed = 0;
+    auto put = [&](uint32_t j16, uint32_t b) {
+        s_ent[lp][tid] = make_uint2(j16, b);
+        lp += b != 0u ? 1u : 0u;
+        nhit += (uint32_t)__builtin_popcount(b);
+        if (lp >= (uint32_t)(kEnt - 1)) {  // full: this lane alone
+            flush(lp, nhit);
+            listed += nhit;
+            lp = 0;
+            nhit = 0;
+        }
+    };
+    // every lane of the block runs the column loop (it holds barriers);
+    // lanes that do not search have empty runs
+    for (int col = 0; col < 9; col++) {
+        if (__any(act && lp > (uint32_t)(kEnt - 1 - kEntSlack))) {
+            if (act) {
+                flush(lp, nhit);
+                listed += nhit;
+                lp = 0;
+                nhit = 0;
+            }
+        }
+        const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
+        uint32_t jb = 0, je = 0;
+        if (act && X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
+            const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
+            jb = cbeg[c0 + zlo];
+            je = cend[c0 + zhi];
+        }
+        const uint32_t len = je - jb;
+        ncand += len;
+        // index range [lo, hi) of the block's runs of this column offset:
+        // consecutive particles lie in one (x, y) column or in neighbouring
+        // ones, whose neighbour columns are neighbours in the x-major order
+        // too, so the range is compact except where the block crosses an
+        // x-layer of cells
+        uint32_t lo = len ? jb : 0xffffffffu, hi = len ? je : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        }
+        if ((tid & 63) == 0) {
+            s_lo[tid >> 6] = lo;
+            s_hi[tid >> 6] = hi;
+        }
+        __syncthreads();  // also: every wave is done with the previous staging
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
+        const bool staged = hi > lo && hi - lo <= (uint32_t)kStage;  // the same in every lane
+        if (staged) {
+            for (uint32_t t = tid; t < hi - lo; t += kInteractThreads) s_stage[t] = pos4[lo + t];
+        }
+        __syncthreads();
+        if (!len) continue;
+        const uint32_t voff = jb * 16u;
+        uint32_t bits = 0;
+        uint32_t k0 = 0;
+        auto test = [&](const v3f (&q)[kUnroll], uint32_t k) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++) {
+                const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                // bits = bits << 1 | (r2 < 4h^2): the sign of the
+                // difference of two floats decides the comparison exactly
+                bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(r2 - kp.r2max), 31);
+            }
+            if ((k & 31u) == 32u - kUnroll) {  // 32 candidates tested
+                const uint32_t c0 = k + kUnroll - 32u;
+                const uint32_t v = len - c0;  // of which inside the run
+                put(voff + c0 * 16u, v >= 32u ? bits : bits & ~(0xffffffffu >> v));
+                bits = 0;
+            }
+        };
+        // k0 is the same for every lane still in its run (the group counter
+        // of the wave). Candidates past the run give garbage that the mask
+        // of valid candidates drops.
+        if (staged) {
+            const float4 *sp = s_stage + (jb - lo);
+            for (; k0 < len; k0 += kUnroll) {
+                v3f q[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    const float4 t = sp[k0 + u];
+                    q[u] = v3f{t.x, t.y, t.z};
+                }
+                test(q, k0);
+            }
+        } else {  // range too wide to stage (a block across an x-layer): bounds-checked loads
+            for (; k0 < len; k0 += kUnroll) {
+                v3f q[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++)  // past the run: in-bounds data or 0
+                    q[u] = __builtin_bit_cast(
+                        v3f, __builtin_amdgcn_raw_buffer_load_b96(rp, voff, (int)(k0 * 16u + 16u * u), 0));
+                test(q, k0);
+            }
+        }
+        const uint32_t tail = k0 & 31u;  // candidates tested since the last mask
+        if (tail) {
+            const uint32_t c0 = k0 - tail;
+            const uint32_t v = len - c0;  // 1 .. tail
+            put(voff + c0 * 16u, (bits << (32u - tail)) & ~(0xffffffffu >> v));
+        }
+    }
+    if (act) {
+        flush(lp, nhit);
+        npair = listed + nhit - 1u;  // minus the self entry
+        nu *= h;
+    }
+    if (inrange) {
+        const float mk = kp.mass * (kCubic ? kp.kgrad_cubic : kp.kgrad);
         float ax = 0.f, ay = 0.f, az = 0.f, ar = 0.f;
         if (ti == kFluid) {
             ax = fmaf(-mk, axs, kp.gx);
@@ -289,7 +328,6 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
                 if (a2 > 0.0f) dtmin = fminf(dtmin, sqrtf(kp.h / sqrtf(a2)));
             }
         }
-        (void)m;
         oax[i] = ax;
         oay[i] = ay;
         oaz[i] = az;
@@ -315,7 +353,7 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
     if (tid == 0) {
         float d = s_rdt[0];
         uint32_t np = s_rnp[0], nc = s_rnc[0];
-        for (int k = 1; k < kInteractThreads / 64; k++) {
+        for (int k = 1; k < kWaves; k++) {
             d = fminf(d, s_rdt[k]);
             np += s_rnp[k];
             nc += s_rnc[k];
