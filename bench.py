@@ -570,8 +570,18 @@ def main() -> int:
         rep = surrogate.report(steps=args.surrogate_steps, weights=wpath,
                                log=lambda *m: print(*m, file=sys.stderr, flush=True))
         judged = [j["max_rel_rho"] for j in rep["judge"]]
+        ser = rep["vs_plain_trajectory"]
         out["surrogate"] = {
-            "workload": rep["workload"], "steps": rep["steps"], "speedup": rep["speedup"],
+            "workload": rep["workload"], "steps": rep["steps"],
+            # steps/s ratio over the whole run; the run falls back to plain SPH
+            # once a judged window exceeds 1 %, so this is not a figure at 1 %
+            "speedup": rep["speedup"],
+            # accumulated error against the plain trajectory from the same start
+            "steps_within_1pct_of_plain_trajectory": ser["steps_within_tol"],
+            "speedup_within_1pct_of_plain_trajectory":
+                rep["speedup_within_tol_of_plain_trajectory"],
+            "max_rel_rho_vs_plain_trajectory": [
+                (q["step"], q["max_rel_rho"]) for q in ser["series"]],
             "steps_per_s": rep["surrogate_steps_per_s"],
             "plain_steps_per_s": rep["plain_steps_per_s"],
             "judge_max_rel_rho": max(judged) if judged else None,

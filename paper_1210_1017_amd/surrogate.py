@@ -244,7 +244,7 @@ def train(n_traj: int = 200, steps_per_traj: int = 2000, window_every: int = 16,
 # ------------------------------------------------------------------ running
 
 def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig | None = None,
-        ctx: sph.Context | None = None, judge: bool = True, log=None) -> dict:
+        ctx: sph.Context | None = None, judge: bool = True, log=None, snap=None) -> dict:
     """Advance ``case`` by ``steps`` time steps. With ``net`` (and its cfg),
     k = 4 steps per surrogate advance. The first advance and then one after
     every cfg.judge_every unjudged ones are judged: the same 4 steps also run
@@ -254,6 +254,8 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
     above cfg.judge_tol, a non-finite value or a density outside cfg.rho_band
     switches to plain SPH for the rest of the run. With cfg.keep_judged the
     loop continues from the judge's plain result. Without a net: plain SPH.
+    ``snap`` (optional, for error series; it synchronises): a callable
+    snap(step, state) called before every step or advance and at the end.
     Returns the final device state, wall time and books."""
     import torch
     n, p = case.n, case.params
@@ -269,9 +271,13 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
     if net is None:
         a = cur
         for q in range(steps):
+            if snap:
+                snap(q, a)
             b = bufs[q % 2]
             ctx.step(a, b, n, q)
             a = b
+        if snap:
+            snap(steps, a)
         torch.cuda.synchronize()
         books["plain_steps"] = steps
         return {"state": a, "seconds": time.perf_counter() - t0, "books": books, "ctx": ctx}
@@ -287,6 +293,8 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
         return _others(bufs, *used)
 
     while step < steps:
+        if snap:
+            snap(step, cur)
         if fallback or dt is None or steps - step < K_STEPS:
             nxt = others(cur)[0]
             ctx.step(cur, nxt, n, step)
@@ -336,6 +344,8 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
         else:
             books["advances"] += 1
         cur, step = S, step + K_STEPS
+    if snap:
+        snap(step, cur)
     torch.cuda.synchronize()
     return {"state": cur, "seconds": time.perf_counter() - t0, "books": books, "ctx": ctx}
 
@@ -360,11 +370,58 @@ def default_weights() -> str:
     return os.path.join(WEIGHTS_DIR, "surrogate_w128.npz")
 
 
+def error_series(case, steps, net, cfg, ctx, base, every: int = 50, tol: float = 0.01) -> dict:
+    """Accumulated error of the surrogate loop against the plain SPH
+    trajectory from the same initial state (not only inside judged
+    windows): the surrogate state is saved at the first step at or after
+    every multiple of ``every``, plain SPH is run to exactly those steps, and
+    the two are compared by particle id (max relative density error over the
+    fluid, and the density, velocity and position changes relative to plain
+    SPH's since the start). steps_within_tol: the last saved step before the
+    max relative density error first exceeds ``tol`` (``steps`` if never)."""
+    import torch
+    saved = {}
+    mark = [0]
+
+    def snap_sur(step, st):
+        if step >= mark[0]:
+            saved[step] = {k: v.clone() for k, v in st.t.items()}
+            mark[0] = (step // every + 1) * every
+
+    run(case, steps, net, cfg, ctx=ctx, snap=snap_sur)
+    want = set(saved)
+    ref = {}
+
+    def snap_plain(step, st):
+        if step in want:
+            ref[step] = {k: v.clone() for k, v in st.t.items()}
+
+    run(case, steps, None, ctx=ctx, snap=snap_plain)
+    out = []
+    within = steps
+    for step in sorted(saved):
+        if step == 0 or step not in ref:
+            continue
+        m = compare_by_id(ctx, sph.DeviceState(saved[step]), sph.DeviceState(ref[step]), base,
+                          case.n)
+        m["step"] = step
+        out.append(m)
+        if m["max_rel_rho"] > tol and within == steps:
+            prev = [q["step"] for q in out[:-1]]
+            within = prev[-1] if prev else 0
+    del saved, ref
+    torch.cuda.synchronize()
+    return {"every": every, "tol": tol, "steps_within_tol": within, "series": out}
+
+
 def report(steps: int = 1000, weights: str | None = None, judge_every: int | None = None,
-           obstacle_seed: int = 9, log=print) -> dict:
+           obstacle_seed: int = 9, log=print, series_every: int = 50) -> dict:
     """Surrogate against plain FP32 SPH on the 1.47M-particle obstacle dam
     break with a layout that training never saw: steps/s of both loops, and
     the surrogate state after ``steps`` steps against the plain state by id;
+    the accumulated error against the plain trajectory along the run
+    (error_series) and the steps/s ratio over the steps that stay within 1 %
+    of it;
     the same for persistence (a network that predicts no change) and, for a
     residual network, for the rows' pair-sum rates alone (a network that
     predicts no residual), which show what the trained network adds."""
@@ -385,7 +442,17 @@ def report(steps: int = 1000, weights: str | None = None, judge_every: int | Non
     pers = run(case, steps, zero, replace(cfg, residual=False), ctx=ctx)
     rates_only = run(case, steps, zero, cfg, ctx=ctx) if cfg.residual else None
     base = sph.DeviceState.from_numpy(case.state)
+    series = error_series(case, steps, net, cfg, ctx, base, every=series_every)
+    within = series["steps_within_tol"]
+    if within >= K_STEPS:
+        # both loops timed again over the steps that stayed within the tolerance
+        p_in = run(case, within, None, ctx=ctx)
+        s_in = run(case, within, net, cfg, ctx=ctx)
+        speed_in = p_in["seconds"] / s_in["seconds"]
+    else:
+        speed_in = None
     out = {"workload": case.name + f"_obstacle_seed{obstacle_seed}", "n": n, "steps": steps,
+           "vs_plain_trajectory": series, "speedup_within_tol_of_plain_trajectory": speed_in,
            "plain_steps_per_s": steps / plain["seconds"],
            "surrogate_steps_per_s": steps / sur["seconds"],
            "speedup": plain["seconds"] / sur["seconds"],
