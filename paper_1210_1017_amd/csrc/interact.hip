@@ -119,7 +119,9 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
     const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
     const float hinv2 = -0.5f * kp.inv_h;
     const float eta2 = kp.eta2, h = kp.h;
-    const float kvis = -kp.alpha * kp.h * kp.c0;  // Pi_ij = kvis (s_i^3 + s_j^3) vr R
+    // Pi_ij = kvis (s_i^2 - s_i s_j + s_j^2) vr / (r^2 + eta^2)
+    const float kvis = -kp.alpha * kp.h * kp.c0 * kp.inv_rho0;
+    const float si2 = si * si;
 
     auto pair = [&](const v4f pj, const v4f vj) {
         const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
@@ -140,15 +142,15 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
         const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
         const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
         drho = fmaf(F, vr, drho);
-        // one reciprocal for mu = h vr / (r^2 + eta^2) and for the
-        // viscous term -alpha cbar mu / rhobar; h (in nu) and kvis
-        // (in the force factor) are applied outside the product
-        const float rs = rhoi + vj.w;
-        const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
-        const float vR = vr * R;
-        nu = fmaxf(nu, fabsf(rs * vR));  // |mu| / h
+        // mu = h vr / (r^2 + eta^2) and the viscous term -alpha cbar mu /
+        // rhobar with cbar = c0 (s_i^3 + s_j^3) / 2, rhobar = rho0 (s_i + s_j) / 2:
+        // (s_i^3 + s_j^3) / (s_i + s_j) = s_i^2 - s_i s_j + s_j^2, so one
+        // reciprocal serves both; h (in nu) and -alpha c0 h / rho0 (in the
+        // force factor) are applied outside the sums
+        const float vR = vr * __builtin_amdgcn_rcpf(r2 + eta2);
+        nu = fmaxf(nu, fabsf(vR));  // |mu| / h
         const float sj = vj.w * kp.inv_rho0;
-        const float visc = vr < 0.0f ? fmaf(sj * sj, sj, si3) * vR : 0.0f;  // Pi / kvis
+        const float visc = vr < 0.0f ? fmaf(sj, sj - si, si2) * vR : 0.0f;  // Pi / kvis
         const float f = fmaf(kvis, visc, Pi + pj.w) * F;
         axs = fmaf(f, dx, axs);
         ays = fmaf(f, dy, ays);
@@ -233,12 +235,15 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
         // consecutive particles lie in one (x, y) column or in neighbouring
         // ones, whose neighbour columns are neighbours in the x-major order
         // too, so the range is compact except where the block crosses an
-        // x-layer of cells
-        uint32_t lo = len ? jb : 0xffffffffu, hi = len ? je : 0u;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
-            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        // x-layer of cells. For a fixed offset the neighbour cell of a later
+        // particle (in sorted order) is never an earlier cell, so jb and je
+        // never decrease along the lanes: the wave's range runs from the jb
+        // of its first lane with a run to the je of its last.
+        const unsigned long long wm = __ballot(len != 0u);
+        uint32_t lo = 0xffffffffu, hi = 0u;
+        if (wm) {
+            lo = (uint32_t)__builtin_amdgcn_readlane((int)jb, __builtin_ctzll(wm));
+            hi = (uint32_t)__builtin_amdgcn_readlane((int)je, 63 - __builtin_clzll(wm));
         }
         if ((tid & 63) == 0) {
             s_lo[tid >> 6] = lo;
