@@ -497,6 +497,7 @@ def main() -> int:
     cand = ctx.candidate_total() - cand0
     status = ctx.status()
     counts = ctx.counts()
+    movers, merged = ctx.sort_stats()
     ctx.timing_begin(0)
     print(f"[bench] {args.steps} steps in {elapsed:.3f} s; status {status}; counts "
           f"{counts['n_label']}", file=sys.stderr, flush=True)
@@ -530,6 +531,9 @@ def main() -> int:
         "phase_ms": {"sort": float(phases[:, 0].mean()), "interact": float(phases[:, 1].mean()),
                      "dt_update": float(phases[:, 2].mean())},
         "roofline": roof,
+        # which way the last timed step sorted: the movers (keys changed since
+        # the previous sort) merged with the rest, or the full radix sort
+        "sort_path": {"movers_last_step": movers, "merged_last_step": merged},
     }
     if args.probe_reps > 0:
         out["machine"] = machine_probe(args.probe_reps)

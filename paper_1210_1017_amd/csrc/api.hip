@@ -68,7 +68,7 @@ void free_all(sph_ctx *c) {
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
                     c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->pos4, c->vel4,
-                    c->rate, c->info};
+                    c->rate, c->info, c->mmask, c->mwpre, c->mcnt, c->mki, c->msplit, c->mtile};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -200,6 +200,12 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     ALLOC(c->vals_b, cap * 4);
     ALLOC(c->perm, cap * 4);
     ALLOC(c->hist, (size_t)256 * c->max_tiles * 4);
+    ALLOC(c->mmask, (cap / 64 + 1) * sizeof(unsigned long long));
+    ALLOC(c->mwpre, (cap / 64 + 1) * 4);
+    ALLOC(c->mcnt, (size_t)c->max_tiles * 4 + 4);
+    ALLOC(c->mki, (size_t)kIncCap * sizeof(uint2));
+    ALLOC(c->mtile, (size_t)c->max_tiles * sizeof(uint2) + 8);
+    ALLOC(c->msplit, (size_t)kIncCap * 4 + 4);
     ALLOC(c->digit_tot, 256 * 4);
     ALLOC(c->cell_begin, (size_t)ncells * 4);
     ALLOC(c->cell_end, (size_t)ncells * 4);
@@ -263,12 +269,10 @@ int sph_sort_kv(sph_ctx *c, const uint32_t *keys, const int32_t *vals, uint32_t 
 }
 
 static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n, hipStream_t s) {
-    // keys with the first digit histogram; the gather also forms the counts
-    hipError_t e = launch_keys_hist(c, *in, n, s);
-    if (e == hipSuccess) e = radix_sort(c, c->keys_a, c->vals_a, c->keys_sorted, c->perm, n,
-                                        c->cell_bits + 2, s, true);
-    if (e == hipSuccess) e = launch_tables(c, n, s, false);
-    if (e == hipSuccess) e = launch_gather(c, *in, *out, n, s);
+    // the sorted keys and cell tables of the previous sort (any path) are the
+    // reference of the incremental sort; without one every particle moves
+    const uint32_t nprev = c->have_sort ? c->sorted_n : 0u;
+    hipError_t e = sort_state(c, *in, *out, n, nprev, s);
     if (e != hipSuccess) return hip_fail(c, e, "sort step");
     c->sorted_n = n;
     c->have_sort = true;
@@ -403,6 +407,17 @@ int sph_get_dt(sph_ctx *c, float *dt, void *stream) {
     float m;
     memcpy(&m, &h.dtmin_bits, sizeof m);
     *dt = c->kp.cfl * m;
+    return SPH_OK;
+}
+
+int sph_get_sort_stats(sph_ctx *c, uint32_t *movers, uint32_t *merged, void *stream) {
+    if (!movers || !merged) return c ? fail(c, SPH_E_INVALID_ARG, "null output") : SPH_E_INVALID_ARG;
+    DevInfo h;
+    int r = read_info(c, &h, stream);
+    if (r) return r;
+    if (!c->have_sort || c->last_path != 0) return fail(c, SPH_E_STATE, "no plain sort yet");
+    *movers = h.movers;
+    *merged = h.sort_mode == kModeIncr ? 1u : 0u;
     return SPH_OK;
 }
 

@@ -20,24 +20,39 @@ __global__ __launch_bounds__(256) void k_keys(KParams kp, const float *__restric
 }
 
 // Keys fused with the digit histogram of the first radix pass (one radix
-// tile per block, as k_radix_hist): saves a kernel and a pass over the keys.
-__global__ __launch_bounds__(kSortThreads) void k_keys_hist(KParams kp, const float *__restrict__ x,
-                                                            const float *__restrict__ y,
-                                                            const float *__restrict__ z,
-                                                            const uint8_t *__restrict__ type,
-                                                            uint32_t n, uint32_t ntiles,
-                                                            uint32_t *__restrict__ keys,
-                                                            int32_t *__restrict__ vals,
-                                                            uint32_t *__restrict__ hist) {
+// tile per block, as k_radix_hist) and with the mover flags of the
+// incremental sort: particle i is a mover when i >= nprev or its key differs
+// from prev[i], the key the previous sort left at index i. Per 64 particles
+// (one wave of one round) the mover bits and the movers before that word in
+// the tile; per tile the mover count, the smallest and largest key, and its
+// movers' (key, index) in index order at the tile's own place of
+// (segk, segi).
+__global__ __launch_bounds__(kSortThreads) void k_keys_move(
+    KParams kp, const float *__restrict__ x, const float *__restrict__ y,
+    const float *__restrict__ z, const uint8_t *__restrict__ type, uint32_t n, uint32_t ntiles,
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,
+    const uint32_t *__restrict__ prev, uint32_t nprev, unsigned long long *__restrict__ mmask,
+    uint32_t *__restrict__ mwpre, uint32_t *__restrict__ mcnt, uint32_t *__restrict__ segk,
+    uint32_t *__restrict__ segi, uint2 *__restrict__ mtile) {
+    constexpr int NW = kSortThreads / 64;
+    constexpr int WPT = kSortTile / 64;  // mask words per tile
+    static_assert(WPT <= 64, "one wave scans a tile's words");
     __shared__ uint32_t h[256];
-    const int tid = threadIdx.x;
+    __shared__ uint32_t s_wc[WPT];
+    __shared__ uint32_t s_kmin, s_kmax;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     h[tid] = 0;
+    if (tid == 0) {
+        s_kmin = 0xffffffffu;
+        s_kmax = 0u;
+    }
     __syncthreads();
     const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
-    // all of the thread's positions and types first (clamped index: in bounds
-    // for every lane), then the keys
+    // all of the thread's loads first (clamped index: in bounds for every
+    // lane), then the keys
     float px[kSortItems], py[kSortItems], pz[kSortItems];
     uint8_t pt[kSortItems];
+    uint32_t pk[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + tid;
@@ -46,27 +61,61 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_hist(KParams kp, const fl
         py[r] = y[ic];
         pz[r] = z[ic];
         pt[r] = type[ic];
+        pk[r] = nprev ? prev[idx < nprev ? idx : nprev - 1u] : 0u;
     }
+    uint32_t key[kSortItems];
+    unsigned long long bm[kSortItems];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t idx = base + r * kSortThreads + tid;
-        if (idx < n) {
-            const uint32_t key = cell_key(kp, px[r], py[r], pz[r], pt[r]);
-            keys[idx] = key;
-            vals[idx] = (int32_t)idx;
-            atomicAdd(&h[key & 255u], 1u);
+        const bool valid = idx < n;
+        key[r] = cell_key(kp, px[r], py[r], pz[r], pt[r]);
+        if (valid) {
+            keys[idx] = key[r];
+            atomicAdd(&h[key[r] & 255u], 1u);
+            kmin = key[r] < kmin ? key[r] : kmin;
+            kmax = key[r] > kmax ? key[r] : kmax;
         }
+        bm[r] = __ballot(valid && (idx >= nprev || key[r] != pk[r]));
+        if (lane == 0) {
+            s_wc[r * NW + w] = (uint32_t)__popcll(bm[r]);
+            if (base + (uint32_t)(r * kSortThreads + w * 64) < n)
+                mmask[(base >> 6) + (uint32_t)(r * NW + w)] = bm[r];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)kmin, o), c = (uint32_t)__shfl_xor((int)kmax, o);
+        kmin = a < kmin ? a : kmin;
+        kmax = c > kmax ? c : kmax;
+    }
+    if (lane == 0) {
+        atomicMin(&s_kmin, kmin);
+        atomicMax(&s_kmax, kmax);
     }
     __syncthreads();
     hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
-}
-
-hipError_t launch_keys_hist(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
-    hipLaunchKernelGGL(k_keys_hist, dim3(ntiles), dim3(kSortThreads), 0, s, c->kp, in.x, in.y,
-                       in.z, in.type, n, ntiles, c->keys_a, c->vals_a, c->hist);
-    return hipGetLastError();
+    if (tid == 0) mtile[blockIdx.x] = make_uint2(s_kmin, s_kmax);
+    if (tid < 64) {  // word r * NW + w covers particles base + 64 (r * NW + w) + [0, 64)
+        const uint32_t v = tid < WPT ? s_wc[tid] : 0u;
+        const uint32_t inc = wave_incl_scan(v);
+        if (tid < WPT) {
+            s_wc[tid] = inc - v;
+            if (base + 64u * (uint32_t)tid < n) mwpre[(base >> 6) + tid] = inc - v;
+        }
+        if (tid == 63) mcnt[blockIdx.x] = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        if ((bm[r] >> lane) & 1ull) {
+            const uint32_t at = base + s_wc[r * NW + w] + (uint32_t)__popcll(bm[r] & lt);
+            segk[at] = key[r];
+            segi[at] = base + r * kSortThreads + tid;
+        }
+    }
 }
 
 hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_t *keys,
@@ -93,7 +142,9 @@ hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              uint32_t n, int shift,
                                                              uint32_t ntiles,
-                                                             uint32_t *__restrict__ hist) {
+                                                             uint32_t *__restrict__ hist,
+                                                             const uint32_t *__restrict__ skip) {
+    if (skip && *skip == kModeIncr) return;
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
     h[tid] = 0;
@@ -113,7 +164,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
 }
 
 __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t ntiles,
-                                                    uint32_t *__restrict__ tot) {
+                                                    uint32_t *__restrict__ tot,
+                                                    const uint32_t *__restrict__ skip) {
+    if (skip && *skip == kModeIncr) return;
     __shared__ uint32_t s_w[4];
     uint32_t *row = hist + (size_t)blockIdx.x * ntiles;
     const int tid = threadIdx.x;
@@ -142,7 +195,9 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist,
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     int32_t *__restrict__ vout, uint32_t n, int shift, uint32_t ntiles,
-    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot) {
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
+    const uint32_t *__restrict__ skip) {
+    if (skip && *skip == kModeIncr) return;
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t s_k[kSortTile];
     __shared__ int32_t s_v[kSortTile];
@@ -172,7 +227,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const uint32_t idx = base + r * kSortThreads + tid;
         const bool valid = idx < n;
         key[r] = valid ? kin[idx] : 0xffffffffu;
-        val[r] = valid ? vin[idx] : 0;
+        val[r] = valid ? (vin ? vin[idx] : (int32_t)idx) : 0;  // no values: the index
     }
     __syncthreads();
     // rank among the wave's lanes with the same digit in this round (ballots
@@ -231,9 +286,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
 }
 
+// vals_in may be null: the first pass then takes each key's index as its value.
 hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_in,
                       uint32_t *keys_out, int32_t *vals_out, uint32_t n, int key_bits,
-                      hipStream_t s, bool first_hist_done) {
+                      hipStream_t s, bool first_hist_done, const uint32_t *skip) {
     if (n == 0) return hipSuccess;
     const int passes = (key_bits + 7) / 8;
     const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
@@ -253,11 +309,11 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
         const int shift = 8 * p;
         if (p > 0 || !first_hist_done)
             hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, n,
-                               shift, ntiles, c->hist);
+                               shift, ntiles, c->hist, skip);
         hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, c->hist, ntiles,
-                           c->digit_tot);
+                           c->digit_tot, skip);
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, vsrc,
-                           kdst, vdst, n, shift, ntiles, c->hist, c->digit_tot);
+                           kdst, vdst, n, shift, ntiles, c->hist, c->digit_tot, skip);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         ksrc = kdst;
@@ -284,16 +340,294 @@ hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint
         int32_t *vdst = to_out ? vals_out : vs;
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, n, shift,
-                           ntiles, hist);
-        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, hist, ntiles, tot);
+                           ntiles, hist, nullptr);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, hist, ntiles, tot, nullptr);
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, vsrc,
-                           kdst, vdst, n, shift, ntiles, hist, tot);
+                           kdst, vdst, n, shift, ntiles, hist, tot, nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         ksrc = kdst;
         vsrc = vdst;
     }
     return hipSuccess;
+}
+
+// ------------------------------------------------------ incremental sort
+// Between two sorts of one simulation most particles keep their cell, so the
+// key of the particle at index i usually equals prev[i], the key the previous
+// sort left at index i. Such a particle is a stayer; every other one (and
+// every index at or beyond the previous sort's n) is a mover. The stayers'
+// keys are the previous sorted keys at their indices, so in index order they
+// never decrease, and the stable sort of all keys is the merge, by
+// (key, index), of the stayers in index order with the movers stably sorted
+// by key (the stable order is unique, so the result is the radix sort's):
+//   stayer i:  dest = i - (movers before index i) + (movers below (key_i, i))
+//   mover k (k-th in (key, index) order):
+//              dest = (stayers below (key, index)) + k,
+// where the stayers below (key, j) are the non-movers before
+// P = clamp(j, lower_bound(prev, key), upper_bound(prev, key)): the pairs
+// (prev[p], p) increase with p. Both bounds come from the previous sort's
+// cell tables (label 0), the label's first index and the previous n
+// (label 3: one key), or a search of prev within the label's range (labels
+// 1 and 2). k_keys_move flags the movers; k_move_plan sorts up to kIncCap of
+// them in LDS (with more it selects the radix passes, whose kernels then run
+// while the merge work is skipped, and vice versa); k_gather moves every
+// particle to its place.
+
+// Movers at indices below q (q <= n).
+__device__ __forceinline__ uint32_t movers_before(uint32_t q, uint32_t n, uint32_t m,
+                                                  const unsigned long long *__restrict__ mmask,
+                                                  const uint32_t *__restrict__ mwpre,
+                                                  const uint32_t *__restrict__ moff) {
+    if (q >= n) return m;
+    const uint32_t wd = q >> 6;
+    return moff[q / (uint32_t)kSortTile] + mwpre[wd] +
+           (uint32_t)__popcll(mmask[wd] & ((1ull << (q & 63u)) - 1ull));
+}
+
+__device__ __forceinline__ uint32_t upper_in(const uint32_t *__restrict__ a, uint32_t lo,
+                                             uint32_t hi, uint32_t key) {
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] <= key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t lower_in(const uint32_t *__restrict__ a, uint32_t lo,
+                                             uint32_t hi, uint32_t key) {
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// The index q below which the stayers precede (key, j) in (key, index)
+// order: P = clamp(j, lower_bound, upper_bound) over the previous keys, at
+// most ns (no stayer at or beyond ns). lb and ub as found for the key.
+__device__ __forceinline__ uint32_t stayer_split(uint32_t j, uint32_t lb, uint32_t ub,
+                                                 uint32_t nprev, uint32_t ns) {
+    lb = lb < nprev ? lb : nprev;
+    ub = ub < lb ? lb : (ub < nprev ? ub : nprev);
+    const uint32_t P = j < lb ? lb : (j > ub ? ub : j);
+    return P < ns ? P : ns;
+}
+
+constexpr int kPlanThreads = 1024;
+constexpr uint32_t kNoSplit = 0xffffffffu;
+
+// One block. Per-tile mover counts -> exclusive offsets (in place) and the
+// total m. If m <= kIncCap: each tile's movers (index order, from the
+// tile's segment) into LDS at the tile's offset; a stable LSD radix sort by
+// key (8-bit digits, ranks from wave ballots as in k_radix_scatter, one
+// particle per thread per round); out as (key, index), with the stayer split
+// of the label-1 and label-2 movers (a search of the previous keys; the
+// gather finds the others' from the cell tables).
+__global__ __launch_bounds__(kPlanThreads) void k_move_plan(
+    uint32_t n, uint32_t ntiles, int passes, const uint32_t *__restrict__ segk,
+    const uint32_t *__restrict__ segi, uint32_t *__restrict__ mcnt, const uint32_t *__restrict__ prev,
+    uint32_t nprev, uint32_t cell_bits, uint2 *__restrict__ mki, uint32_t *__restrict__ msplit,
+    uint2 *__restrict__ mtile, DevInfo *__restrict__ info) {
+    constexpr int NW = kPlanThreads / 64;
+    __shared__ uint32_t s_k[2][kIncCap];
+    __shared__ uint32_t s_i[2][kIncCap];
+    __shared__ uint32_t s_wc[NW][256];
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_w[NW];
+    __shared__ uint32_t s_hist[4][256];  // digit counts of every pass
+    __shared__ uint32_t s_big;  // a tile with more movers than one thread copies was seen
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_big = 0u;
+    (&s_hist[0][0])[tid] = 0u;
+    // per-(wave, digit) counts carry the stamp of their round in the high
+    // half: entries of earlier rounds read as zero, so no clearing per round
+    for (int q = tid; q < NW * 256; q += kPlanThreads) (&s_wc[0][0])[q] = 0u;
+    // the first tiles' key ranges, needed at the end: loaded now
+    const uint2 kr0 = (uint32_t)tid < ntiles ? mtile[tid] : make_uint2(0u, 0u);
+
+    // offsets, one tile per thread per round; a thread copies the movers of
+    // its tile when there are at most kSmall (loads in flight together), a
+    // wave those of larger tiles below
+    constexpr uint32_t kSmall = 12;
+    uint32_t running = 0;
+    for (uint32_t start = 0; start < ntiles; start += kPlanThreads) {
+        const uint32_t t = start + (uint32_t)tid;
+        const uint32_t v = t < ntiles ? mcnt[t] : 0u;
+        uint32_t total;
+        const uint32_t pre = block_excl_scan<kPlanThreads>(v, s_w, &total) + running;
+        running += total;
+        const bool fits = running <= kIncCap;  // the same in every thread
+        if (t < ntiles) mcnt[t] = pre;
+        if (fits && v > kSmall) s_big = 1u;
+        if (fits && v > 0u && v <= kSmall) {
+            const uint32_t sb = t * (uint32_t)kSortTile;
+            uint32_t kk[kSmall], ii[kSmall];
+#pragma unroll
+            for (uint32_t u = 0; u < kSmall; u++) {
+                const uint32_t j = u < v ? u : v - 1u;
+                kk[u] = segk[sb + j];
+                ii[u] = segi[sb + j];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kSmall; u++)
+                if (u < v) {
+                    s_k[0][pre + u] = kk[u];
+                    s_i[0][pre + u] = ii[u];
+                }
+        }
+    }
+    const uint32_t m = running;
+    if (m > kIncCap) {
+        if (tid == 0) {
+            info->sort_mode = kModeFull;
+            info->movers = m;
+        }
+        return;
+    }
+    __syncthreads();  // offsets (global) and s_big
+    if (s_big) {
+        // tiles with more movers: wave w takes tiles w, w + NW, ... (lane j
+        // reads the offsets of the j-th of them), 64 movers per load and
+        // eight loads in flight
+        for (uint32_t g = 0; g * (uint32_t)(NW * 64) < ntiles; g++) {
+            const uint32_t t = (uint32_t)w + (uint32_t)NW * ((uint32_t)lane + 64u * g);
+            const uint32_t off = t < ntiles ? mcnt[t] : m;
+            const uint32_t nxt = t + 1 < ntiles ? mcnt[t + 1] : m;
+            unsigned long long big = __ballot(t < ntiles && nxt - off > kSmall);
+            while (big) {
+                const int src = __builtin_ctzll(big);
+                big &= big - 1ull;
+                const uint32_t tt = (uint32_t)w + (uint32_t)NW * ((uint32_t)src + 64u * g);
+                const uint32_t toff = __shfl(off, src), tcnt = __shfl(nxt - off, src);
+                const uint32_t sb = tt * (uint32_t)kSortTile;
+                for (uint32_t j0 = 0; j0 < tcnt; j0 += 512) {
+                    uint32_t kk[8], ii[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const uint32_t j = j0 + (uint32_t)(u * 64 + lane);
+                        const uint32_t jc = j < tcnt ? j : tcnt - 1u;
+                        kk[u] = segk[sb + jc];
+                        ii[u] = segi[sb + jc];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const uint32_t j = j0 + (uint32_t)(u * 64 + lane);
+                        if (j < tcnt) {
+                            s_k[0][toff + j] = kk[u];
+                            s_i[0][toff + j] = ii[u];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {  // digit counts of all passes
+        const uint32_t key = s_k[0][k];
+        for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+    }
+    __syncthreads();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int src = 0;
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        const uint32_t cnt = tid < 256 ? s_hist[p][tid] : 0u;
+        const uint32_t start = block_excl_scan<kPlanThreads>(cnt, s_w);
+        if (tid < 256) s_base[tid] = start;
+        for (uint32_t c0 = 0; c0 < m; c0 += kPlanThreads) {
+            const uint32_t stamp = (uint32_t)p * 64u + c0 / kPlanThreads + 1u;  // < 2^16
+            const uint32_t k = c0 + (uint32_t)tid;
+            const bool valid = k < m;
+            const uint32_t key = valid ? s_k[src][k] : 0u;
+            const uint32_t idx = valid ? s_i[src][k] : 0u;
+            const uint32_t d = (key >> shift) & 255u;
+            unsigned long long peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const bool bit = (d >> b) & 1u;
+                const unsigned long long mb = __ballot(bit);
+                peers &= bit ? mb : ~mb;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & lt);
+            if (valid && rank == 0) s_wc[w][d] = stamp << 16 | (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (tid < 256) {  // per digit: prefix over the waves in order
+                uint32_t c[NW];
+#pragma unroll
+                for (int q = 0; q < NW; q++) {
+                    const uint32_t e = s_wc[q][tid];
+                    c[q] = (e >> 16) == stamp ? (e & 0xffffu) : 0u;
+                }
+                uint32_t run = s_base[tid];
+#pragma unroll
+                for (int q = 0; q < NW; q++) {
+                    s_wc[q][tid] = run;
+                    run += c[q];
+                }
+                s_base[tid] = run;
+            }
+            __syncthreads();
+            if (valid) {
+                const uint32_t pos = s_wc[w][d] + rank;
+                s_k[src ^ 1][pos] = key;
+                s_i[src ^ 1][pos] = idx;
+            }
+            __syncthreads();
+        }
+        src ^= 1;
+    }
+    // per tile: the range of the sorted movers that can lie below its
+    // particles, [movers below (kmin, first index), movers below (kmax, end)]
+    for (uint32_t t = (uint32_t)tid; t < ntiles; t += kPlanThreads) {
+        const uint2 kr = t == (uint32_t)tid ? kr0 : mtile[t];
+        const uint32_t i0 = t * (uint32_t)kSortTile, i1 = i0 + (uint32_t)kSortTile;
+        // two lower bounds in step (the same halving sequence): the first
+        // sorted mover not below (kmin, first index), resp. (kmax, end)
+        uint32_t b0 = 0, b1 = 0;
+        for (uint32_t len = m; len > 1;) {
+            const uint32_t half = len / 2;
+            const uint32_t ka = s_k[src][b0 + half], ia = s_i[src][b0 + half];
+            const uint32_t kb = s_k[src][b1 + half], ib = s_i[src][b1 + half];
+            if (ka < kr.x || (ka == kr.x && ia < i0)) b0 += half;
+            if (kb < kr.y || (kb == kr.y && ib < i1)) b1 += half;
+            len -= half;
+        }
+        if (m > 0) {
+            const uint32_t ka = s_k[src][b0], ia = s_i[src][b0];
+            const uint32_t kb = s_k[src][b1], ib = s_i[src][b1];
+            b0 += (ka < kr.x || (ka == kr.x && ia < i0)) ? 1u : 0u;
+            b1 += (kb < kr.y || (kb == kr.y && ib < i1)) ? 1u : 0u;
+        }
+        mtile[t] = make_uint2(b0, b1);
+    }
+    const uint32_t ns = nprev < n ? nprev : n;
+    for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {
+        const uint32_t key = s_k[src][k], idx = s_i[src][k];
+        mki[k] = make_uint2(key, idx);
+        const uint32_t l = key >> cell_bits;
+        uint32_t split = kNoSplit;
+        if ((l == 1u || l == 2u) && ns > 0) {
+            uint32_t hi = info->lstart[l + 1];
+            hi = hi < nprev ? hi : nprev;
+            uint32_t lo = info->lstart[l];
+            lo = lo < hi ? lo : hi;
+            const uint32_t lb = lower_in(prev, lo, hi, key);
+            split = stayer_split(idx, lb, upper_in(prev, lb, hi, key), nprev, ns);
+        }
+        msplit[k] = split;
+    }
+    if (tid == 0) {
+        info->sort_mode = kModeIncr;
+        info->movers = m;
+    }
 }
 
 // ---------------------------------------------------- counts and ranges
@@ -309,9 +643,10 @@ hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint
 //             move little between sorts, so the bound is usually a few
 //             places away); the exponential-then-binary search is correct
 //             from any start, including uninitialised tables.
-//   k_counts: label counts, and the packing ranges of x-layers 0, 1,
-//             ncx-2, ncx-1 read off begin[] (each layer is one contiguous
-//             range of the x-major order, Sec. 4.2-4.3).
+//             With counts: label counts, and the packing ranges of x-layers
+//             0, 1, ncx-2, ncx-1, each the begin of a layer's first cell
+//             (each layer is one contiguous range of the x-major order,
+//             Sec. 4.2-4.3).
 __device__ __forceinline__ uint32_t lower_bound_from(const uint32_t *__restrict__ sk, uint32_t n,
                                                      uint32_t key, uint32_t hint) {
     hint = hint < n ? hint : n;
@@ -351,67 +686,74 @@ __device__ __forceinline__ uint32_t lower_bound_from(const uint32_t *__restrict_
     return lo;
 }
 
+// Cell of the packing range bound t < 8 (Sec. 4.2-4.3): the first cell of
+// x-layer 0, 1, ncx-2, ncx-1 (even t) or of the layer after it (odd t).
+__device__ __forceinline__ uint32_t layer_cell(const KParams &kp, int t) {
+    int lay;
+    switch (t >> 1) {
+        case 0: lay = 0; break;
+        case 1: lay = 1; break;
+        case 2: lay = kp.ncx - 2; break;
+        default: lay = kp.ncx - 1; break;
+    }
+    lay = lay < 0 ? 0 : (lay >= kp.ncx ? kp.ncx - 1 : lay);
+    return (uint32_t)(lay + (t & 1)) * (uint32_t)kp.ncy * (uint32_t)kp.ncz;
+}
+
+// With `counts`, each thread also writes the counts and ranges that its own
+// bounds decide: a cell thread the packing bounds at its cell, label thread
+// l the first index of label l, the size of label l and the ranges that
+// start or end there (no thread waits for another).
 __global__ __launch_bounds__(256) void k_tables(KParams kp, const uint32_t *__restrict__ sk,
                                                 uint32_t n, DevInfo *__restrict__ info,
                                                 uint32_t *__restrict__ begin,
-                                                uint32_t *__restrict__ end) {
+                                                uint32_t *__restrict__ end, int counts) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nc = kp.ncells;
     if (t < nc) {
         const uint32_t b = lower_bound_from(sk, n, t, begin[t]);
         begin[t] = b;
         if (t > 0) end[t - 1] = b;
+        if (counts)
+#pragma unroll
+            for (int r = 0; r < 8; r++)
+                if (layer_cell(kp, r) == t) info->ranges[r] = b;
     } else if (t < nc + 3) {
         const uint32_t l = t - nc + 1;
-        const uint32_t b = lower_bound_from(sk, n, l << kp.cell_bits, info->lstart[l]);
+        const uint32_t hint = info->lstart[l];
+        const uint32_t b = lower_bound_from(sk, n, l << kp.cell_bits, hint);
+        // the next label's first index (n after label 3), for the count
+        const uint32_t b1 = l < 3 ? lower_bound_from(sk, n, (l + 1) << kp.cell_bits, b) : n;
         info->lstart[l] = b;
         if (l == 1) {
             info->lstart[0] = 0;
             if (nc > 0) end[nc - 1] = b;
         }
-    }
-}
-
-// Thread t < 9 of one block: label counts and packing ranges.
-__device__ __forceinline__ void table_counts(const KParams &kp, const uint32_t *__restrict__ begin,
-                                             uint32_t n, DevInfo *__restrict__ info, int t) {
-    const uint32_t n0 = info->lstart[1];
-    if (t < 4) info->n_label[t] = (t < 3 ? info->lstart[t + 1] : n) - info->lstart[t];
-    if (t < 8) {
-        const uint32_t L = (uint32_t)kp.ncy * (uint32_t)kp.ncz;
-        int lay;
-        switch (t >> 1) {
-            case 0: lay = 0; break;
-            case 1: lay = 1; break;
-            case 2: lay = kp.ncx - 2; break;
-            default: lay = kp.ncx - 1; break;
+        if (counts) {
+            info->n_label[l] = b1 - b;
+            if (l == 1) {
+                info->n_label[0] = b;
+                info->ranges[8] = b;
+#pragma unroll
+                for (int r = 0; r < 8; r++)
+                    if (layer_cell(kp, r) >= nc) info->ranges[r] = b;
+            } else if (l == 2) {
+                info->ranges[9] = b;
+                info->ranges[10] = b;
+            } else {
+                info->ranges[11] = b;
+                info->ranges[12] = b;
+                info->ranges[13] = n;
+                if (n > b) atomicOr(&info->flags, (uint32_t)SPH_S_EXCLUDED);
+            }
         }
-        lay = lay < 0 ? 0 : (lay >= kp.ncx ? kp.ncx - 1 : lay);
-        const uint32_t c = (uint32_t)(lay + (t & 1)) * L;
-        info->ranges[t] = c < kp.ncells ? begin[c] : n0;
     }
-    if (t == 8) {
-        info->ranges[8] = info->lstart[1];
-        info->ranges[9] = info->lstart[2];
-        info->ranges[10] = info->lstart[2];
-        info->ranges[11] = info->lstart[3];
-        info->ranges[12] = info->lstart[3];
-        info->ranges[13] = n;
-        if (n > info->lstart[3]) atomicOr(&info->flags, (uint32_t)SPH_S_EXCLUDED);
-    }
-}
-
-__global__ void k_counts(KParams kp, const uint32_t *__restrict__ begin, uint32_t n,
-                         DevInfo *__restrict__ info) {
-    table_counts(kp, begin, n, info, (int)threadIdx.x);
 }
 
 hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s, bool counts) {
     const uint32_t threads = c->ncells + 3;
     hipLaunchKernelGGL(k_tables, dim3((threads + 255) / 256), dim3(256), 0, s, c->kp, c->keys_sorted,
-                       n, c->info, c->cell_begin, c->cell_end);
-    if (counts)
-        hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, s, c->kp, c->cell_begin, n, c->info);
+                       n, c->info, c->cell_begin, c->cell_end, counts ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -422,40 +764,123 @@ __device__ __forceinline__ void reset_step_reductions(DevInfo *info) {
     info->pairs = 0ull;
 }
 
-// Reorder every state array by the sorted permutation (Sec. 3.1: all arrays
-// are ordered according to the sorted IDs) and write the packed interaction
-// inputs (x, y, z, p/rho^2) and (vx, vy, vz, rho).
-// Block 0 also forms the label counts and packing ranges from the cell
-// tables (no separate kernel).
-__global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa out,
-                                                const int32_t *__restrict__ perm, uint32_t n,
-                                                float4 *__restrict__ pos4,
-                                                float4 *__restrict__ vel4,
-                                                const uint32_t *__restrict__ cbegin,
-                                                DevInfo *__restrict__ info) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0) reset_step_reductions(info);
-    if (k < 9) table_counts(kp, cbegin, n, info, (int)k);
-    if (k >= n) return;
-    const uint32_t s = (uint32_t)perm[k];
+// Reorder every state array by the sort (Sec. 3.1: all arrays are ordered
+// according to the sorted IDs) and write the packed interaction inputs
+// (x, y, z, p/rho^2) and (vx, vy, vz, rho). After the radix passes thread k
+// pulls particle perm[k] into place k; after the merge path thread i pushes
+// particle i to its destination and writes its key there (the sorted keys).
+struct MoveArgs {
+    const uint32_t *keys;  // unsorted keys (index order)
+    uint32_t *skeys;       // sorted keys: read as the previous ones, written by the merge
+    const uint2 *mki;
+    const uint2 *mtile;  // per tile: range of mki holding its particles' ranks
+    const uint32_t *msplit;
+    const unsigned long long *mmask;
+    const uint32_t *mwpre, *moff;
+    const uint32_t *cbegin, *cend;  // the previous sort's cell tables
+    uint32_t nprev;
+};
+
+__device__ __forceinline__ void move_particle(const KParams &kp, const sph_soa &in,
+                                              const sph_soa &out, uint32_t s, uint32_t k,
+                                              float4 *__restrict__ pos4,
+                                              float4 *__restrict__ vel4) {
     const float x = in.x[s], y = in.y[s], z = in.z[s];
     const float vx = in.vx[s], vy = in.vy[s], vz = in.vz[s], rho = in.rho[s];
+    const float vxp = in.vxp[s], vyp = in.vyp[s], vzp = in.vzp[s], rhop = in.rhop[s];
+    const uint8_t ty = in.type[s];
+    const int32_t id = in.id[s];
     out.x[k] = x; out.y[k] = y; out.z[k] = z;
     out.vx[k] = vx; out.vy[k] = vy; out.vz[k] = vz;
     out.rho[k] = rho;
-    out.vxp[k] = in.vxp[s]; out.vyp[k] = in.vyp[s]; out.vzp[k] = in.vzp[s];
-    out.rhop[k] = in.rhop[s];
-    out.type[k] = in.type[s];
-    out.id[k] = in.id[s];
+    out.vxp[k] = vxp; out.vyp[k] = vyp; out.vzp[k] = vzp;
+    out.rhop[k] = rhop;
+    out.type[k] = ty;
+    out.id[k] = id;
     pos4[k] = make_float4(x, y, z, tait_p_over_rho2(kp, rho));
     vel4[k] = make_float4(vx, vy, vz, rho);
 }
 
-hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
-                         hipStream_t s) {
+__global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa out,
+                                                const int32_t *__restrict__ perm, uint32_t n,
+                                                float4 *__restrict__ pos4,
+                                                float4 *__restrict__ vel4,
+                                                DevInfo *__restrict__ info, MoveArgs mv) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) reset_step_reductions(info);
+    if (k >= n) return;
+    if (info->sort_mode != kModeIncr) {
+        move_particle(kp, in, out, (uint32_t)perm[k], k, pos4, vel4);
+        return;
+    }
+    const uint32_t i = k, m = info->movers;
+    const uint32_t key = mv.keys[i];
+    const uint2 range = mv.mtile[i / (uint32_t)kSortTile];
+    uint32_t lo = range.x, hi = range.y;  // movers below (key, i) in (key, index) order
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const uint2 e = mv.mki[mid];
+        if (e.x < key || (e.x == key && e.y < i))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const uint32_t wd = i >> 6;
+    const unsigned long long bits = mv.mmask[wd];
+    uint32_t dest;
+    if ((bits >> (i & 63u)) & 1ull) {  // a mover: lo is its own rank
+        const uint32_t ns = mv.nprev < n ? mv.nprev : n;
+        uint32_t q = mv.msplit[lo];
+        if (q == kNoSplit) {
+            if (ns == 0)
+                q = 0;
+            else if (key < kp.ncells)
+                q = stayer_split(i, mv.cbegin[key], mv.cend[key], mv.nprev, ns);
+            else  // label 3: a single key, from its first index to the end
+                q = stayer_split(i, info->lstart[3], mv.nprev, mv.nprev, ns);
+        }
+        dest = q - movers_before(q, n, m, mv.mmask, mv.mwpre, mv.moff) + lo;
+    } else {
+        const uint32_t before = mv.moff[i / (uint32_t)kSortTile] + mv.mwpre[wd] +
+                                (uint32_t)__popcll(bits & ((1ull << (i & 63u)) - 1ull));
+        dest = i - before + lo;
+    }
+    move_particle(kp, in, out, i, dest, pos4, vel4);
+    mv.skeys[dest] = key;
+}
+
+// The plain sort step: keys and mover flags, the mover plan, the radix passes
+// (run only when the plan chose them), reorder, cell tables and counts of
+// the new order.
+hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
+                      uint32_t nprev, hipStream_t s) {
+    const uint32_t *mode = &c->info->sort_mode;
+    if (n > 0) {
+        const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
+        const int key_bits = c->cell_bits + 2;
+        // the movers' tile segments live in the radix ping-pong pair, which
+        // the radix passes only write after the plan has read them
+        hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kSortThreads), 0, s, c->kp, in.x,
+                           in.y, in.z, in.type, n, ntiles, c->keys_a, c->hist, c->keys_sorted,
+                           nprev, c->mmask, c->mwpre, c->mcnt, c->keys_b, (uint32_t *)c->vals_b,
+                           c->mtile);
+        hipLaunchKernelGGL(k_move_plan, dim3(1), dim3(kPlanThreads), 0, s, n, ntiles,
+                           (key_bits + 7) / 8, c->keys_b, (const uint32_t *)c->vals_b, c->mcnt,
+                           c->keys_sorted, nprev, (uint32_t)c->cell_bits, c->mki, c->msplit,
+                           c->mtile, c->info);
+        // the first pass takes each key's index as its value
+        hipError_t e = radix_sort(c, c->keys_a, nullptr, c->keys_sorted, c->perm, n, key_bits,
+                                  s, true, mode);
+        if (e != hipSuccess) return e;
+    }
+    const MoveArgs mv = {c->keys_a, c->keys_sorted, c->mki,        c->mtile,    c->msplit,
+                         c->mmask,  c->mwpre,       c->mcnt,       c->cell_begin, c->cell_end,
+                         nprev};
     hipLaunchKernelGGL(k_gather, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, in,
-                       out, c->perm, n, c->pos4, c->vel4, c->cell_begin, c->info);
-    return hipGetLastError();
+                       out, c->perm, n, c->pos4, c->vel4, c->info, mv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_tables(c, n, s, true);
 }
 
 __global__ __launch_bounds__(256) void k_pack(KParams kp, sph_soa in, uint32_t n,

@@ -19,6 +19,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = SPH_SORT_ITEMS;  // keys per thread of a radix tile
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix tile
 constexpr int kInteractThreads = 256;
+// Incremental sort: at most kIncCap particles may change their key between
+// two sorts for the merge path; with more, the radix passes run.
+constexpr uint32_t kIncCap = 8192;
+constexpr uint32_t kModeFull = 0u, kModeIncr = 1u;
 constexpr int kRunBits = 12;                          // offset bits of a neighbour entry
 constexpr uint32_t kRunMax = (1u << kRunBits) - 1u;
 
@@ -52,6 +56,9 @@ struct DevInfo {
     unsigned long long pairs;        // neighbour pairs of the last interaction
     unsigned long long pairs_total;  // summed over every interaction since creation
     unsigned long long cand_total;   // candidates tested, summed likewise
+    uint32_t sort_mode;  // kModeFull / kModeIncr: the path the last plain sort took
+    uint32_t movers;     // particles whose key differs from the previous sort's at their index
+    uint32_t pad2_[2];
 };
 
 }  // namespace sph
@@ -68,6 +75,13 @@ struct sph_ctx {
     uint32_t *keys_a = nullptr, *keys_b = nullptr, *keys_sorted = nullptr;
     int32_t *vals_a = nullptr, *vals_b = nullptr, *perm = nullptr;
     uint32_t *hist = nullptr;       // 256 * max_tiles, digit-major
+    // incremental sort: mover bits per 64 particles, movers before each word
+    // within its tile, movers per tile (then their exclusive offsets), the
+    // movers sorted by (key, index), the stayer split of label-1/2 movers,
+    // per tile its key range, then the range of sorted movers below it
+    unsigned long long *mmask = nullptr;
+    uint32_t *mwpre = nullptr, *mcnt = nullptr, *msplit = nullptr;
+    uint2 *mki = nullptr, *mtile = nullptr;
     uint32_t *digit_tot = nullptr;  // 256
     uint32_t *cell_begin = nullptr, *cell_end = nullptr;
     float4 *pos4 = nullptr, *vel4 = nullptr;  // packed (x,y,z,p/rho^2), (vx,vy,vz,rho)
@@ -100,18 +114,18 @@ struct sph_ctx {
 namespace sph {
 
 // sort.hip
-hipError_t launch_keys_hist(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s);
 hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_t *keys,
                        int32_t *vals, hipStream_t s);
 hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_in,
                       uint32_t *keys_out, int32_t *vals_out, uint32_t n, int key_bits,
-                      hipStream_t s, bool first_hist_done = false);
+                      hipStream_t s, bool first_hist_done = false,
+                      const uint32_t *skip_mode = nullptr);
+hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
+                      uint32_t nprev, hipStream_t s);
 hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
                            int32_t *vals_out, uint32_t n, int key_bits, uint32_t *ks,
                            int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s);
 hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s, bool counts = true);
-hipError_t launch_gather(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
-                         hipStream_t s);
 hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s);
 hipError_t launch_clear_flags(sph_ctx *c, hipStream_t s);
 

@@ -129,6 +129,7 @@ def lib() -> C.CDLL:
         L.sph_get_counts.argtypes = [vp, P(Counts), vp]
         L.sph_get_dt.argtypes = [vp, P(C.c_float), vp]
         L.sph_get_pairs.argtypes = [vp, P(C.c_uint64), vp]
+        L.sph_get_sort_stats.argtypes = [vp, P(C.c_uint32), P(C.c_uint32), vp]
         L.sph_get_status.argtypes = [vp, P(C.c_uint32), vp]
         L.sph_clear_status.argtypes = [vp, vp]
         L.sph_get_pair_total.argtypes = [vp, P(C.c_uint64), vp]
@@ -463,6 +464,14 @@ class Context:
         v = C.c_uint64()
         self._check(self.L.sph_get_pairs(self.h, C.byref(v), _stream_ptr(stream)))
         return int(v.value)
+
+    def sort_stats(self, stream=None) -> tuple:
+        """(movers, merged) of the last plain sort: merged is True when the
+        movers were sorted and merged, False when the full radix sort ran."""
+        m, g = C.c_uint32(), C.c_uint32()
+        self._check(self.L.sph_get_sort_stats(self.h, C.byref(m), C.byref(g),
+                                               _stream_ptr(stream)))
+        return int(m.value), bool(g.value)
 
     def pair_total(self, stream=None) -> int:
         v = C.c_uint64()
