@@ -68,9 +68,11 @@ void free_all(sph_ctx *c) {
         if (p) (void)hipFree(p);
     void *ptrs[] = {c->keys_a, c->keys_b, c->keys_sorted, c->vals_a, c->vals_b, c->perm,
                     c->hist, c->digit_tot, c->cell_begin, c->cell_end, c->pos4, c->vel4,
-                    c->rate, c->info, c->mmask, c->mwpre, c->mcnt, c->mki, c->msplit, c->mtile};
+                    c->rate, c->info, c->mmask, c->mwpre, c->mcnt, c->mtile};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (c->fb) (void)hipHostFree(c->fb);
+    c->fb = c->fb_dev = nullptr;
 }
 
 }  // namespace
@@ -203,9 +205,7 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     ALLOC(c->mmask, (cap / 64 + 1) * sizeof(unsigned long long));
     ALLOC(c->mwpre, (cap / 64 + 1) * 4);
     ALLOC(c->mcnt, (size_t)c->max_tiles * 4 + 4);
-    ALLOC(c->mki, (size_t)kIncCap * sizeof(uint2));
     ALLOC(c->mtile, (size_t)c->max_tiles * sizeof(uint2) + 8);
-    ALLOC(c->msplit, (size_t)kIncCap * 4 + 4);
     ALLOC(c->digit_tot, 256 * 4);
     ALLOC(c->cell_begin, (size_t)ncells * 4);
     ALLOC(c->cell_end, (size_t)ncells * 4);
@@ -229,6 +229,13 @@ int sph_create(const sph_params *p, sph_ctx **out) {
         ALLOC(c->nn_rate, cap * 4 * sizeof(float));
     }
 #undef ALLOC
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->fb, sizeof(unsigned long long),
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        *c->fb = 0ull;
+        e = hipHostGetDevicePointer((void **)&c->fb_dev, c->fb, 0);
+    }
     if (e == hipSuccess) e = hipMemset(c->info, 0, sizeof(DevInfo));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -268,11 +275,20 @@ int sph_sort_kv(sph_ctx *c, const uint32_t *keys, const int32_t *vals, uint32_t 
     return SPH_OK;
 }
 
-static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n, hipStream_t s) {
+// skip_rv: the caller (the plain step) takes r, v and rho of the new order
+// from the packed arrays; the reorder leaves them out of `out`.
+static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n, hipStream_t s,
+                   bool skip_rv = false) {
     // the sorted keys and cell tables of the previous sort (any path) are the
     // reference of the incremental sort; without one every particle moves
     const uint32_t nprev = c->have_sort ? c->sorted_n : 0u;
-    hipError_t e = sort_state(c, *in, *out, n, nprev, s);
+    // the last mover plan that has run (the host does not wait for it) saw a
+    // previous sort and few movers: expect few again and launch only the
+    // merge (which still sorts any number of movers, slowly); else launch
+    // the radix passes too and let the plan choose
+    const unsigned long long fb = __atomic_load_n(c->fb, __ATOMIC_RELAXED);
+    const bool expect = nprev > 0 && (fb & 1ull) && (fb >> 1) <= kIncCap;
+    hipError_t e = sort_state(c, *in, *out, n, nprev, expect, skip_rv, s);
     if (e != hipSuccess) return hip_fail(c, e, "sort step");
     c->sorted_n = n;
     c->have_sort = true;
@@ -336,7 +352,11 @@ int sph_step(sph_ctx *c, const sph_soa *cur, sph_soa *next, uint32_t n, uint64_t
         c->ev_used++;
         (void)hipEventRecord(ev[0], s);
     }
-    r = do_sort(c, cur, next, n, s);
+    // the plain update writes r, v and rho of every particle from the packed
+    // arrays; the symplectic half step overwrites those, so it needs them in
+    // the state
+    const bool sym = (c->kp.options & SPH_O_SYMPLECTIC) != 0;
+    r = do_sort(c, cur, next, n, s, !sym);
     if (r) return r;
     if (ev) (void)hipEventRecord(ev[1], s);
     const size_t cap = c->capacity;
@@ -352,7 +372,8 @@ int sph_step(sph_ctx *c, const sph_soa *cur, sph_soa *next, uint32_t n, uint64_t
         if (e == hipSuccess) e = launch_sym_full(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, s);
     } else {
         e = launch_interact(c, next->type, n, rt, s, ev ? ev[2] : nullptr);
-        if (e == hipSuccess) e = launch_update(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, step, s);
+        if (e == hipSuccess)
+            e = launch_update(c, *next, rt.ax, rt.ay, rt.az, rt.arho, n, step, s, true);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(c, e, "step");

@@ -421,40 +421,191 @@ __device__ __forceinline__ uint32_t stayer_split(uint32_t j, uint32_t lb, uint32
 }
 
 constexpr int kPlanThreads = 1024;
+constexpr int kPlanWaves = kPlanThreads / 64;
 constexpr uint32_t kNoSplit = 0xffffffffu;
 
+// One round of a stable LSD radix pass over (sk, si)[c0, c0 + 1024) into
+// (dk, di) (LDS or global): ranks among the wave's lanes with the same digit
+// from 8 ballots, per-(wave, digit) counts stamped with the round so that
+// earlier rounds' entries read as zero, one prefix per digit over the waves
+// on top of the running digit starts s_base.
+__device__ __forceinline__ void lsd_round(const uint32_t *sk, const uint32_t *si, uint32_t *dk,
+                                          uint32_t *di, uint32_t m, uint32_t c0, int shift,
+                                          uint32_t stamp, uint32_t (*s_wc)[256],
+                                          uint32_t *s_base) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t k = c0 + (uint32_t)tid;
+    const bool valid = k < m;
+    const uint32_t key = valid ? sk[k] : 0u;
+    const uint32_t idx = valid ? si[k] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const unsigned long long mb = __ballot(bit);
+        peers &= bit ? mb : ~mb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    if (valid && rank == 0) s_wc[w][d] = stamp << 16 | (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (tid < 256) {  // per digit: prefix over the waves in order
+        uint32_t c[kPlanWaves];
+#pragma unroll
+        for (int q = 0; q < kPlanWaves; q++) {
+            const uint32_t e = s_wc[q][tid];
+            c[q] = (e >> 16) == stamp ? (e & 0xffffu) : 0u;
+        }
+        uint32_t run = s_base[tid];
+#pragma unroll
+        for (int q = 0; q < kPlanWaves; q++) {
+            s_wc[q][tid] = run;
+            run += c[q];
+        }
+        s_base[tid] = run;
+    }
+    __syncthreads();
+    if (valid) {
+        const uint32_t pos = s_wc[w][d] + rank;
+        dk[pos] = key;
+        di[pos] = idx;
+    }
+    __syncthreads();
+}
+
+// Stable LSD sort of (key, index) pairs by key: `passes` 8-bit digits, the
+// digit counts of all passes in s_hist. Returns the buffer (0 or 1) that
+// holds the result.
+__device__ __forceinline__ int lsd_sort(uint32_t *k0, uint32_t *i0, uint32_t *k1, uint32_t *i1,
+                                        uint32_t m, int passes, uint32_t (*s_wc)[256],
+                                        uint32_t *s_base, uint32_t (*s_hist)[256],
+                                        uint32_t *s_w, uint32_t *stamp) {
+    const int tid = threadIdx.x;
+    int src = 0;
+    for (int p = 0; p < passes; p++) {
+        const uint32_t cnt = tid < 256 ? s_hist[p][tid] : 0u;
+        const uint32_t start = block_excl_scan<kPlanThreads>(cnt, s_w);
+        if (tid < 256) s_base[tid] = start;
+        uint32_t *sk = src ? k1 : k0, *si = src ? i1 : i0;
+        uint32_t *dk = src ? k0 : k1, *di = src ? i0 : i1;
+        for (uint32_t c0 = 0; c0 < m; c0 += kPlanThreads) {
+            uint32_t st = ++*stamp & 0xffffu;
+            if (st == 0) {  // the stamps wrapped: clear, and skip stamp 0
+                for (int q = tid; q < kPlanWaves * 256; q += kPlanThreads) (&s_wc[0][0])[q] = 0u;
+                __syncthreads();
+                st = ++*stamp & 0xffffu;
+            }
+            lsd_round(sk, si, dk, di, m, c0, 8 * p, st, s_wc, s_base);
+        }
+        src ^= 1;
+    }
+    return src;
+}
+
+// Lower bounds of (k0, j0) and (k1, j1) in the (key, index)-sorted (sk, si)
+// of length m, searched in step (the same halving sequence).
+__device__ __forceinline__ uint2 lower_bound2(const uint32_t *sk, const uint32_t *si, uint32_t m,
+                                              uint32_t k0, uint32_t j0, uint32_t k1, uint32_t j1) {
+    uint32_t b0 = 0, b1 = 0;
+    for (uint32_t len = m; len > 1;) {
+        const uint32_t half = len / 2;
+        const uint32_t ka = sk[b0 + half], ia = si[b0 + half];
+        const uint32_t kb = sk[b1 + half], ib = si[b1 + half];
+        if (ka < k0 || (ka == k0 && ia < j0)) b0 += half;
+        if (kb < k1 || (kb == k1 && ib < j1)) b1 += half;
+        len -= half;
+    }
+    if (m > 0) {
+        const uint32_t ka = sk[b0], ia = si[b0];
+        const uint32_t kb = sk[b1], ib = si[b1];
+        b0 += (ka < k0 || (ka == k0 && ia < j0)) ? 1u : 0u;
+        b1 += (kb < k1 || (kb == k1 && ib < j1)) ? 1u : 0u;
+    }
+    return make_uint2(b0, b1);
+}
+
+// Wave-cooperative copy of the tiles' mover segments with more than `above`
+// movers to (dk, di) at the tiles' offsets: wave w takes tiles w, w + NW,
+// ... (lane j reads the offsets of the j-th of them), 64 movers per load and
+// eight loads in flight.
+__device__ __forceinline__ void copy_segments(const uint32_t *__restrict__ segk,
+                                              const uint32_t *__restrict__ segi,
+                                              const uint32_t *__restrict__ moff, uint32_t ntiles,
+                                              uint32_t m, uint32_t above, uint32_t *dk,
+                                              uint32_t *di) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (uint32_t g = 0; g * (uint32_t)(kPlanWaves * 64) < ntiles; g++) {
+        const uint32_t t = (uint32_t)w + (uint32_t)kPlanWaves * ((uint32_t)lane + 64u * g);
+        const uint32_t off = t < ntiles ? moff[t] : m;
+        const uint32_t nxt = t + 1 < ntiles ? moff[t + 1] : m;
+        unsigned long long big = __ballot(t < ntiles && nxt - off > above);
+        while (big) {
+            const int src = __builtin_ctzll(big);
+            big &= big - 1ull;
+            const uint32_t tt = (uint32_t)w + (uint32_t)kPlanWaves * ((uint32_t)src + 64u * g);
+            const uint32_t toff = __shfl(off, src), tcnt = __shfl(nxt - off, src);
+            const uint32_t sb = tt * (uint32_t)kSortTile;
+            for (uint32_t j0 = 0; j0 < tcnt; j0 += 512) {
+                uint32_t kk[8], ii[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const uint32_t j = j0 + (uint32_t)(u * 64 + lane);
+                    const uint32_t jc = j < tcnt ? j : tcnt - 1u;
+                    kk[u] = segk[sb + jc];
+                    ii[u] = segi[sb + jc];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const uint32_t j = j0 + (uint32_t)(u * 64 + lane);
+                    if (j < tcnt) {
+                        dk[toff + j] = kk[u];
+                        di[toff + j] = ii[u];
+                    }
+                }
+            }
+        }
+    }
+}
+
 // One block. Per-tile mover counts -> exclusive offsets (in place) and the
-// total m. If m <= kIncCap: each tile's movers (index order, from the
-// tile's segment) into LDS at the tile's offset; a stable LSD radix sort by
-// key (8-bit digits, ranks from wave ballots as in k_radix_scatter, one
-// particle per thread per round); out as (key, index), with the stayer split
-// of the label-1 and label-2 movers (a search of the previous keys; the
-// gather finds the others' from the cell tables).
+// total m, reported to the host word fb (m and whether there was a previous
+// sort) when fb is set. Then:
+//  * m <= kIncCap: the movers (index order, from the tiles' segments) into
+//    LDS at their tiles' offsets, sorted stably by key there;
+//  * m > kIncCap and allow_full: the radix passes are chosen, nothing more;
+//  * m > kIncCap otherwise (the host expected few movers): the movers are
+//    copied to global memory and sorted there by the same passes, slowly
+//    but exactly.
+// Out: the movers sorted by (key, index) in (outk, outi); per tile the range
+// of sorted movers its particles can fall between; the stayer split of the
+// label-1 and label-2 movers (a search of the previous keys; the gather
+// finds the others' from the cell tables) in tmpk. (tmpk, tmpi) is the
+// second buffer of the global sort; the one of (outk, outi) and (tmpk, tmpi)
+// that the pass count makes the start of the global sort must not be the
+// segments' buffer.
 __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
     uint32_t n, uint32_t ntiles, int passes, const uint32_t *__restrict__ segk,
     const uint32_t *__restrict__ segi, uint32_t *__restrict__ mcnt, const uint32_t *__restrict__ prev,
-    uint32_t nprev, uint32_t cell_bits, uint2 *__restrict__ mki, uint32_t *__restrict__ msplit,
-    uint2 *__restrict__ mtile, DevInfo *__restrict__ info) {
-    constexpr int NW = kPlanThreads / 64;
+    uint32_t nprev, uint32_t cell_bits, uint32_t *outk, uint32_t *outi, uint32_t *tmpk,
+    uint32_t *tmpi, uint2 *__restrict__ mtile,
+    DevInfo *__restrict__ info, int allow_full, unsigned long long *fb) {
     __shared__ uint32_t s_k[2][kIncCap];
     __shared__ uint32_t s_i[2][kIncCap];
-    __shared__ uint32_t s_wc[NW][256];
+    __shared__ uint32_t s_wc[kPlanWaves][256];
     __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_w[NW];
+    __shared__ uint32_t s_w[kPlanWaves];
     __shared__ uint32_t s_hist[4][256];  // digit counts of every pass
     __shared__ uint32_t s_big;  // a tile with more movers than one thread copies was seen
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x;
     if (tid == 0) s_big = 0u;
     (&s_hist[0][0])[tid] = 0u;
-    // per-(wave, digit) counts carry the stamp of their round in the high
-    // half: entries of earlier rounds read as zero, so no clearing per round
-    for (int q = tid; q < NW * 256; q += kPlanThreads) (&s_wc[0][0])[q] = 0u;
+    for (int q = tid; q < kPlanWaves * 256; q += kPlanThreads) (&s_wc[0][0])[q] = 0u;
     // the first tiles' key ranges, needed at the end: loaded now
     const uint2 kr0 = (uint32_t)tid < ntiles ? mtile[tid] : make_uint2(0u, 0u);
 
     // offsets, one tile per thread per round; a thread copies the movers of
-    // its tile when there are at most kSmall (loads in flight together), a
-    // wave those of larger tiles below
+    // its tile to LDS when there are at most kSmall (loads in flight
+    // together), a wave those of larger tiles below
     constexpr uint32_t kSmall = 12;
     uint32_t running = 0;
     for (uint32_t start = 0; start < ntiles; start += kPlanThreads) {
@@ -483,8 +634,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
                 }
         }
     }
-    const uint32_t m = running;
-    if (m > kIncCap) {
+    const uint32_t m = running;  // the same in every thread
+    if (tid == 0 && fb)
+        __hip_atomic_store(fb, (unsigned long long)m << 1 | (nprev > 0 ? 1ull : 0ull),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const bool small = m <= kIncCap;
+    if (!small && allow_full) {
         if (tid == 0) {
             info->sort_mode = kModeFull;
             info->movers = m;
@@ -492,126 +647,50 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
         return;
     }
     __syncthreads();  // offsets (global) and s_big
-    if (s_big) {
-        // tiles with more movers: wave w takes tiles w, w + NW, ... (lane j
-        // reads the offsets of the j-th of them), 64 movers per load and
-        // eight loads in flight
-        for (uint32_t g = 0; g * (uint32_t)(NW * 64) < ntiles; g++) {
-            const uint32_t t = (uint32_t)w + (uint32_t)NW * ((uint32_t)lane + 64u * g);
-            const uint32_t off = t < ntiles ? mcnt[t] : m;
-            const uint32_t nxt = t + 1 < ntiles ? mcnt[t + 1] : m;
-            unsigned long long big = __ballot(t < ntiles && nxt - off > kSmall);
-            while (big) {
-                const int src = __builtin_ctzll(big);
-                big &= big - 1ull;
-                const uint32_t tt = (uint32_t)w + (uint32_t)NW * ((uint32_t)src + 64u * g);
-                const uint32_t toff = __shfl(off, src), tcnt = __shfl(nxt - off, src);
-                const uint32_t sb = tt * (uint32_t)kSortTile;
-                for (uint32_t j0 = 0; j0 < tcnt; j0 += 512) {
-                    uint32_t kk[8], ii[8];
-#pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        const uint32_t j = j0 + (uint32_t)(u * 64 + lane);
-                        const uint32_t jc = j < tcnt ? j : tcnt - 1u;
-                        kk[u] = segk[sb + jc];
-                        ii[u] = segi[sb + jc];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        const uint32_t j = j0 + (uint32_t)(u * 64 + lane);
-                        if (j < tcnt) {
-                            s_k[0][toff + j] = kk[u];
-                            s_i[0][toff + j] = ii[u];
-                        }
-                    }
-                }
-            }
+    uint32_t stamp = 0;
+    const uint32_t *fk, *fi;  // the sorted movers
+    if (small) {
+        if (s_big) copy_segments(segk, segi, mcnt, ntiles, m, kSmall, s_k[0], s_i[0]);
+        __syncthreads();
+        for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {  // digit counts of all passes
+            const uint32_t key = s_k[0][k];
+            for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
         }
-    }
-    __syncthreads();
-
-    for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {  // digit counts of all passes
-        const uint32_t key = s_k[0][k];
-        for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
-    }
-    __syncthreads();
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    int src = 0;
-    for (int p = 0; p < passes; p++) {
-        const int shift = 8 * p;
-        const uint32_t cnt = tid < 256 ? s_hist[p][tid] : 0u;
-        const uint32_t start = block_excl_scan<kPlanThreads>(cnt, s_w);
-        if (tid < 256) s_base[tid] = start;
-        for (uint32_t c0 = 0; c0 < m; c0 += kPlanThreads) {
-            const uint32_t stamp = (uint32_t)p * 64u + c0 / kPlanThreads + 1u;  // < 2^16
-            const uint32_t k = c0 + (uint32_t)tid;
-            const bool valid = k < m;
-            const uint32_t key = valid ? s_k[src][k] : 0u;
-            const uint32_t idx = valid ? s_i[src][k] : 0u;
-            const uint32_t d = (key >> shift) & 255u;
-            unsigned long long peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; b++) {
-                const bool bit = (d >> b) & 1u;
-                const unsigned long long mb = __ballot(bit);
-                peers &= bit ? mb : ~mb;
-            }
-            const uint32_t rank = (uint32_t)__popcll(peers & lt);
-            if (valid && rank == 0) s_wc[w][d] = stamp << 16 | (uint32_t)__popcll(peers);
-            __syncthreads();
-            if (tid < 256) {  // per digit: prefix over the waves in order
-                uint32_t c[NW];
-#pragma unroll
-                for (int q = 0; q < NW; q++) {
-                    const uint32_t e = s_wc[q][tid];
-                    c[q] = (e >> 16) == stamp ? (e & 0xffffu) : 0u;
-                }
-                uint32_t run = s_base[tid];
-#pragma unroll
-                for (int q = 0; q < NW; q++) {
-                    s_wc[q][tid] = run;
-                    run += c[q];
-                }
-                s_base[tid] = run;
-            }
-            __syncthreads();
-            if (valid) {
-                const uint32_t pos = s_wc[w][d] + rank;
-                s_k[src ^ 1][pos] = key;
-                s_i[src ^ 1][pos] = idx;
-            }
-            __syncthreads();
+        __syncthreads();
+        const int r = lsd_sort(s_k[0], s_i[0], s_k[1], s_i[1], m, passes, s_wc, s_base, s_hist,
+                               s_w, &stamp);
+        for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {
+            outk[k] = s_k[r][k];
+            outi[k] = s_i[r][k];
         }
-        src ^= 1;
+        fk = s_k[r];
+        fi = s_i[r];
+    } else {
+        // the pass count decides where to start so that the result lands in
+        // (outk, outi)
+        uint32_t *ak = (passes & 1) ? tmpk : outk, *ai = (passes & 1) ? tmpi : outi;
+        uint32_t *bk = (passes & 1) ? outk : tmpk, *bi = (passes & 1) ? outi : tmpi;
+        copy_segments(segk, segi, mcnt, ntiles, m, 0u, ak, ai);
+        __syncthreads();
+        for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {
+            const uint32_t key = ak[k];
+            for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+        }
+        __syncthreads();
+        lsd_sort(ak, ai, bk, bi, m, passes, s_wc, s_base, s_hist, s_w, &stamp);
+        fk = outk;
+        fi = outi;
     }
     // per tile: the range of the sorted movers that can lie below its
     // particles, [movers below (kmin, first index), movers below (kmax, end)]
     for (uint32_t t = (uint32_t)tid; t < ntiles; t += kPlanThreads) {
         const uint2 kr = t == (uint32_t)tid ? kr0 : mtile[t];
-        const uint32_t i0 = t * (uint32_t)kSortTile, i1 = i0 + (uint32_t)kSortTile;
-        // two lower bounds in step (the same halving sequence): the first
-        // sorted mover not below (kmin, first index), resp. (kmax, end)
-        uint32_t b0 = 0, b1 = 0;
-        for (uint32_t len = m; len > 1;) {
-            const uint32_t half = len / 2;
-            const uint32_t ka = s_k[src][b0 + half], ia = s_i[src][b0 + half];
-            const uint32_t kb = s_k[src][b1 + half], ib = s_i[src][b1 + half];
-            if (ka < kr.x || (ka == kr.x && ia < i0)) b0 += half;
-            if (kb < kr.y || (kb == kr.y && ib < i1)) b1 += half;
-            len -= half;
-        }
-        if (m > 0) {
-            const uint32_t ka = s_k[src][b0], ia = s_i[src][b0];
-            const uint32_t kb = s_k[src][b1], ib = s_i[src][b1];
-            b0 += (ka < kr.x || (ka == kr.x && ia < i0)) ? 1u : 0u;
-            b1 += (kb < kr.y || (kb == kr.y && ib < i1)) ? 1u : 0u;
-        }
-        mtile[t] = make_uint2(b0, b1);
+        const uint32_t i0 = t * (uint32_t)kSortTile;
+        mtile[t] = lower_bound2(fk, fi, m, kr.x, i0, kr.y, i0 + (uint32_t)kSortTile);
     }
     const uint32_t ns = nprev < n ? nprev : n;
     for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {
-        const uint32_t key = s_k[src][k], idx = s_i[src][k];
-        mki[k] = make_uint2(key, idx);
+        const uint32_t key = fk[k], idx = fi[k];
         const uint32_t l = key >> cell_bits;
         uint32_t split = kNoSplit;
         if ((l == 1u || l == 2u) && ns > 0) {
@@ -622,7 +701,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
             const uint32_t lb = lower_in(prev, lo, hi, key);
             split = stayer_split(idx, lb, upper_in(prev, lb, hi, key), nprev, ns);
         }
-        msplit[k] = split;
+        tmpk[k] = split;
     }
     if (tid == 0) {
         info->sort_mode = kModeIncr;
@@ -772,8 +851,8 @@ __device__ __forceinline__ void reset_step_reductions(DevInfo *info) {
 struct MoveArgs {
     const uint32_t *keys;  // unsorted keys (index order)
     uint32_t *skeys;       // sorted keys: read as the previous ones, written by the merge
-    const uint2 *mki;
-    const uint2 *mtile;  // per tile: range of mki holding its particles' ranks
+    const uint32_t *mk, *mi;  // the movers sorted by (key, index)
+    const uint2 *mtile;       // per tile: the range of them its particles fall between
     const uint32_t *msplit;
     const unsigned long long *mmask;
     const uint32_t *mwpre, *moff;
@@ -781,18 +860,22 @@ struct MoveArgs {
     uint32_t nprev;
 };
 
+// With skip_rv the position, velocity and density go to the packed arrays
+// only (the step's update writes them to the state from there).
 __device__ __forceinline__ void move_particle(const KParams &kp, const sph_soa &in,
                                               const sph_soa &out, uint32_t s, uint32_t k,
                                               float4 *__restrict__ pos4,
-                                              float4 *__restrict__ vel4) {
+                                              float4 *__restrict__ vel4, bool skip_rv) {
     const float x = in.x[s], y = in.y[s], z = in.z[s];
     const float vx = in.vx[s], vy = in.vy[s], vz = in.vz[s], rho = in.rho[s];
     const float vxp = in.vxp[s], vyp = in.vyp[s], vzp = in.vzp[s], rhop = in.rhop[s];
     const uint8_t ty = in.type[s];
     const int32_t id = in.id[s];
-    out.x[k] = x; out.y[k] = y; out.z[k] = z;
-    out.vx[k] = vx; out.vy[k] = vy; out.vz[k] = vz;
-    out.rho[k] = rho;
+    if (!skip_rv) {
+        out.x[k] = x; out.y[k] = y; out.z[k] = z;
+        out.vx[k] = vx; out.vy[k] = vy; out.vz[k] = vz;
+        out.rho[k] = rho;
+    }
     out.vxp[k] = vxp; out.vyp[k] = vyp; out.vzp[k] = vzp;
     out.rhop[k] = rhop;
     out.type[k] = ty;
@@ -805,12 +888,13 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
                                                 const int32_t *__restrict__ perm, uint32_t n,
                                                 float4 *__restrict__ pos4,
                                                 float4 *__restrict__ vel4,
-                                                DevInfo *__restrict__ info, MoveArgs mv) {
+                                                DevInfo *__restrict__ info, MoveArgs mv,
+                                                int skip_rv) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) reset_step_reductions(info);
     if (k >= n) return;
     if (info->sort_mode != kModeIncr) {
-        move_particle(kp, in, out, (uint32_t)perm[k], k, pos4, vel4);
+        move_particle(kp, in, out, (uint32_t)perm[k], k, pos4, vel4, skip_rv != 0);
         return;
     }
     const uint32_t i = k, m = info->movers;
@@ -819,8 +903,8 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
     uint32_t lo = range.x, hi = range.y;  // movers below (key, i) in (key, index) order
     while (lo < hi) {
         const uint32_t mid = lo + (hi - lo) / 2;
-        const uint2 e = mv.mki[mid];
-        if (e.x < key || (e.x == key && e.y < i))
+        const uint32_t ek = mv.mk[mid], ei = mv.mi[mid];
+        if (ek < key || (ek == key && ei < i))
             lo = mid + 1;
         else
             hi = mid;
@@ -845,39 +929,45 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
                                 (uint32_t)__popcll(bits & ((1ull << (i & 63u)) - 1ull));
         dest = i - before + lo;
     }
-    move_particle(kp, in, out, i, dest, pos4, vel4);
+    move_particle(kp, in, out, i, dest, pos4, vel4, skip_rv != 0);
     mv.skeys[dest] = key;
 }
 
 // The plain sort step: keys and mover flags, the mover plan, the radix passes
-// (run only when the plan chose them), reorder, cell tables and counts of
-// the new order.
+// (run only when the plan chose them; not launched at all when the caller
+// expects few movers, the plan then sorting any number itself), reorder,
+// cell tables and counts of the new order.
 hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
-                      uint32_t nprev, hipStream_t s) {
+                      uint32_t nprev, bool expect_merge, bool skip_rv, hipStream_t s) {
     const uint32_t *mode = &c->info->sort_mode;
+    const int key_bits = c->cell_bits + 2;
+    const int passes = (key_bits + 7) / 8;
+    // the movers' tile segments live in (keys_b, vals_b); the sorted movers
+    // end in (keys_b, vals_b) after an odd number of passes, else in
+    // (perm, vals_a); the other pair holds the stayer splits
+    uint32_t *segk = c->keys_b, *segi = (uint32_t *)c->vals_b;
+    uint32_t *xk = (uint32_t *)c->perm, *xi = (uint32_t *)c->vals_a;
+    uint32_t *outk = (passes & 1) ? segk : xk, *outi = (passes & 1) ? segi : xi;
+    uint32_t *tmpk = (passes & 1) ? xk : segk, *tmpi = (passes & 1) ? xi : segi;
     if (n > 0) {
         const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
-        const int key_bits = c->cell_bits + 2;
-        // the movers' tile segments live in the radix ping-pong pair, which
-        // the radix passes only write after the plan has read them
         hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kSortThreads), 0, s, c->kp, in.x,
                            in.y, in.z, in.type, n, ntiles, c->keys_a, c->hist, c->keys_sorted,
-                           nprev, c->mmask, c->mwpre, c->mcnt, c->keys_b, (uint32_t *)c->vals_b,
-                           c->mtile);
-        hipLaunchKernelGGL(k_move_plan, dim3(1), dim3(kPlanThreads), 0, s, n, ntiles,
-                           (key_bits + 7) / 8, c->keys_b, (const uint32_t *)c->vals_b, c->mcnt,
-                           c->keys_sorted, nprev, (uint32_t)c->cell_bits, c->mki, c->msplit,
-                           c->mtile, c->info);
-        // the first pass takes each key's index as its value
-        hipError_t e = radix_sort(c, c->keys_a, nullptr, c->keys_sorted, c->perm, n, key_bits,
-                                  s, true, mode);
-        if (e != hipSuccess) return e;
+                           nprev, c->mmask, c->mwpre, c->mcnt, segk, segi, c->mtile);
+        hipLaunchKernelGGL(k_move_plan, dim3(1), dim3(kPlanThreads), 0, s, n, ntiles, passes, segk,
+                           segi, c->mcnt, c->keys_sorted, nprev, (uint32_t)c->cell_bits, outk,
+                           outi, tmpk, tmpi, c->mtile, c->info, expect_merge ? 0 : 1, c->fb_dev);
+        if (!expect_merge) {
+            // the first pass takes each key's index as its value
+            hipError_t e = radix_sort(c, c->keys_a, nullptr, c->keys_sorted, c->perm, n,
+                                      key_bits, s, true, mode);
+            if (e != hipSuccess) return e;
+        }
     }
-    const MoveArgs mv = {c->keys_a, c->keys_sorted, c->mki,        c->mtile,    c->msplit,
-                         c->mmask,  c->mwpre,       c->mcnt,       c->cell_begin, c->cell_end,
-                         nprev};
+    const MoveArgs mv = {c->keys_a, c->keys_sorted, outk,  outi,      c->mtile,   tmpk,
+                         c->mmask,  c->mwpre,       c->mcnt, c->cell_begin, c->cell_end, nprev};
     hipLaunchKernelGGL(k_gather, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, in,
-                       out, c->perm, n, c->pos4, c->vel4, c->info, mv);
+                       out, c->perm, n, c->pos4, c->vel4, c->info, mv, skip_rv ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_tables(c, n, s, true);

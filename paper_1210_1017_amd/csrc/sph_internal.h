@@ -76,12 +76,15 @@ struct sph_ctx {
     int32_t *vals_a = nullptr, *vals_b = nullptr, *perm = nullptr;
     uint32_t *hist = nullptr;       // 256 * max_tiles, digit-major
     // incremental sort: mover bits per 64 particles, movers before each word
-    // within its tile, movers per tile (then their exclusive offsets), the
-    // movers sorted by (key, index), the stayer split of label-1/2 movers,
-    // per tile its key range, then the range of sorted movers below it
+    // within its tile, movers per tile (then their exclusive offsets), per
+    // tile its key range, then the range of sorted movers below it
     unsigned long long *mmask = nullptr;
-    uint32_t *mwpre = nullptr, *mcnt = nullptr, *msplit = nullptr;
-    uint2 *mki = nullptr, *mtile = nullptr;
+    uint32_t *mwpre = nullptr, *mcnt = nullptr;
+    uint2 *mtile = nullptr;
+    // the mover plan's report to the host (pinned, mapped): movers << 1 |
+    // (there was a previous sort); read without waiting to choose the kernels
+    // of the next sort
+    unsigned long long *fb = nullptr, *fb_dev = nullptr;
     uint32_t *digit_tot = nullptr;  // 256
     uint32_t *cell_begin = nullptr, *cell_end = nullptr;
     float4 *pos4 = nullptr, *vel4 = nullptr;  // packed (x,y,z,p/rho^2), (vx,vy,vz,rho)
@@ -121,7 +124,7 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
                       hipStream_t s, bool first_hist_done = false,
                       const uint32_t *skip_mode = nullptr);
 hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
-                      uint32_t nprev, hipStream_t s);
+                      uint32_t nprev, bool expect_merge, bool skip_rv, hipStream_t s);
 hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
                            int32_t *vals_out, uint32_t n, int key_bits, uint32_t *ks,
                            int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s);
@@ -215,6 +218,6 @@ hipError_t launch_probe_copy(const void *src, void *dst, uint64_t bytes, uint32_
                              hipStream_t s);
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
                          const float *az, const float *arho, uint32_t n, uint64_t step,
-                         hipStream_t s);
+                         hipStream_t s, bool packed = false);
 
 }  // namespace sph

@@ -11,11 +11,17 @@ namespace sph {
 //   leapfrog: v' = v_prev + 2dt a,  rho' = rho_prev + 2dt D
 //   r' = r + dt v + dt^2 a / 2, then (v_prev, rho_prev) <- (v, rho).
 // With SPH_O_RHO_FLOOR a boundary particle's new density is at least rho0.
+// PACKED (inside sph_step): r, v and rho are read from the interaction's
+// packed inputs (pos4, vel4), which hold the same bits, and written for every
+// particle, updated or not, since the reorder left them out of the state.
+template <bool PACKED>
 __global__ __launch_bounds__(256) void k_verlet(KParams kp, sph_soa st,
                                                 const float *__restrict__ ax,
                                                 const float *__restrict__ ay,
                                                 const float *__restrict__ az,
                                                 const float *__restrict__ arho,
+                                                const float4 *__restrict__ pos4,
+                                                const float4 *__restrict__ vel4, uint32_t n,
                                                 DevInfo *__restrict__ info, int euler) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     // dt = CFL * (smallest per-particle limit of the interaction), Sec. 3.3
@@ -24,33 +30,56 @@ __global__ __launch_bounds__(256) void k_verlet(KParams kp, sph_soa st,
         info->dt = dt;
         if (!(dt > 0.0f) || !(dt < INFINITY)) atomicOr(&info->flags, (uint32_t)SPH_S_DT);
     }
-    if (k >= info->n_label[0]) return;
+    const uint32_t n0 = info->n_label[0];
+    if (k >= (PACKED ? n : n0)) return;
     const uint8_t t = st.type[k];
-    if (t == kGhost) return;
-    const float rho = st.rho[k];
-    float rn = euler ? fmaf(dt, arho[k], rho) : fmaf(2.0f * dt, arho[k], st.rhop[k]);
-    if ((kp.options & SPH_O_RHO_FLOOR) && t == kBoundary && rn < kp.rho0) rn = kp.rho0;
-    st.rhop[k] = rho;
-    st.rho[k] = rn;
-    bool ok = isfinite(rn);
-    if (t == kFluid) {
-        const float a[3] = {ax[k], ay[k], az[k]};
-        float *pos[3] = {st.x, st.y, st.z};
-        float *vel[3] = {st.vx, st.vy, st.vz};
-        float *velp[3] = {st.vxp, st.vyp, st.vzp};
-        const float hdt2 = 0.5f * dt * dt;
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const float v = vel[d][k];
-            const float vn = euler ? fmaf(dt, a[d], v) : fmaf(2.0f * dt, a[d], velp[d][k]);
-            const float xn = pos[d][k] + fmaf(hdt2, a[d], dt * v);
-            pos[d][k] = xn;
-            velp[d][k] = v;
-            vel[d][k] = vn;
-            ok = ok && isfinite(vn) && isfinite(xn);
-        }
+    float r[3], v[3], rho;
+    if (PACKED) {
+        const float4 p4 = pos4[k], v4 = vel4[k];
+        r[0] = p4.x; r[1] = p4.y; r[2] = p4.z;
+        v[0] = v4.x; v[1] = v4.y; v[2] = v4.z;
+        rho = v4.w;
     }
-    if (!ok) atomicOr(&info->flags, (uint32_t)SPH_S_NONFINITE);
+    const bool upd = k < n0 && t != kGhost;
+    if (upd) {
+        if (!PACKED) rho = st.rho[k];
+        float rn = euler ? fmaf(dt, arho[k], rho) : fmaf(2.0f * dt, arho[k], st.rhop[k]);
+        if ((kp.options & SPH_O_RHO_FLOOR) && t == kBoundary && rn < kp.rho0) rn = kp.rho0;
+        st.rhop[k] = rho;
+        rho = rn;
+        bool ok = isfinite(rn);
+        if (t == kFluid) {
+            const float a[3] = {ax[k], ay[k], az[k]};
+            const float *pos[3] = {st.x, st.y, st.z};
+            const float *vel[3] = {st.vx, st.vy, st.vz};
+            float *velp[3] = {st.vxp, st.vyp, st.vzp};
+            const float hdt2 = 0.5f * dt * dt;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                if (!PACKED) {
+                    r[d] = pos[d][k];
+                    v[d] = vel[d][k];
+                }
+                const float vn = euler ? fmaf(dt, a[d], v[d]) : fmaf(2.0f * dt, a[d], velp[d][k]);
+                const float xn = r[d] + fmaf(hdt2, a[d], dt * v[d]);
+                velp[d][k] = v[d];
+                r[d] = xn;
+                v[d] = vn;
+                ok = ok && isfinite(vn) && isfinite(xn);
+            }
+            if (!PACKED) {
+                st.x[k] = r[0]; st.y[k] = r[1]; st.z[k] = r[2];
+                st.vx[k] = v[0]; st.vy[k] = v[1]; st.vz[k] = v[2];
+            }
+        }
+        if (!PACKED) st.rho[k] = rho;
+        if (!ok) atomicOr(&info->flags, (uint32_t)SPH_S_NONFINITE);
+    }
+    if (PACKED) {
+        st.x[k] = r[0]; st.y[k] = r[1]; st.z[k] = r[2];
+        st.vx[k] = v[0]; st.vy[k] = v[1]; st.vz[k] = v[2];
+        st.rho[k] = rho;
+    }
 }
 
 // Symplectic variant (SPH_O_SYMPLECTIC, not in the paper): a kick-drift
@@ -155,11 +184,16 @@ hipError_t launch_sym_full(sph_ctx *c, const sph_soa &st, const float *ax, const
 
 hipError_t launch_update(sph_ctx *c, const sph_soa &st, const float *ax, const float *ay,
                          const float *az, const float *arho, uint32_t n, uint64_t step,
-                         hipStream_t s) {
+                         hipStream_t s, bool packed) {
     const int E = c->kp.euler_every;
     const int euler = E > 0 ? (step % (uint64_t)E == 0) : (step == 0);
-    hipLaunchKernelGGL(k_verlet, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, st,
-                       ax, ay, az, arho, c->info, euler);
+    const dim3 grid(n == 0 ? 1 : (n + 255) / 256);
+    if (packed)
+        hipLaunchKernelGGL(k_verlet<true>, grid, dim3(256), 0, s, c->kp, st, ax, ay, az, arho,
+                           c->pos4, c->vel4, n, c->info, euler);
+    else
+        hipLaunchKernelGGL(k_verlet<false>, grid, dim3(256), 0, s, c->kp, st, ax, ay, az, arho,
+                           c->pos4, c->vel4, n, c->info, euler);
     return hipGetLastError();
 }
 

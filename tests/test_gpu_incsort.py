@@ -151,3 +151,46 @@ def test_unrelated_state_on_the_same_context():
     movers, merged = ctx.sort_stats()
     assert merged
     _check(ctx, p, small, out, m)
+
+
+@pytest.mark.parametrize("j", [CAP, CAP + 1, 9000])
+def test_expected_merge_with_many_movers(j):
+    """After a sort that had a previous one and few movers, the next sort
+    launches the merge only; with more than 8192 movers the plan then sorts
+    them in global memory itself. Moved as in the limit test; bits equal."""
+    case = cases.perturb(cases.case_c1(), 10)
+    p, n = case.params, case.n
+    announce(f"expected merge, j={j} n={n}")
+    ctx = sph.Context(p, n)
+    srt = _sort(ctx, case.state, n).to_numpy(n)
+    _sort(ctx, srt, n)  # a previous sort and no movers: the next sort expects the merge
+    assert ctx.sort_stats() == (0, True)
+    st = {k: v.copy() for k, v in srt.items()}
+    fluid = np.nonzero(st["type"] == cases.FLUID)[0]
+    pick = np.random.default_rng(j + 3).choice(fluid, j, replace=False)
+    st["x"][pick] = (st["x"][pick].astype(np.float64) + 3.0 * p["h"]).astype(np.float32)
+    out = _sort(ctx, st, n)
+    assert ctx.sort_stats() == (j, True)
+    _check(ctx, p, st, out, n)
+
+
+def test_expected_merge_then_unrelated_state():
+    """The merge expected, then a reversed copy (every particle moves): the
+    plan sorts all of them itself; the sort after it lets the plan choose
+    again (the radix passes for a second reversed copy)."""
+    case = cases.perturb(cases.case_c1(), 11)
+    p, n = case.params, case.n
+    announce(f"expected merge, unrelated state n={n}")
+    ctx = sph.Context(p, n)
+    srt = _sort(ctx, case.state, n).to_numpy(n)
+    _sort(ctx, srt, n)
+    rev = {k: v[::-1].copy() for k, v in srt.items()}
+    out = _sort(ctx, rev, n)
+    movers, merged = ctx.sort_stats()
+    assert merged and movers > CAP
+    _check(ctx, p, rev, out, n)
+    rev2 = {k: v[::-1].copy() for k, v in out.to_numpy(n).items()}
+    out2 = _sort(ctx, rev2, n)
+    movers, merged = ctx.sort_stats()
+    assert not merged and movers > CAP
+    _check(ctx, p, rev2, out2, n)
