@@ -119,9 +119,10 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
     const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
     const float hinv2 = -0.5f * kp.inv_h;
     const float eta2 = kp.eta2, h = kp.h;
-    // Pi_ij = kvis (s_i^2 - s_i s_j + s_j^2) vr / (r^2 + eta^2)
-    const float kvis = -kp.alpha * kp.h * kp.c0 * kp.inv_rho0;
-    const float si2 = si * si;
+    // Pi_ij = kvis (s_i^2 - s_i s_j + s_j^2) vr / (r^2 + eta^2) with s = rho/rho0,
+    // evaluated as kvis2 (rho_i^2 - rho_i rho_j + rho_j^2) vr / (r^2 + eta^2)
+    const float kvis2 = -kp.alpha * kp.h * kp.c0 * kp.inv_rho0 * kp.inv_rho0 * kp.inv_rho0;
+    const float rhoi2 = rhoi * rhoi;
 
     auto pair = [&](const v4f pj, const v4f vj) {
         const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
@@ -145,13 +146,13 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
         // mu = h vr / (r^2 + eta^2) and the viscous term -alpha cbar mu /
         // rhobar with cbar = c0 (s_i^3 + s_j^3) / 2, rhobar = rho0 (s_i + s_j) / 2:
         // (s_i^3 + s_j^3) / (s_i + s_j) = s_i^2 - s_i s_j + s_j^2, so one
-        // reciprocal serves both; h (in nu) and -alpha c0 h / rho0 (in the
-        // force factor) are applied outside the sums
+        // reciprocal serves both; h (in nu) and -alpha c0 h / rho0^3 (in the
+        // force factor) are applied outside the sums. vR has the sign of vr:
+        // min(vR, 0) is the approaching-pair switch (Pi = 0 when vr >= 0).
         const float vR = vr * __builtin_amdgcn_rcpf(r2 + eta2);
         nu = fmaxf(nu, fabsf(vR));  // |mu| / h
-        const float sj = vj.w * kp.inv_rho0;
-        const float visc = vr < 0.0f ? fmaf(sj, sj - si, si2) * vR : 0.0f;  // Pi / kvis
-        const float f = fmaf(kvis, visc, Pi + pj.w) * F;
+        const float visc = fmaf(vj.w, vj.w - rhoi, rhoi2) * fminf(vR, 0.0f);  // Pi / kvis2
+        const float f = fmaf(kvis2, visc, Pi + pj.w) * F;
         axs = fmaf(f, dx, axs);
         ays = fmaf(f, dy, ays);
         azs = fmaf(f, dz, azs);

@@ -19,6 +19,11 @@ __global__ __launch_bounds__(256) void k_keys(KParams kp, const float *__restric
     vals[i] = (int32_t)i;
 }
 
+// One radix tile per block, with twice the threads of the radix kernels (more
+// waves in flight for the loads; the tile and its mask words are the same).
+constexpr int kKeysThreads = 2 * kSortThreads;
+constexpr int kKeysItems = kSortTile / kKeysThreads;
+
 // Keys fused with the digit histogram of the first radix pass (one radix
 // tile per block, as k_radix_hist) and with the mover flags of the
 // incremental sort: particle i is a mover when i >= nprev or its key differs
@@ -27,21 +32,21 @@ __global__ __launch_bounds__(256) void k_keys(KParams kp, const float *__restric
 // the tile; per tile the mover count, the smallest and largest key, and its
 // movers' (key, index) in index order at the tile's own place of
 // (segk, segi).
-__global__ __launch_bounds__(kSortThreads) void k_keys_move(
+__global__ __launch_bounds__(kKeysThreads) void k_keys_move(
     KParams kp, const float *__restrict__ x, const float *__restrict__ y,
     const float *__restrict__ z, const uint8_t *__restrict__ type, uint32_t n, uint32_t ntiles,
     uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,
     const uint32_t *__restrict__ prev, uint32_t nprev, unsigned long long *__restrict__ mmask,
     uint32_t *__restrict__ mwpre, uint32_t *__restrict__ mcnt, uint32_t *__restrict__ segk,
     uint32_t *__restrict__ segi, uint2 *__restrict__ mtile) {
-    constexpr int NW = kSortThreads / 64;
+    constexpr int NW = kKeysThreads / 64;
     constexpr int WPT = kSortTile / 64;  // mask words per tile
     static_assert(WPT <= 64, "one wave scans a tile's words");
     __shared__ uint32_t h[256];
     __shared__ uint32_t s_wc[WPT];
     __shared__ uint32_t s_kmin, s_kmax;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    h[tid] = 0;
+    if (tid < 256) h[tid] = 0;
     if (tid == 0) {
         s_kmin = 0xffffffffu;
         s_kmax = 0u;
@@ -50,12 +55,12 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_move(
     const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
     // all of the thread's loads first (clamped index: in bounds for every
     // lane), then the keys
-    float px[kSortItems], py[kSortItems], pz[kSortItems];
-    uint8_t pt[kSortItems];
-    uint32_t pk[kSortItems];
+    float px[kKeysItems], py[kKeysItems], pz[kKeysItems];
+    uint8_t pt[kKeysItems];
+    uint32_t pk[kKeysItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; r++) {
-        const uint32_t idx = base + r * kSortThreads + tid;
+    for (int r = 0; r < kKeysItems; r++) {
+        const uint32_t idx = base + r * kKeysThreads + tid;
         const uint32_t ic = idx < n ? idx : n - 1u;
         px[r] = x[ic];
         py[r] = y[ic];
@@ -63,13 +68,13 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_move(
         pt[r] = type[ic];
         pk[r] = nprev ? prev[idx < nprev ? idx : nprev - 1u] : 0u;
     }
-    uint32_t key[kSortItems];
-    unsigned long long bm[kSortItems];
+    uint32_t key[kKeysItems];
+    unsigned long long bm[kKeysItems];
     const unsigned long long lt = (1ull << lane) - 1ull;
     uint32_t kmin = 0xffffffffu, kmax = 0u;
 #pragma unroll
-    for (int r = 0; r < kSortItems; r++) {
-        const uint32_t idx = base + r * kSortThreads + tid;
+    for (int r = 0; r < kKeysItems; r++) {
+        const uint32_t idx = base + r * kKeysThreads + tid;
         const bool valid = idx < n;
         key[r] = cell_key(kp, px[r], py[r], pz[r], pt[r]);
         if (valid) {
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_move(
         bm[r] = __ballot(valid && (idx >= nprev || key[r] != pk[r]));
         if (lane == 0) {
             s_wc[r * NW + w] = (uint32_t)__popcll(bm[r]);
-            if (base + (uint32_t)(r * kSortThreads + w * 64) < n)
+            if (base + (uint32_t)(r * kKeysThreads + w * 64) < n)
                 mmask[(base >> 6) + (uint32_t)(r * NW + w)] = bm[r];
         }
     }
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_move(
         atomicMax(&s_kmax, kmax);
     }
     __syncthreads();
-    hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
+    if (tid < 256) hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
     if (tid == 0) mtile[blockIdx.x] = make_uint2(s_kmin, s_kmax);
     if (tid < 64) {  // word r * NW + w covers particles base + 64 (r * NW + w) + [0, 64)
         const uint32_t v = tid < WPT ? s_wc[tid] : 0u;
@@ -109,11 +114,11 @@ __global__ __launch_bounds__(kSortThreads) void k_keys_move(
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; r++) {
+    for (int r = 0; r < kKeysItems; r++) {
         if ((bm[r] >> lane) & 1ull) {
             const uint32_t at = base + s_wc[r * NW + w] + (uint32_t)__popcll(bm[r] & lt);
             segk[at] = key[r];
-            segi[at] = base + r * kSortThreads + tid;
+            segi[at] = base + r * kKeysThreads + tid;
         }
     }
 }
@@ -951,7 +956,7 @@ hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_
     uint32_t *tmpk = (passes & 1) ? xk : segk, *tmpi = (passes & 1) ? xi : segi;
     if (n > 0) {
         const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
-        hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kSortThreads), 0, s, c->kp, in.x,
+        hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kKeysThreads), 0, s, c->kp, in.x,
                            in.y, in.z, in.type, n, ntiles, c->keys_a, c->hist, c->keys_sorted,
                            nprev, c->mmask, c->mwpre, c->mcnt, segk, segi, c->mtile);
         hipLaunchKernelGGL(k_move_plan, dim3(1), dim3(kPlanThreads), 0, s, n, ntiles, passes, segk,
