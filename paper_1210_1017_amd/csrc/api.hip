@@ -282,14 +282,17 @@ static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n
     // the sorted keys and cell tables of the previous sort (any path) are the
     // reference of the incremental sort; without one every particle moves
     const uint32_t nprev = c->have_sort ? c->sorted_n : 0u;
-    // the last mover plan that has run (the host does not wait for it) saw a
+    // the input is the state the last plain sort wrote (a time loop), and the
+    // last mover plan that has run (the host does not wait for it) saw a
     // previous sort and few movers: expect few again and launch only the
     // merge (which still sorts any number of movers, slowly); else launch
     // the radix passes too and let the plan choose
     const unsigned long long fb = __atomic_load_n(c->fb, __ATOMIC_RELAXED);
-    const bool expect = nprev > 0 && (fb & 1ull) && (fb >> 1) <= kIncCap;
+    const bool expect = nprev > 0 && c->last_path == 0 && in->x == c->last_out_x && (fb & 1ull) &&
+                        (fb >> 1) <= kIncCap;
     hipError_t e = sort_state(c, *in, *out, n, nprev, expect, skip_rv, s);
     if (e != hipSuccess) return hip_fail(c, e, "sort step");
+    c->last_out_x = out->x;
     c->sorted_n = n;
     c->have_sort = true;
     c->have_dt = false;

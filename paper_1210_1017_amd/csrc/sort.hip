@@ -431,13 +431,15 @@ constexpr uint32_t kNoSplit = 0xffffffffu;
 
 // One round of a stable LSD radix pass over (sk, si)[c0, c0 + 1024) into
 // (dk, di) (LDS or global): ranks among the wave's lanes with the same digit
-// from 8 ballots, per-(wave, digit) counts stamped with the round so that
-// earlier rounds' entries read as zero, one prefix per digit over the waves
-// on top of the running digit starts s_base.
+// from 8 ballots, per-(wave, digit) counts stamped (high half) with the
+// round, one prefix per digit over the waves. The prefixes overwrite every
+// entry and are relative to the round's start of the digit (below 1024, so
+// their high half is 0 and never a stamp); that start is kept in s_b0 and
+// the running digit starts in s_base advance by the round's counts.
 __device__ __forceinline__ void lsd_round(const uint32_t *sk, const uint32_t *si, uint32_t *dk,
                                           uint32_t *di, uint32_t m, uint32_t c0, int shift,
                                           uint32_t stamp, uint32_t (*s_wc)[256],
-                                          uint32_t *s_base) {
+                                          uint32_t *s_base, uint32_t *s_b0) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t k = c0 + (uint32_t)tid;
     const bool valid = k < m;
@@ -461,17 +463,19 @@ __device__ __forceinline__ void lsd_round(const uint32_t *sk, const uint32_t *si
             const uint32_t e = s_wc[q][tid];
             c[q] = (e >> 16) == stamp ? (e & 0xffffu) : 0u;
         }
-        uint32_t run = s_base[tid];
+        uint32_t run = 0;
 #pragma unroll
         for (int q = 0; q < kPlanWaves; q++) {
             s_wc[q][tid] = run;
             run += c[q];
         }
-        s_base[tid] = run;
+        const uint32_t b0 = s_base[tid];
+        s_b0[tid] = b0;
+        s_base[tid] = b0 + run;
     }
     __syncthreads();
     if (valid) {
-        const uint32_t pos = s_wc[w][d] + rank;
+        const uint32_t pos = s_b0[d] + s_wc[w][d] + rank;
         dk[pos] = key;
         di[pos] = idx;
     }
@@ -483,8 +487,9 @@ __device__ __forceinline__ void lsd_round(const uint32_t *sk, const uint32_t *si
 // holds the result.
 __device__ __forceinline__ int lsd_sort(uint32_t *k0, uint32_t *i0, uint32_t *k1, uint32_t *i1,
                                         uint32_t m, int passes, uint32_t (*s_wc)[256],
-                                        uint32_t *s_base, uint32_t (*s_hist)[256],
-                                        uint32_t *s_w, uint32_t *stamp) {
+                                        uint32_t *s_base, uint32_t *s_b0,
+                                        uint32_t (*s_hist)[256], uint32_t *s_w,
+                                        uint32_t *stamp) {
     const int tid = threadIdx.x;
     int src = 0;
     for (int p = 0; p < passes; p++) {
@@ -500,7 +505,7 @@ __device__ __forceinline__ int lsd_sort(uint32_t *k0, uint32_t *i0, uint32_t *k1
                 __syncthreads();
                 st = ++*stamp & 0xffffu;
             }
-            lsd_round(sk, si, dk, di, m, c0, 8 * p, st, s_wc, s_base);
+            lsd_round(sk, si, dk, di, m, c0, 8 * p, st, s_wc, s_base, s_b0);
         }
         src ^= 1;
     }
@@ -598,6 +603,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
     __shared__ uint32_t s_i[2][kIncCap];
     __shared__ uint32_t s_wc[kPlanWaves][256];
     __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_b0[256];
     __shared__ uint32_t s_w[kPlanWaves];
     __shared__ uint32_t s_hist[4][256];  // digit counts of every pass
     __shared__ uint32_t s_big;  // a tile with more movers than one thread copies was seen
@@ -662,8 +668,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
             for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
         }
         __syncthreads();
-        const int r = lsd_sort(s_k[0], s_i[0], s_k[1], s_i[1], m, passes, s_wc, s_base, s_hist,
-                               s_w, &stamp);
+        const int r = lsd_sort(s_k[0], s_i[0], s_k[1], s_i[1], m, passes, s_wc, s_base, s_b0,
+                               s_hist, s_w, &stamp);
         for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {
             outk[k] = s_k[r][k];
             outi[k] = s_i[r][k];
@@ -682,7 +688,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
             for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
         }
         __syncthreads();
-        lsd_sort(ak, ai, bk, bi, m, passes, s_wc, s_base, s_hist, s_w, &stamp);
+        lsd_sort(ak, ai, bk, bi, m, passes, s_wc, s_base, s_b0, s_hist, s_w, &stamp);
         fk = outk;
         fi = outi;
     }

@@ -85,6 +85,7 @@ struct sph_ctx {
     // (there was a previous sort); read without waiting to choose the kernels
     // of the next sort
     unsigned long long *fb = nullptr, *fb_dev = nullptr;
+    const float *last_out_x = nullptr;  // x array the last plain sort wrote
     uint32_t *digit_tot = nullptr;  // 256
     uint32_t *cell_begin = nullptr, *cell_end = nullptr;
     float4 *pos4 = nullptr, *vel4 = nullptr;  // packed (x,y,z,p/rho^2), (vx,vy,vz,rho)

@@ -153,44 +153,92 @@ def test_unrelated_state_on_the_same_context():
     _check(ctx, p, small, out, m)
 
 
+def _write(ds, st):
+    """Overwrite the first n particles of a device state in place."""
+    n = st["x"].shape[0]
+    for k in sph.SOA_FIELDS:
+        ds.t[k][:n].copy_(torch.from_numpy(np.ascontiguousarray(st[k])))
+    torch.cuda.synchronize()
+
+
+def _primed(case):
+    """A context whose last sort read the state its previous sort wrote and
+    found no movers: the next sort of that output buffer expects the merge
+    and launches it alone. Returns (ctx, the buffer the last sort wrote, a
+    spare buffer)."""
+    p, n = case.params, case.n
+    ctx = sph.Context(p, n)
+    a = sph.DeviceState.from_numpy(case.state, capacity=n)
+    b, c = sph.DeviceState.empty(n), sph.DeviceState.empty(n)
+    ctx.sort(a, b, n)
+    ctx.sort(b, c, n)
+    torch.cuda.synchronize()
+    assert ctx.sort_stats() == (0, True)
+    return ctx, c, a
+
+
 @pytest.mark.parametrize("j", [CAP, CAP + 1, 9000])
 def test_expected_merge_with_many_movers(j):
-    """After a sort that had a previous one and few movers, the next sort
-    launches the merge only; with more than 8192 movers the plan then sorts
-    them in global memory itself. Moved as in the limit test; bits equal."""
+    """The sort of the buffer the last sort wrote, after a sort with a
+    previous one and no movers, launches the merge only; with more than 8192
+    movers the plan then sorts them in global memory itself. j particles
+    moved in place as in the limit test; bits equal to the oracle's."""
     case = cases.perturb(cases.case_c1(), 10)
     p, n = case.params, case.n
     announce(f"expected merge, j={j} n={n}")
-    ctx = sph.Context(p, n)
-    srt = _sort(ctx, case.state, n).to_numpy(n)
-    _sort(ctx, srt, n)  # a previous sort and no movers: the next sort expects the merge
-    assert ctx.sort_stats() == (0, True)
-    st = {k: v.copy() for k, v in srt.items()}
+    ctx, last, spare = _primed(case)
+    st = last.to_numpy(n)
     fluid = np.nonzero(st["type"] == cases.FLUID)[0]
     pick = np.random.default_rng(j + 3).choice(fluid, j, replace=False)
     st["x"][pick] = (st["x"][pick].astype(np.float64) + 3.0 * p["h"]).astype(np.float32)
-    out = _sort(ctx, st, n)
+    _write(last, st)
+    ctx.sort(last, spare, n)
+    torch.cuda.synchronize()
     assert ctx.sort_stats() == (j, True)
-    _check(ctx, p, st, out, n)
+    _check(ctx, p, st, spare, n)
 
 
 def test_expected_merge_then_unrelated_state():
-    """The merge expected, then a reversed copy (every particle moves): the
-    plan sorts all of them itself; the sort after it lets the plan choose
-    again (the radix passes for a second reversed copy)."""
+    """The merge expected, then the output buffer overwritten with a reversed
+    copy (every particle moves): the plan sorts all of them itself; the next
+    sort of the output, reversed again, lets the plan choose (the radix
+    passes); a new input buffer is never expected to merge."""
     case = cases.perturb(cases.case_c1(), 11)
     p, n = case.params, case.n
     announce(f"expected merge, unrelated state n={n}")
-    ctx = sph.Context(p, n)
-    srt = _sort(ctx, case.state, n).to_numpy(n)
-    _sort(ctx, srt, n)
-    rev = {k: v[::-1].copy() for k, v in srt.items()}
-    out = _sort(ctx, rev, n)
+    ctx, last, spare = _primed(case)
+    rev = {k: v[::-1].copy() for k, v in last.to_numpy(n).items()}
+    _write(last, rev)
+    ctx.sort(last, spare, n)
+    torch.cuda.synchronize()
     movers, merged = ctx.sort_stats()
     assert merged and movers > CAP
-    _check(ctx, p, rev, out, n)
-    rev2 = {k: v[::-1].copy() for k, v in out.to_numpy(n).items()}
-    out2 = _sort(ctx, rev2, n)
+    _check(ctx, p, rev, spare, n)
+    rev2 = {k: v[::-1].copy() for k, v in spare.to_numpy(n).items()}
+    _write(spare, rev2)
+    ctx.sort(spare, last, n)
+    torch.cuda.synchronize()
     movers, merged = ctx.sort_stats()
     assert not merged and movers > CAP
-    _check(ctx, p, rev2, out2, n)
+    _check(ctx, p, rev2, last, n)
+    # a fresh buffer with the sorted state: no expectation, the plan merges
+    out = _sort(ctx, last.to_numpy(n), n)
+    assert ctx.sort_stats() == (0, True)
+
+
+def test_expected_merge_of_every_particle_at_full_size():
+    """The same at 1.47M particles (the obstacle dam break): a reversed copy
+    written over the output buffer makes all 1,472,392 particles movers, far
+    beyond the 16-bit halves the plan's per-round tables carry; the plan's
+    global sort must still give the oracle's bits."""
+    case = cases.case_c2()
+    p, n = case.params, case.n
+    announce(f"expected merge of every particle n={n}")
+    ctx, last, spare = _primed(case)
+    rev = {k: v[::-1].copy() for k, v in last.to_numpy(n).items()}
+    _write(last, rev)
+    ctx.sort(last, spare, n)
+    torch.cuda.synchronize()
+    movers, merged = ctx.sort_stats()
+    assert merged and movers > 1 << 16
+    _check(ctx, p, rev, spare, n)
