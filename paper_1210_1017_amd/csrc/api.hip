@@ -196,10 +196,12 @@ int sph_create(const sph_params *p, sph_ctx **out) {
         if (e == hipSuccess) e = hipMalloc((void **)&(ptr), (bytes));   \
     } while (0)
     ALLOC(c->keys_a, cap * 4);
-    ALLOC(c->keys_b, cap * 4);
+    // + 64 B: the mover plan reads a tile's first movers in 16-byte pieces,
+    // up to 11 entries past the last particle of a partial last tile
+    ALLOC(c->keys_b, cap * 4 + 64);
     ALLOC(c->keys_sorted, cap * 4);
     ALLOC(c->vals_a, cap * 4);
-    ALLOC(c->vals_b, cap * 4);
+    ALLOC(c->vals_b, cap * 4 + 64);
     ALLOC(c->perm, cap * 4);
     ALLOC(c->hist, (size_t)256 * c->max_tiles * 4);
     ALLOC(c->mmask, (cap / 64 + 1) * sizeof(unsigned long long));

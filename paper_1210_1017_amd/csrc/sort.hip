@@ -488,14 +488,25 @@ __device__ __forceinline__ void lsd_round(const uint32_t *sk, const uint32_t *si
 __device__ __forceinline__ int lsd_sort(uint32_t *k0, uint32_t *i0, uint32_t *k1, uint32_t *i1,
                                         uint32_t m, int passes, uint32_t (*s_wc)[256],
                                         uint32_t *s_base, uint32_t *s_b0,
-                                        uint32_t (*s_hist)[256], uint32_t *s_w,
-                                        uint32_t *stamp) {
+                                        uint32_t (*s_hist)[256], uint32_t *stamp) {
     const int tid = threadIdx.x;
     int src = 0;
     for (int p = 0; p < passes; p++) {
-        const uint32_t cnt = tid < 256 ? s_hist[p][tid] : 0u;
-        const uint32_t start = block_excl_scan<kPlanThreads>(cnt, s_w);
-        if (tid < 256) s_base[tid] = start;
+        if (tid < 64) {  // digit starts: one wave, 4 digits per lane; the first
+                         // round's barrier orders them before their reads
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                c[e] = s_hist[p][4 * tid + e];
+                sum += c[e];
+            }
+            uint32_t ex = wave_incl_scan(sum) - sum;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                s_base[4 * tid + e] = ex;
+                ex += c[e];
+            }
+        }
         uint32_t *sk = src ? k1 : k0, *si = src ? i1 : i0;
         uint32_t *dk = src ? k0 : k1, *di = src ? i0 : i1;
         for (uint32_t c0 = 0; c0 < m; c0 += kPlanThreads) {
@@ -629,20 +640,28 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
         if (t < ntiles) mcnt[t] = pre;
         if (fits && v > kSmall) s_big = 1u;
         if (fits && v > 0u && v <= kSmall) {
-            const uint32_t sb = t * (uint32_t)kSortTile;
-            uint32_t kk[kSmall], ii[kSmall];
+            // 16-byte loads from the tile's segment (8 KB aligned), only as
+            // many as hold its movers: one cache line per lane and load
+            const uint4 *gk = (const uint4 *)(segk + t * (uint32_t)kSortTile);
+            const uint4 *gi = (const uint4 *)(segi + t * (uint32_t)kSortTile);
+            uint4 kk[kSmall / 4], ii[kSmall / 4];
 #pragma unroll
-            for (uint32_t u = 0; u < kSmall; u++) {
-                const uint32_t j = u < v ? u : v - 1u;
-                kk[u] = segk[sb + j];
-                ii[u] = segi[sb + j];
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kSmall; u++)
-                if (u < v) {
-                    s_k[0][pre + u] = kk[u];
-                    s_i[0][pre + u] = ii[u];
+            for (uint32_t u = 0; u < kSmall / 4; u++)
+                if (4u * u < v) {
+                    kk[u] = gk[u];
+                    ii[u] = gi[u];
                 }
+#pragma unroll
+            for (uint32_t u = 0; u < kSmall / 4; u++) {
+                const uint32_t kv[4] = {kk[u].x, kk[u].y, kk[u].z, kk[u].w};
+                const uint32_t iv[4] = {ii[u].x, ii[u].y, ii[u].z, ii[u].w};
+#pragma unroll
+                for (uint32_t e = 0; e < 4; e++)
+                    if (4u * u + e < v) {
+                        s_k[0][pre + 4u * u + e] = kv[e];
+                        s_i[0][pre + 4u * u + e] = iv[e];
+                    }
+            }
         }
     }
     const uint32_t m = running;  // the same in every thread
@@ -669,7 +688,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
         }
         __syncthreads();
         const int r = lsd_sort(s_k[0], s_i[0], s_k[1], s_i[1], m, passes, s_wc, s_base, s_b0,
-                               s_hist, s_w, &stamp);
+                               s_hist, &stamp);
         for (uint32_t k = (uint32_t)tid; k < m; k += kPlanThreads) {
             outk[k] = s_k[r][k];
             outi[k] = s_i[r][k];
@@ -688,7 +707,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
             for (int p = 0; p < passes; p++) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
         }
         __syncthreads();
-        lsd_sort(ak, ai, bk, bi, m, passes, s_wc, s_base, s_b0, s_hist, s_w, &stamp);
+        lsd_sort(ak, ai, bk, bi, m, passes, s_wc, s_base, s_b0, s_hist, &stamp);
         fk = outk;
         fi = outi;
     }
