@@ -56,12 +56,12 @@ enum {
 enum {
     SPH_S_NONFINITE = 1u << 0,    /* non-finite position/velocity/density after an update */
     SPH_S_DT = 1u << 1,           /* dt not finite or not positive                        */
-    SPH_S_RUN_OVERFLOW = 1u << 2, /* cell + offset interaction or surrogate rows: a
-                                     3-cell neighbour run held more than 4096 particles
-                                     (their 12-bit run offsets): the excess was skipped,
-                                     results of that call invalid. The plain interaction
-                                     addresses candidates by full indices and searches
-                                     any run completely                                   */
+    SPH_S_RUN_OVERFLOW = 1u << 2, /* surrogate rows: a 3-cell neighbour run held more
+                                     than 4096 particles (their 12-bit run offsets): the
+                                     excess was skipped, results of that call invalid.
+                                     The plain and the cell + offset interactions
+                                     address candidates by full indices and search any
+                                     run completely                                       */
     SPH_S_EXCLUDED = 1u << 3,     /* some particles lie outside the cell grid (label 3)   */
     SPH_S_NN_RANGE = 1u << 4,     /* surrogate: a result was non-finite or its density
                                      left the allowed band (sph_nn_apply, sph_nn_advance) */
@@ -121,7 +121,8 @@ enum {
 
 /* Feature bits of sph_params.features. */
 enum {
-    SPH_F_CELL = 1u << 0, /* cell + offset position path (sph_cstate, sph_c*)  */
+    SPH_F_CELL = 1u << 0, /* cell + offset position path (sph_cstate, sph_c*);
+                             capacity below 2^27                                */
     SPH_F_FP64 = 1u << 1, /* FP64 reference path (sph_dstate, sph_d*)          */
     SPH_F_SURROGATE = 1u << 2 /* rows, outputs and rates of sph_nn_advance:
                                  capacity x (SPH_NN_IN x 2 + 32) bytes         */

@@ -127,6 +127,9 @@ int sph_create(const sph_params *p, sph_ctx **out) {
             return fail(nullptr, SPH_E_INVALID_ARG, "bad grid or gravity on axis %d", a);
     if (p->capacity < 1 || p->capacity >= (1u << 28))
         return fail(nullptr, SPH_E_INVALID_ARG, "capacity must be in [1, 2^28)");
+    if ((p->features & SPH_F_CELL) && p->capacity >= (1u << 27))
+        return fail(nullptr, SPH_E_INVALID_ARG,
+                    "the cell path lists neighbours as index << 5: capacity must be < 2^27");
     const uint64_t ncells = (uint64_t)p->ncell[0] * p->ncell[1] * p->ncell[2];
     const int bits = cell_bits_for(ncells);
     if (bits > 30)

@@ -180,157 +180,260 @@ hipError_t launch_gather_cell(sph_ctx *c, const sph_cstate &in, const sph_cstate
 }
 
 // Interaction on cell + offset positions. The structure is that of the plain
-// kernel (lane per particle, 9 contiguous z-runs, support test into a
-// per-lane LDS list, pair terms for the listed neighbours); what differs is
-// the separation: r_ij = (o_i + s) - o_j with s = (c_i - c_j) cs, the cell
-// difference being the run's (x, y) column offset and, along z, which of the
-// run's three cells j lies in (from the run's cell boundaries). The list is
-// flushed by the whole wave at run boundaries once any lane passes
-// kCCap - kCSlack entries.
-constexpr int kCCap = 64;
-constexpr int kCSlack = 24;
-constexpr int kCUnroll = 8;
-constexpr int kCSlots = kCCap + kCUnroll;
+// kernel (lane per particle, 9 contiguous z-runs, the candidates of each
+// column offset staged in LDS, FP32 support test into 32-bit hit masks in a
+// per-lane LDS list, four pairs per step of the compute phase); what
+// differs is the separation: r_ij = (o_i + s) - o_j with s = (c_i - c_j) cs,
+// the cell difference being the run's (x, y) column offset and, along z,
+// which of the run's three cells j lies in (from the run's cell
+// boundaries). A mask is split by those cells, so a list entry holds one
+// shift: (j << 5 | tag, mask) with tag = 3 column + z cell indexing the
+// shift table.
+constexpr int kCEnt = 19;       // list slots per lane (one for the sentinel)
+constexpr int kCUnroll = 8;     // candidates tested per group
+constexpr int kCStage = 768;    // staged candidate positions per column offset
+constexpr int kCSlack = 6;      // converged flush when a lane cannot take this many more
 
-__global__ __launch_bounds__(kInteractThreads, 2) void k_interact_cell(
-    KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4, uint32_t n,
-    const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
-    const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend,
-    DevInfo *__restrict__ info, float *__restrict__ oax, float *__restrict__ oay,
-    float *__restrict__ oaz, float *__restrict__ orho, float *__restrict__ opress,
-    float *__restrict__ onu, uint32_t *__restrict__ onpair) {
-    __shared__ uint16_t s_list[kCSlots][kInteractThreads];
-    __shared__ uint32_t s_base[9][kInteractThreads];
-    __shared__ uint32_t s_zb[9][kInteractThreads];  // run-relative starts of cells z and z+1
-    __shared__ double s_rdt[kInteractThreads / 64];
-    __shared__ uint32_t s_rnp[kInteractThreads / 64];
-    __shared__ uint32_t s_rnc[kInteractThreads / 64];
+__global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void
+k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4,
+                uint32_t n, const uint8_t *__restrict__ type, const uint32_t *__restrict__ sk,
+                const uint32_t *__restrict__ cbeg, const uint32_t *__restrict__ cend,
+                DevInfo *__restrict__ info, float *__restrict__ oax, float *__restrict__ oay,
+                float *__restrict__ oaz, float *__restrict__ orho, float *__restrict__ opress,
+                float *__restrict__ onu, uint32_t *__restrict__ onpair) {
+    constexpr int kWaves = kInteractThreads / 64;
+    __shared__ uint2 s_ent[kCEnt][kInteractThreads];
+    __shared__ float4 s_stage[kCStage + kCUnroll];
+    __shared__ float4 s_sh[27];  // (x, y, z) shift of tag 3 col + zc
+    __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+    __shared__ double s_rdt[kWaves];
+    __shared__ uint32_t s_rnp[kWaves];
+    __shared__ uint32_t s_rnc[kWaves];
 
     const int tid = threadIdx.x;
+    const float cs = 2.0f * kp.h;
+    if (tid < 27) {
+        const int col = tid / 3, zc = tid % 3;
+        s_sh[tid] = make_float4((float)(1 - col / 3) * cs, (float)(1 - col % 3) * cs,
+                                (float)(1 - zc) * cs, 0.0f);
+    }
     const uint32_t n0 = info->n_label[0];
     const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kInteractThreads + tid;
     const bool inrange = i < n0;
     const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;
+    const bool act = ti != kGhost;
     double dtmin = INFINITY;
     uint32_t npair = 0, ncand = 0;
-    const float cs = 2.0f * kp.h;
 
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), vi = pi;
     if (inrange) {
-        const float4 pi = pos4[i], vi = vel4[i];
-        const float rhoi = vi.w, Pi = pi.w;
-        const float si = rhoi * kp.inv_rho0;
-        const float si3 = si * si * si;
-        float axs = 0.f, ays = 0.f, azs = 0.f, drho = 0.f, nu = 0.f;
-        if (ti != kGhost) {
-            const __amdgpu_buffer_rsrc_t rp =
-                __builtin_amdgcn_make_buffer_rsrc((void *)pos4, 0, (int)(n * 16u), kRsrc3);
-            const __amdgpu_buffer_rsrc_t rv =
-                __builtin_amdgcn_make_buffer_rsrc((void *)vel4, 0, (int)(n * 16u), kRsrc3);
-            const uint32_t cell = sk[i] & kp.cell_mask;
-            const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
-            const int cz = (int)(cell % ncz);
-            const int cy = (int)((cell / ncz) % ncy);
-            const int cx = (int)(cell / (ncz * ncy));
-            const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
-            const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
-            const float hinv2 = -0.5f * kp.inv_h;
-            const float eta2 = kp.eta2, h = kp.h;
-            const float kvis = -kp.alpha * kp.h * kp.c0;
-            const float zm = pi.z + cs, zp = pi.z - cs;  // i's z relative to cells z-1, z+1
+        pi = pos4[i];
+        vi = vel4[i];
+    }
+    const float rhoi = vi.w, Pi = pi.w;
+    float axs = 0.f, ays = 0.f, azs = 0.f, drho = 0.f, nu = 0.f;
+    const __amdgpu_buffer_rsrc_t rp =
+        __builtin_amdgcn_make_buffer_rsrc((void *)pos4, 0, (int)(n * 16u), kRsrc3);
+    const __amdgpu_buffer_rsrc_t rv =
+        __builtin_amdgcn_make_buffer_rsrc((void *)vel4, 0, (int)(n * 16u), kRsrc3);
+    const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
+    int cx = 0, cy = 0, cz = 0;
+    if (act) {
+        const uint32_t cell = sk[i] & kp.cell_mask;
+        cz = (int)(cell % ncz);
+        cy = (int)((cell / ncz) % ncy);
+        cx = (int)(cell / (ncz * ncy));
+    }
+    const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
+    const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
+    const float hinv2 = -0.5f * kp.inv_h;
+    const float eta2 = kp.eta2;
+    // Pi_ij as in the plain kernel: kvis2 (rho_i^2 - rho_i rho_j + rho_j^2) vr / (r^2 + eta^2)
+    const float kvis2 = -kp.alpha * kp.h * kp.c0 * kp.inv_rho0 * kp.inv_rho0 * kp.inv_rho0;
+    const float rhoi2 = rhoi * rhoi;
+    const float zm = pi.z + cs, zp = pi.z - cs;  // i's z relative to the cells z-1, z+1
 
-            auto flush = [&](int cnt) {
-#pragma unroll 4
-                for (int k = 0; k < cnt; k++) {
-                    const uint32_t e = s_list[k][tid];
-                    const uint32_t col = e >> kRunBits, kk = e & kRunMax;
-                    const uint32_t j = s_base[col][tid] + kk;
-                    const uint32_t zb = s_zb[col][tid];
-                    const float shx = (float)(1 - (int)(col / 3)) * cs;
-                    const float shy = (float)(1 - (int)(col % 3)) * cs;
-                    const float ziz = kk < (zb & 0xffffu) ? zm : (kk < (zb >> 16) ? pi.z : zp);
-                    const v4f pj = __builtin_amdgcn_raw_buffer_load_b128(rp, j * 16u, 0, 0);
-                    const v4f vj = __builtin_amdgcn_raw_buffer_load_b128(rv, j * 16u, 0, 0);
-                    const float dx = (pi.x + shx) - pj.x, dy = (pi.y + shy) - pj.y, dz = ziz - pj.z;
-                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);
-                    const float F = t * t * t;
-                    const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
-                    const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
-                    drho = fmaf(F, vr, drho);
-                    const float rs = rhoi + vj.w;
-                    const float R = __builtin_amdgcn_rcpf((r2 + eta2) * rs);
-                    const float vR = vr * R;
-                    const float mu = (h * rs) * vR;
-                    nu = fmaxf(nu, fabsf(mu));
-                    const float sj = vj.w * kp.inv_rho0;
-                    const float visc = vr < 0.0f ? kvis * fmaf(sj * sj, sj, si3) * vR : 0.0f;
-                    const float f = (Pi + pj.w + visc) * F;
-                    axs = fmaf(f, dx, axs);
-                    ays = fmaf(f, dy, ays);
-                    azs = fmaf(f, dz, azs);
-                }
-            };
+    auto pair = [&](const v4f pj, const v4f vj, const float4 sh) {
+        const float dx = (pi.x + sh.x) - pj.x, dy = (pi.y + sh.y) - pj.y, dz = (pi.z + sh.z) - pj.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float t = fmaf(hinv2, __builtin_amdgcn_sqrtf(r2), 1.0f);  // 1 - q/2
+        const float F = t * t * t;
+        const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+        const float vr = fmaf(uz, dz, fmaf(uy, dy, ux * dx));
+        drho = fmaf(F, vr, drho);
+        const float vR = vr * __builtin_amdgcn_rcpf(r2 + eta2);
+        nu = fmaxf(nu, fabsf(vR));  // |mu| / h
+        const float visc = fmaf(vj.w, vj.w - rhoi, rhoi2) * fminf(vR, 0.0f);
+        const float f = fmaf(kvis2, visc, Pi + pj.w) * F;
+        axs = fmaf(f, dx, axs);
+        ays = fmaf(f, dy, ays);
+        azs = fmaf(f, dz, azs);
+    };
 
-            uint16_t *const lp0 = &s_list[0][tid];
-            uint16_t *const lpcap = &s_list[kCCap][tid];
-            uint16_t *lp = lp0;
-            uint32_t listed = 0;
-            for (int col = 0; col < 9; col++) {
-                if (__any(lp > lpcap - (size_t)kCSlack * kInteractThreads)) {
-                    const int cnt = (int)((lp - lp0) / kInteractThreads);
-                    flush(cnt);
-                    listed += cnt;
-                    lp = lp0;
-                }
-                const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
-                uint32_t jb = 0, je = 0, b1 = 0, b2 = 0;
-                if (X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
-                    const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
-                    jb = cbeg[c0 + zlo];
-                    je = cend[c0 + zhi];
-                    b1 = cbeg[c0 + (uint32_t)cz];
-                    b2 = (uint32_t)cz + 1 < ncz ? cbeg[c0 + (uint32_t)cz + 1] : je;
-                }
-                if (je - jb > kRunMax + 1u) {
-                    atomicOr(&info->flags, (uint32_t)SPH_S_RUN_OVERFLOW);
-                    je = jb + kRunMax + 1u;
-                }
-                const uint32_t len = je - jb;
-                const uint32_t kb1 = min(b1 - jb, len), kb2 = min(b2 - jb, len);
-                s_base[col][tid] = jb;
-                s_zb[col][tid] = kb1 | (kb2 << 16);
-                ncand += len;
-                const float pix = pi.x + (float)(1 - col / 3) * cs;
-                const float piy = pi.y + (float)(1 - col % 3) * cs;
-                const uint32_t voff = jb * 16u;
-                for (uint32_t k0 = 0; k0 < len; k0 += kCUnroll) {
-                    v4f q[kCUnroll];
+    // compute phase over the cnt entries of the lane's list holding nhit
+    // set bits; the sentinel (i, the own cell's tag 13, bit 31) after the
+    // last entry stands in for every position past the end (the self pair
+    // adds exactly zero)
+    auto flush = [&](uint32_t cnt, uint32_t nhit) {
+        s_ent[cnt][tid] = make_uint2(i << 5 | 13u, 0x80000000u);
+        uint32_t pk = 0, cb = 0, ce = 0;
+        uint2 nx = s_ent[0][tid];
+        auto draw = [&](uint32_t (&jj)[4], uint32_t (&tt)[4]) {
 #pragma unroll
-                    for (int u = 0; u < kCUnroll; u++)
-                        q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
-#pragma unroll
-                    for (int u = 0; u < kCUnroll; u++) {
-                        const uint32_t kk = k0 + u;
-                        const float ziz = kk < kb1 ? zm : (kk < kb2 ? pi.z : zp);
-                        const float dx = pix - q[u].x, dy = piy - q[u].y, dz = ziz - q[u].z;
-                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        // branch-free append: always written, kept only by a hit
-                        const bool hit = (kk < len) & (r2 < kp.r2max);
-                        *lp = (uint16_t)(((uint32_t)col << kRunBits) + kk);
-                        lp += hit ? kInteractThreads : 0;
-                    }
-                    if (lp >= lpcap) {
-                        const int cnt = (int)((lp - lp0) / kInteractThreads);
-                        flush(cnt);
-                        listed += cnt;
-                        lp = lp0;
-                    }
-                }
+            for (int u = 0; u < 4; u++) {
+                const bool empty = cb == 0u;
+                cb = empty ? nx.y : cb;
+                ce = empty ? nx.x : ce;
+                pk = min(pk + (empty ? 1u : 0u), cnt);
+                nx = s_ent[pk][tid];
+                const uint32_t off = (uint32_t)__builtin_clz(cb);
+                jj[u] = ((ce >> 5) + off) << 4;  // byte offset of j
+                tt[u] = ce & 31u;
+                cb &= 0x7fffffffu >> off;
             }
-            const int cnt = (int)((lp - lp0) / kInteractThreads);
-            flush(cnt);
-            npair = listed + cnt - 1u;  // minus the self entry
+        };
+        uint32_t jn[4], tn[4];
+        draw(jn, tn);
+        for (uint32_t t = 0; t < nhit; t += 4) {
+            v4f qp[4], qv[4];
+            float4 sh[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                qp[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, jn[u], 0, 0);
+                qv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, jn[u], 0, 0);
+                sh[u] = s_sh[tn[u]];
+            }
+            draw(jn, tn);
+#pragma unroll
+            for (int u = 0; u < 4; u++) pair(qp[u], qv[u], sh[u]);
         }
+    };
+
+    uint32_t lp = 0, nhit = 0, listed = 0;
+    auto put1 = [&](uint32_t e, uint32_t b) {
+        s_ent[lp][tid] = make_uint2(e, b);
+        lp += b != 0u ? 1u : 0u;
+        nhit += (uint32_t)__builtin_popcount(b);
+    };
+    for (int col = 0; col < 9; col++) {
+        if (__any(act && lp > (uint32_t)(kCEnt - 1 - kCSlack))) {
+            if (act) {
+                flush(lp, nhit);
+                listed += nhit;
+                lp = 0;
+                nhit = 0;
+            }
+        }
+        const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
+        uint32_t jb = 0, je = 0, b1 = 0, b2 = 0;
+        if (act && X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
+            const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
+            jb = cbeg[c0 + zlo];
+            je = cend[c0 + zhi];
+            b1 = cbeg[c0 + (uint32_t)cz];
+            b2 = (uint32_t)cz + 1 < ncz ? cbeg[c0 + (uint32_t)cz + 1] : je;
+        }
+        const uint32_t len = je - jb;
+        const uint32_t kb1 = min(b1 - jb, len), kb2 = min(b2 - jb, len);
+        ncand += len;
+        // the block's index range of this column offset, staged in LDS when
+        // it fits (as in the plain kernel: jb, je never decrease along the lanes)
+        const unsigned long long wm = __ballot(len != 0u);
+        uint32_t lo = 0xffffffffu, hi = 0u;
+        if (wm) {
+            lo = (uint32_t)__builtin_amdgcn_readlane((int)jb, __builtin_ctzll(wm));
+            hi = (uint32_t)__builtin_amdgcn_readlane((int)je, 63 - __builtin_clzll(wm));
+        }
+        if ((tid & 63) == 0) {
+            s_lo[tid >> 6] = lo;
+            s_hi[tid >> 6] = hi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
+        const bool staged = hi > lo && hi - lo <= (uint32_t)kCStage;
+        if (staged) {
+            for (uint32_t t = tid; t < hi - lo; t += kInteractThreads) s_stage[t] = pos4[lo + t];
+        }
+        __syncthreads();
+        if (!len) continue;
+        const float pix = pi.x + (float)(1 - col / 3) * cs;
+        const float piy = pi.y + (float)(1 - col % 3) * cs;
+        const uint32_t tag0 = (uint32_t)col * 3u;
+        uint32_t bits = 0, k0 = 0;
+        // a full or final mask of 32 candidates from c0: split by z cell
+        // (candidates below kb1 in cell z-1, below kb2 in cell z, the rest
+        // in z+1) and listed; a lane flushes alone when it could not take
+        // three more entries
+        auto put = [&](uint32_t c0, uint32_t b) {
+            const uint32_t l1 = kb1 > c0 ? min(kb1 - c0, 32u) : 0u;
+            const uint32_t l2 = kb2 > c0 ? min(kb2 - c0, 32u) : 0u;
+            const uint32_t m1 = (uint32_t)(0xffffffff00000000ull >> l1);  // the first l1 candidates
+            const uint32_t m2 = (uint32_t)(0xffffffff00000000ull >> l2);
+            const uint32_t e = (jb + c0) << 5;
+            put1(e | tag0, b & m1);
+            put1(e | (tag0 + 1u), b & m2 & ~m1);
+            put1(e | (tag0 + 2u), b & ~m2);
+            if (lp > (uint32_t)(kCEnt - 1 - 3)) {
+                flush(lp, nhit);
+                listed += nhit;
+                lp = 0;
+                nhit = 0;
+            }
+        };
+        auto test = [&](const v4f (&q)[kCUnroll], uint32_t k) {
+#pragma unroll
+            for (int u = 0; u < kCUnroll; u++) {
+                const uint32_t kk = k + (uint32_t)u;
+                const float ziz = kk < kb1 ? zm : (kk < kb2 ? pi.z : zp);
+                const float dx = pix - q[u].x, dy = piy - q[u].y, dz = ziz - q[u].z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(r2 - kp.r2max), 31);
+            }
+            if ((k & 31u) == 32u - kCUnroll) {
+                const uint32_t c0 = k + kCUnroll - 32u;
+                const uint32_t v = len - c0;
+                put(c0, v >= 32u ? bits : bits & ~(0xffffffffu >> v));
+                bits = 0;
+            }
+        };
+        if (staged) {
+            const float4 *sp = s_stage + (jb - lo);
+            for (; k0 < len; k0 += kCUnroll) {
+                v4f q[kCUnroll];
+#pragma unroll
+                for (int u = 0; u < kCUnroll; u++) {
+                    const float4 t = sp[k0 + u];
+                    q[u] = v4f{t.x, t.y, t.z, 0.0f};
+                }
+                test(q, k0);
+            }
+        } else {
+            const uint32_t voff = jb * 16u;
+            for (; k0 < len; k0 += kCUnroll) {
+                v4f q[kCUnroll];
+#pragma unroll
+                for (int u = 0; u < kCUnroll; u++)
+                    q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
+                test(q, k0);
+            }
+        }
+        const uint32_t tail = k0 & 31u;
+        if (tail) {
+            const uint32_t c0 = k0 - tail;
+            const uint32_t v = len - c0;
+            put(c0, (bits << (32u - tail)) & ~(0xffffffffu >> v));
+        }
+    }
+    if (act) {
+        flush(lp, nhit);
+        npair = listed + nhit - 1u;  // minus the self entry
+        nu *= kp.h;
+    }
+    if (inrange) {
         const float mk = kp.mass * kp.kgrad;
         float ax = 0.f, ay = 0.f, az = 0.f, ar = 0.f;
         if (ti == kFluid) {
@@ -372,7 +475,7 @@ __global__ __launch_bounds__(kInteractThreads, 2) void k_interact_cell(
     if (tid == 0) {
         double d = s_rdt[0];
         uint32_t np = s_rnp[0], nc = s_rnc[0];
-        for (int k = 1; k < kInteractThreads / 64; k++) {
+        for (int k = 1; k < kWaves; k++) {
             d = fmin(d, s_rdt[k]);
             np += s_rnp[k];
             nc += s_rnc[k];

@@ -3,8 +3,8 @@
 Every case here runs ordinary kernels to their end: the conditions come from
 the data handed to the library (a NaN density, a state that imposes no time
 step limit, a density whose sound speed overflows FP32, a cell holding more
-particles than a 12-bit run offset can address), never from a kernel made to
-fail.
+particles than the surrogate rows' 12-bit run offsets can address), never
+from a kernel made to fail.
 """
 import numpy as np
 import pytest
@@ -122,13 +122,13 @@ def test_overfull_cell_plain_interaction_exact():
     assert not ctx.status() & sph.STATUS_RUN_OVERFLOW
 
 
-def test_overfull_cell_flagged_on_bounded_paths():
-    """The cell + offset interaction and the surrogate's rows address a run
-    with 12-bit offsets: a run of more than 4,096 particles is cut there and
-    flagged (results of that call invalid), and the call still completes."""
+def test_overfull_cell_cell_path_exact():
+    """The cell + offset interaction also addresses its candidates by full
+    indices: the 5,000-candidate run is searched completely (every pair
+    counted) and no run overflow is reported."""
     case = _overfull_cloud()
     p, n = case.params, case.n
-    announce(f"status: overfull cell, cell path and surrogate rows n={n}")
+    announce(f"status: overfull cell, cell path n={n}")
     ctx = sph.Context(p, n, sph.FEATURE_CELL)
     t64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
     ca, cb = sph.CellState.empty(n), sph.CellState.empty(n)
@@ -140,9 +140,19 @@ def test_overfull_cell_flagged_on_bounded_paths():
     rates = sph.make_rates(n)
     ctx.cinteract(cb, n, rates)
     torch.cuda.synchronize()
-    assert ctx.status() & sph.STATUS_RUN_OVERFLOW
-    assert ctx.pairs() < n * (n - 1)
+    assert ctx.pairs() == n * (n - 1)
+    assert not ctx.status() & sph.STATUS_RUN_OVERFLOW
+    for k, v in rates.items():
+        assert torch.isfinite(v[:n].float()).all(), k
 
+
+def test_overfull_cell_flagged_in_surrogate_rows():
+    """The surrogate's rows address a run with 12-bit offsets: a run of more
+    than 4,096 particles is cut there and flagged (results of that call
+    invalid), and the call still completes."""
+    case = _overfull_cloud()
+    p, n = case.params, case.n
+    announce(f"status: overfull cell, surrogate rows n={n}")
     ctx2 = sph.Context(p, n)
     _, out = gpu_sort(ctx2, case.state, n)
     X = torch.empty(n, sph.NN_IN, dtype=torch.bfloat16, device="cuda")
