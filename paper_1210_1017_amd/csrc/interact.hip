@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
     __shared__ uint32_t s_rnc[kWaves];
 
     const int tid = threadIdx.x;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t n0 = info->n_label[0];
+    const uint32_t blk = layer_block(blockIdx.x, (n0 + kInteractThreads - 1) / kInteractThreads, sk, cbeg, kp);
     const uint32_t i = blk * kInteractThreads + tid;
     const bool inrange = i < n0;
     const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;

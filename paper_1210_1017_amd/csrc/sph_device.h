@@ -76,6 +76,34 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
     return (k / kXcdChunk) * round + x * kXcdChunk + k % kXcdChunk;
 }
 
+// Block order of the interaction kernels (blocks of kInteractThreads
+// particles): the hardware hands block b to XCD b % 8. In the sorted
+// order, the blocks whose first particle lies in x-layer X of cells form a
+// range [s0, s1); of these, each XCD receives as many as it would in index
+// order, but as one contiguous group (XCD 0 the first group, and so on).
+// All XCDs then work through the same layer at the same time, each on its
+// own range of rows, and the neighbour rows in layers X - 1 and X + 1 of a
+// group are the same XCD's groups there, read shortly before and after
+// (its L2 keeps them). Blocks past the label-0 prefix keep their index.
+__device__ __forceinline__ uint32_t layer_block(uint32_t b, uint32_t nb0,
+                                                const uint32_t *__restrict__ sk,
+                                                const uint32_t *__restrict__ cbeg,
+                                                const KParams &kp) {
+    if (b >= nb0) return b;
+    const uint32_t lay = (uint32_t)kp.ncy * (uint32_t)kp.ncz;
+    const uint32_t X = (sk[b * kInteractThreads] & kp.cell_mask) / lay;
+    auto start = [&](uint32_t x) -> uint32_t {  // first block of layer x
+        return x >= (uint32_t)kp.ncx ? nb0
+                                     : min((cbeg[x * lay] + kInteractThreads - 1) / kInteractThreads, nb0);
+    };
+    const uint32_t s0 = start(X), s1 = start(X + 1);
+    auto cnt = [](uint32_t a, uint32_t x) { return (a + 7u - x) / 8u; };  // j < a with j % 8 == x
+    const uint32_t x = b % 8u;
+    uint32_t g = s0;
+    for (uint32_t y = 0; y < x; y++) g += cnt(s1, y) - cnt(s0, y);
+    return g + cnt(b, x) - cnt(s0, x);
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = __lane_id();
 #pragma unroll

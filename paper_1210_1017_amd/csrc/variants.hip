@@ -218,7 +218,9 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
                                 (float)(1 - zc) * cs, 0.0f);
     }
     const uint32_t n0 = info->n_label[0];
-    const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kInteractThreads + tid;
+    const uint32_t i =
+        layer_block(blockIdx.x, (n0 + kInteractThreads - 1) / kInteractThreads, sk, cbeg, kp) *
+            kInteractThreads + tid;
     const bool inrange = i < n0;
     const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;
     const bool act = ti != kGhost;
