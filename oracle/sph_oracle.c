@@ -13,7 +13,9 @@
  * checks, so that both sides make the same decision:
  *   - the cell coordinate floorf((x - o) * (1/cs)) of Sec. 3.1 (cells of 2h);
  *   - the neighbour test |r_i - r_j|^2 < (2h)^2 of Sec. 2.2 (compact support,
- *     kappa = 2), evaluated as fmaf(dz,dz, fmaf(dy,dy, dx*dx)) < (float)(4h^2).
+ *     kappa = 2), evaluated as fmaf(dz,dz, fmaf(dy,dy, fmaf(dx,dx, -r2))) < 0
+ *     with r2 = (float)(4h^2): the difference r^2 - 4h^2 as one chain of
+ *     fused multiply-adds.
  * Build with -ffp-contract=off so that no other expression is contracted.
  *
  * Particle types: 0 fluid, 1 boundary (dynamic boundary, Sec. 2.3),
@@ -313,13 +315,18 @@ static void pair_terms(const orc_params *p, double rx, double ry, double rz,
     if (fabs(mu) > a->nu) a->nu = fabs(mu);
 }
 
+/* r^2 - 4h^2 in FP32, one fused chain (see header). */
+static float support_excess(float dx, float dy, float dz, float r2max)
+{
+    return fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -r2max)));
+}
+
 /* Neighbour decision in FP32 (see header). */
 static int within_support(float xi, float yi, float zi, float xj, float yj, float zj,
                           float r2max)
 {
     const float dx = xi - xj, dy = yi - yj, dz = zi - zj;
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    return r2 < r2max;
+    return support_excess(dx, dy, dz, r2max) < 0.0f;
 }
 
 static float support_r2(const orc_params *p)
@@ -428,7 +435,7 @@ void orc_interact_brute(const orc_params *p, int64_t n, const double *x, const d
                 /* same FP32 test on the (minimum-image) separation */
                 const float dx = (float)r[0], dy = (float)r[1], dz = (float)r[2];
                 if (box) {
-                    if (!(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < r2max)) continue;
+                    if (!(support_excess(dx, dy, dz, r2max) < 0.0f)) continue;
                 } else if (!within_support((float)x[i], (float)y[i], (float)z[i], (float)x[j],
                                            (float)y[j], (float)z[j], r2max)) {
                     continue;

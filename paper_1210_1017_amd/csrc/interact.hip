@@ -269,10 +269,10 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
 #pragma unroll
             for (int u = 0; u < kUnroll; u++) {
                 const float dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
-                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                // bits = bits << 1 | (r2 < 4h^2): the sign of the
-                // difference of two floats decides the comparison exactly
-                bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(r2 - kp.r2max), 31);
+                // e = r^2 - 4h^2 as one chain of fused multiply-adds from
+                // -4h^2; bits = bits << 1 | (e < 0) (a zero sum is +0)
+                const float e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -kp.r2max)));
+                bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(e), 31);
             }
             if ((k & 31u) == 32u - kUnroll) {  // 32 candidates tested
                 const uint32_t c0 = k + kUnroll - 32u;

@@ -392,8 +392,8 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
                 const uint32_t kk = k + (uint32_t)u;
                 const float ziz = kk < kb1 ? zm : (kk < kb2 ? pi.z : zp);
                 const float dx = pix - q[u].x, dy = piy - q[u].y, dz = ziz - q[u].z;
-                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(r2 - kp.r2max), 31);
+                const float e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -kp.r2max)));  // r^2 - 4h^2
+                bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(e), 31);
             }
             if ((k & 31u) == 32u - kCUnroll) {
                 const uint32_t c0 = k + kCUnroll - 32u;

@@ -250,3 +250,24 @@ def test_totals_hand_sums(orc):
               epsrel=1e-13)[0] for rr in rho[:3]]
     assert t[6] == pytest.approx(m * sum(e), rel=1e-9)
     assert t[7] == 3.0
+
+
+def test_support_edge_is_strict_and_three_dimensional(orc):
+    """The neighbour test of Sec. 2.2 (|r_ij| < 2h, strict) at its edge, on
+    separations whose FP32 arithmetic is exact: h = 1.5 s with s = 2^-7, so
+    4h^2 = 9 s^2, and r_ij = (s, 2s, 2s + d) has |r_ij|^2 = 4h^2 exactly for
+    d = 0. A pair at exactly 2h is no neighbour, one 2^-20 m closer is, one
+    2^-20 m farther is not; every component counts (dropping dz or dy, or
+    flipping the comparison, changes a count)."""
+    s = 2.0 ** -7
+    p = _params()
+    p["h"] = 1.5 * s
+    cases.set_grid(p, (-0.2, -0.2, -0.2), (0.6, 0.6, 0.6))
+    ri = np.array([0.25, 0.25, 0.25])
+    eps = 2.0 ** -20
+    for d, want in ((0.0, 0), (-eps, 1), (eps, 0)):
+        for perm in ((0, 1, 2), (2, 0, 1), (1, 2, 0)):
+            sep = np.array([s, 2 * s, 2 * s + d])[list(perm)]
+            st = _state([ri, ri - sep], [[0.0] * 3] * 2, [1000.0, 1000.0])
+            acc, _, _ = _by_id(orc, p, st)
+            assert acc["npair"].tolist() == [want, want], (d, perm)
