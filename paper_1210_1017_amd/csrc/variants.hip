@@ -254,6 +254,7 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
     const float kvis2 = -kp.alpha * kp.h * kp.c0 * kp.inv_rho0 * kp.inv_rho0 * kp.inv_rho0;
     const float rhoi2 = rhoi * rhoi;
     const float zm = pi.z + cs, zp = pi.z - cs;  // i's z relative to the cells z-1, z+1
+    const float zabs = pi.z + (float)cz * cs;    // i's z against staged candidates
 
     auto pair = [&](const v4f pj, const v4f vj, const float4 sh) {
         const float dx = (pi.x + sh.x) - pj.x, dy = (pi.y + sh.y) - pj.y, dz = (pi.z + sh.z) - pj.z;
@@ -358,7 +359,16 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
         }
         const bool staged = hi > lo && hi - lo <= (uint32_t)kCStage;
         if (staged) {
-            for (uint32_t t = tid; t < hi - lo; t += kInteractThreads) s_stage[t] = pos4[lo + t];
+            // z of a staged candidate as o_z + c_z cs (its cell's z index
+            // from its key): the lanes then test every candidate of a run
+            // against one z, o_z,i + c_z,i cs, without choosing the z cell
+            // per candidate. Only the support test sees these sums; the pair
+            // terms use the offsets and the exact cell shifts.
+            for (uint32_t t = tid; t < hi - lo; t += kInteractThreads) {
+                float4 q = pos4[lo + t];
+                q.z += (float)((sk[lo + t] & kp.cell_mask) % ncz) * cs;
+                s_stage[t] = q;
+            }
         }
         __syncthreads();
         if (!len) continue;
@@ -386,11 +396,11 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
                 nhit = 0;
             }
         };
-        auto test = [&](const v4f (&q)[kCUnroll], uint32_t k) {
+        auto test = [&](const v4f (&q)[kCUnroll], uint32_t k, const bool absz) {
 #pragma unroll
             for (int u = 0; u < kCUnroll; u++) {
                 const uint32_t kk = k + (uint32_t)u;
-                const float ziz = kk < kb1 ? zm : (kk < kb2 ? pi.z : zp);
+                const float ziz = absz ? zabs : (kk < kb1 ? zm : (kk < kb2 ? pi.z : zp));
                 const float dx = pix - q[u].x, dy = piy - q[u].y, dz = ziz - q[u].z;
                 const float e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -kp.r2max)));  // r^2 - 4h^2
                 bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(e), 31);
@@ -411,7 +421,7 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
                     const float4 t = sp[k0 + u];
                     q[u] = v4f{t.x, t.y, t.z, 0.0f};
                 }
-                test(q, k0);
+                test(q, k0, true);
             }
         } else {
             const uint32_t voff = jb * 16u;
@@ -420,7 +430,7 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
 #pragma unroll
                 for (int u = 0; u < kCUnroll; u++)
                     q[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, voff, (int)(k0 * 16u + 16u * u), 0);
-                test(q, k0);
+                test(q, k0, false);
             }
         }
         const uint32_t tail = k0 & 31u;
