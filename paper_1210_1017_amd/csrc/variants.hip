@@ -186,13 +186,15 @@ hipError_t launch_gather_cell(sph_ctx *c, const sph_cstate &in, const sph_cstate
 // differs is the separation: r_ij = (o_i + s) - o_j with s = (c_i - c_j) cs,
 // the cell difference being the run's (x, y) column offset and, along z,
 // which of the run's three cells j lies in (from the run's cell
-// boundaries). A mask is split by those cells, so a list entry holds one
-// shift: (j << 5 | tag, mask) with tag = 3 column + z cell indexing the
-// shift table.
-constexpr int kCEnt = 19;       // list slots per lane (one for the sentinel)
+// boundaries). A list entry is (j << 5 | 3 column, mask) and, beside it, the
+// two positions in the mask where the z cell changes (l1: first candidate
+// not in cell z - 1, l2: first one in cell z + 1); the compute phase takes
+// the shift-table index 3 column + z cell of each drawn candidate from
+// them.
+constexpr int kCEnt = 15;       // list slots per lane (one for the sentinel)
 constexpr int kCUnroll = 8;     // candidates tested per group
 constexpr int kCStage = 768;    // staged candidate positions per column offset
-constexpr int kCSlack = 6;      // converged flush when a lane cannot take this many more
+constexpr int kCSlack = 4;      // converged flush when a lane cannot take this many more
 
 __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4,
@@ -203,6 +205,7 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
                 float *__restrict__ onu, uint32_t *__restrict__ onpair) {
     constexpr int kWaves = kInteractThreads / 64;
     __shared__ uint2 s_ent[kCEnt][kInteractThreads];
+    __shared__ uint16_t s_zs[kCEnt][kInteractThreads];  // l1 | l2 << 6 of each entry
     __shared__ float4 s_stage[kCStage + kCUnroll];
     __shared__ float4 s_sh[27];  // (x, y, z) shift of tag 3 col + zc
     __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
@@ -274,24 +277,28 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
     };
 
     // compute phase over the cnt entries of the lane's list holding nhit
-    // set bits; the sentinel (i, the own cell's tag 13, bit 31) after the
-    // last entry stands in for every position past the end (the self pair
-    // adds exactly zero)
+    // set bits; the sentinel (i in the own cell: column 4, z cell 1 for
+    // every position, bit 31) after the last entry stands in for every
+    // position past the end (the self pair adds exactly zero)
     auto flush = [&](uint32_t cnt, uint32_t nhit) {
-        s_ent[cnt][tid] = make_uint2(i << 5 | 13u, 0x80000000u);
-        uint32_t pk = 0, cb = 0, ce = 0;
+        s_ent[cnt][tid] = make_uint2(i << 5 | 12u, 0x80000000u);
+        s_zs[cnt][tid] = (uint16_t)(32u << 6);
+        uint32_t pk = 0, cb = 0, ce = 0, cz = 0;
         uint2 nx = s_ent[0][tid];
+        uint32_t nz = s_zs[0][tid];
         auto draw = [&](uint32_t (&jj)[4], uint32_t (&tt)[4]) {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const bool empty = cb == 0u;
                 cb = empty ? nx.y : cb;
                 ce = empty ? nx.x : ce;
+                cz = empty ? nz : cz;
                 pk = min(pk + (empty ? 1u : 0u), cnt);
                 nx = s_ent[pk][tid];
+                nz = s_zs[pk][tid];
                 const uint32_t off = (uint32_t)__builtin_clz(cb);
                 jj[u] = ((ce >> 5) + off) << 4;  // byte offset of j
-                tt[u] = ce & 31u;
+                tt[u] = (ce & 31u) + (off >= (cz & 63u) ? 1u : 0u) + (off >= (cz >> 6) ? 1u : 0u);
                 cb &= 0x7fffffffu >> off;
             }
         };
@@ -313,11 +320,6 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
     };
 
     uint32_t lp = 0, nhit = 0, listed = 0;
-    auto put1 = [&](uint32_t e, uint32_t b) {
-        s_ent[lp][tid] = make_uint2(e, b);
-        lp += b != 0u ? 1u : 0u;
-        nhit += (uint32_t)__builtin_popcount(b);
-    };
     for (int col = 0; col < 9; col++) {
         if (__any(act && lp > (uint32_t)(kCEnt - 1 - kCSlack))) {
             if (act) {
@@ -376,20 +378,18 @@ k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__res
         const float piy = pi.y + (float)(1 - col % 3) * cs;
         const uint32_t tag0 = (uint32_t)col * 3u;
         uint32_t bits = 0, k0 = 0;
-        // a full or final mask of 32 candidates from c0: split by z cell
-        // (candidates below kb1 in cell z-1, below kb2 in cell z, the rest
-        // in z+1) and listed; a lane flushes alone when it could not take
-        // three more entries
+        // a full or final mask of 32 candidates from c0 is listed with the
+        // positions where its z cell changes (candidates below kb1 lie in
+        // cell z - 1, below kb2 in cell z, the rest in z + 1); a lane
+        // flushes alone when its list is full
         auto put = [&](uint32_t c0, uint32_t b) {
             const uint32_t l1 = kb1 > c0 ? min(kb1 - c0, 32u) : 0u;
             const uint32_t l2 = kb2 > c0 ? min(kb2 - c0, 32u) : 0u;
-            const uint32_t m1 = (uint32_t)(0xffffffff00000000ull >> l1);  // the first l1 candidates
-            const uint32_t m2 = (uint32_t)(0xffffffff00000000ull >> l2);
-            const uint32_t e = (jb + c0) << 5;
-            put1(e | tag0, b & m1);
-            put1(e | (tag0 + 1u), b & m2 & ~m1);
-            put1(e | (tag0 + 2u), b & ~m2);
-            if (lp > (uint32_t)(kCEnt - 1 - 3)) {
+            s_ent[lp][tid] = make_uint2((jb + c0) << 5 | tag0, b);
+            s_zs[lp][tid] = (uint16_t)(l1 | l2 << 6);
+            lp += b != 0u ? 1u : 0u;
+            nhit += (uint32_t)__builtin_popcount(b);
+            if (lp >= (uint32_t)(kCEnt - 1)) {
                 flush(lp, nhit);
                 listed += nhit;
                 lp = 0;
