@@ -399,6 +399,7 @@ def slab_bench(args) -> dict:
     cand = ctx.candidate_total() - cand0
     c = ctx.counts()
     status = ctx.status()
+    movers, path = ctx.sort_stats()
     kern_ms = float(ph.sum(axis=1).mean())
     t_int = float(ph[:, 1].mean()) * 1e-3
     pairs_per_launch = pairs / args.steps
@@ -421,7 +422,9 @@ def slab_bench(args) -> dict:
                         "hbm_gbs_algorithmic":
                             BYTES_PER_PARTICLE_INTERACT * c["n_label"][0] / t_int / 1e9},
            "last_counts": c, "migrated_out": books["migrated_out"], "wrapped": books["wrapped"],
-           "dt_last": float(ctx.dt()), "status": int(status)}
+           "dt_last": float(ctx.dt()), "status": int(status),
+           "sort_path": {"movers_last_step": movers,
+                         "path": ("radix", "merge", "merge_mover_passes")[path]}}
     return out
 
 
@@ -532,8 +535,10 @@ def main() -> int:
                      "dt_update": float(phases[:, 2].mean())},
         "roofline": roof,
         # which way the last timed step sorted: the movers (keys changed since
-        # the previous sort) merged with the rest, or the full radix sort
-        "sort_path": {"movers_last_step": movers, "merged_last_step": merged},
+        # the previous sort) merged with the rest (sorted by one block, or by
+        # their own radix passes), or the full radix sort
+        "sort_path": {"movers_last_step": movers, "merged_last_step": bool(merged),
+                      "path": ("radix", "merge", "merge_mover_passes")[merged]},
     }
     if args.probe_reps > 0:
         out["machine"] = machine_probe(args.probe_reps)

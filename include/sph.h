@@ -219,13 +219,14 @@ int sph_sort_kv_noalloc(const uint32_t *keys, const int32_t *vals, uint32_t *key
  * begin/end tables over the label-0 prefix (an empty cell c has
  * begin = end = first index with cell >= c), label counts and packing ranges.
  * `in` and `out` must not share arrays.
- * The stable order is unique, and it is found one of two ways, chosen on the
- * device: when at most 8192 particles have a key that differs from the key
- * the previous sort on ctx (any path) left at their index (the "movers", e.g.
- * a state that the previous step wrote, moved by one step), the movers alone
- * are sorted and merged with the others, which keep their order; otherwise
- * (a first sort, an unrelated state, many movers) the full radix sort runs.
- * Both give the same bits. */
+ * The stable order is unique, and it is found one of three ways, chosen on
+ * the device: when at most n / 4 particles have a key that differs from the
+ * key the previous sort on ctx (any path) left at their index (the "movers",
+ * e.g. a state that the previous step wrote, moved by one step, with
+ * migrants), the movers alone are sorted (by one block up to 8192, by their
+ * own radix passes above) and merged with the others, which keep their
+ * order; otherwise (a first sort, an unrelated state, many movers) the full
+ * radix sort runs. All give the same bits. */
 int sph_sort(sph_ctx *ctx, const sph_soa *in, sph_soa *out, uint32_t n, void *stream);
 
 /* Interaction (Sec. 3.2, equations of Sec. 2.2, boundaries of Sec. 2.3) on the
@@ -255,9 +256,12 @@ int sph_get_counts(sph_ctx *ctx, sph_counts *out, void *stream);
 int sph_get_dt(sph_ctx *ctx, float *dt, void *stream);
 int sph_get_pairs(sph_ctx *ctx, uint64_t *pairs, void *stream);
 /* The last plain sort (sph_sort, sph_step): its movers (particles whose key
- * differed from the previous sort's at their index; above 8192 the count
- * that made the radix path run) and whether the mover merge ran (1) or the
- * full radix sort (0). SPH_E_STATE when the last sort was a variant path's. */
+ * differed from the previous sort's at their index) and the path it took:
+ * 0 the radix sort of all keys, 1 the mover merge with the movers sorted by
+ * one block (at most 8192 of them, or any number when the host expected few),
+ * 2 the mover merge with the movers sorted by their own radix passes (more
+ * than 8192, at most n / 4). SPH_E_STATE when the last sort was a variant
+ * path's. */
 int sph_get_sort_stats(sph_ctx *ctx, uint32_t *movers, uint32_t *merged, void *stream);
 int sph_get_status(sph_ctx *ctx, uint32_t *flags, void *stream);
 /* Clear the status bits (a kernel on the stream; no host synchronisation). */

@@ -446,7 +446,7 @@ int sph_get_sort_stats(sph_ctx *c, uint32_t *movers, uint32_t *merged, void *str
     if (r) return r;
     if (!c->have_sort || c->last_path != 0) return fail(c, SPH_E_STATE, "no plain sort yet");
     *movers = h.movers;
-    *merged = h.sort_mode == kModeIncr ? 1u : 0u;
+    *merged = h.sort_mode;  // kModeFull 0, kModeIncr 1, kModeMid 2
     return SPH_OK;
 }
 

@@ -144,34 +144,43 @@ hipError_t launch_keys(const KParams &kp, const sph_soa &in, uint32_t n, uint32_
 // Stability: keys are ranked in input order (round, wave, lane), so equal
 // keys keep their relative order in every pass.
 
+// Gating and size of the passes: with `skip`, a pass runs only when the
+// sort's mode (*skip) is `run_mode`; with `n_dev`, the key count is *n_dev
+// (at most ntiles tiles; tiles past it count nothing and write nothing).
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              uint32_t n, int shift,
                                                              uint32_t ntiles,
                                                              uint32_t *__restrict__ hist,
-                                                             const uint32_t *__restrict__ skip) {
-    if (skip && *skip == kModeIncr) return;
+                                                             const uint32_t *__restrict__ skip,
+                                                             uint32_t run_mode,
+                                                             const uint32_t *__restrict__ n_dev) {
+    if (skip && *skip != run_mode) return;
+    if (n_dev) n = *n_dev;
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
     h[tid] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * (uint32_t)kSortTile;
-    uint32_t k[kSortItems];  // all loads first (clamped index), then the counts
+    if (base < n) {
+        uint32_t k[kSortItems];  // all loads first (clamped index), then the counts
 #pragma unroll
-    for (int r = 0; r < kSortItems; r++) {
-        const uint32_t idx = base + r * kSortThreads + tid;
-        k[r] = keys[idx < n ? idx : n - 1u];
+        for (int r = 0; r < kSortItems; r++) {
+            const uint32_t idx = base + r * kSortThreads + tid;
+            k[r] = keys[idx < n ? idx : n - 1u];
+        }
+#pragma unroll
+        for (int r = 0; r < kSortItems; r++)
+            if (base + r * kSortThreads + tid < n) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     }
-#pragma unroll
-    for (int r = 0; r < kSortItems; r++)
-        if (base + r * kSortThreads + tid < n) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
 }
 
 __global__ __launch_bounds__(256) void k_radix_scan(uint32_t *__restrict__ hist, uint32_t ntiles,
                                                     uint32_t *__restrict__ tot,
-                                                    const uint32_t *__restrict__ skip) {
-    if (skip && *skip == kModeIncr) return;
+                                                    const uint32_t *__restrict__ skip,
+                                                    uint32_t run_mode) {
+    if (skip && *skip != run_mode) return;
     __shared__ uint32_t s_w[4];
     uint32_t *row = hist + (size_t)blockIdx.x * ntiles;
     const int tid = threadIdx.x;
@@ -201,8 +210,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     int32_t *__restrict__ vout, uint32_t n, int shift, uint32_t ntiles,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot,
-    const uint32_t *__restrict__ skip) {
-    if (skip && *skip == kModeIncr) return;
+    const uint32_t *__restrict__ skip, uint32_t run_mode, const uint32_t *__restrict__ n_dev) {
+    if (skip && *skip != run_mode) return;
+    if (n_dev) n = *n_dev;
+    if (blockIdx.x * (uint32_t)kSortTile >= n) return;  // a tile past the keys
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t s_k[kSortTile];
     __shared__ int32_t s_v[kSortTile];
@@ -314,11 +325,12 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
         const int shift = 8 * p;
         if (p > 0 || !first_hist_done)
             hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, n,
-                               shift, ntiles, c->hist, skip);
+                               shift, ntiles, c->hist, skip, kModeFull, nullptr);
         hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, c->hist, ntiles,
-                           c->digit_tot, skip);
+                           c->digit_tot, skip, kModeFull);
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, vsrc,
-                           kdst, vdst, n, shift, ntiles, c->hist, c->digit_tot, skip);
+                           kdst, vdst, n, shift, ntiles, c->hist, c->digit_tot, skip, kModeFull,
+                           nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         ksrc = kdst;
@@ -333,7 +345,8 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
 // source (the input is only read).
 hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
                            int32_t *vals_out, uint32_t n, int key_bits, uint32_t *ks,
-                           int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s) {
+                           int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s,
+                           const uint32_t *skip, uint32_t run_mode, const uint32_t *n_dev) {
     if (n == 0) return hipSuccess;
     const int passes = (key_bits + 7) / 8;
     const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
@@ -345,10 +358,11 @@ hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint
         int32_t *vdst = to_out ? vals_out : vs;
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, n, shift,
-                           ntiles, hist, nullptr);
-        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, hist, ntiles, tot, nullptr);
+                           ntiles, hist, skip, run_mode, n_dev);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, hist, ntiles, tot, skip,
+                           run_mode);
         hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, ksrc, vsrc,
-                           kdst, vdst, n, shift, ntiles, hist, tot, nullptr);
+                           kdst, vdst, n, shift, ntiles, hist, tot, skip, run_mode, n_dev);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         ksrc = kdst;
@@ -545,6 +559,32 @@ __device__ __forceinline__ uint2 lower_bound2(const uint32_t *sk, const uint32_t
     return make_uint2(b0, b1);
 }
 
+// Lower bound of (key, idx) in the (key, index)-sorted (sk, si) of length m,
+// by the 64 lanes of a wave together (every lane gets it): each step tests 64
+// evenly spaced pivots of [lo, hi) and keeps the gap after the last one below.
+__device__ __forceinline__ uint32_t wave_lower_bound(const uint32_t *sk, const uint32_t *si,
+                                                     uint32_t m, uint32_t key, uint32_t idx,
+                                                     uint32_t lane) {
+    uint32_t lo = 0, hi = m;  // the answer lies in [lo, hi]
+    while (hi > lo) {
+        const uint32_t step = (hi - lo + 63u) / 64u;
+        const uint32_t p = lo + lane * step;
+        bool below = false;
+        if (p < hi) {
+            const uint32_t k = sk[p], j = si[p];
+            below = k < key || (k == key && j < idx);
+        }
+        const uint32_t c = (uint32_t)__popcll(__ballot(below));  // pivots below: lanes 0..c-1
+        if (c == 0) return lo;
+        const uint32_t last = lo + (c - 1u) * step;  // below the target
+        const uint32_t next = lo + c * step;          // at or above it, when < hi
+        lo = last + 1u;
+        hi = next < hi ? next : hi;
+        if (step == 1u) return lo;
+    }
+    return lo;
+}
+
 // Wave-cooperative copy of the tiles' mover segments with more than `above`
 // movers to (dk, di) at the tiles' offsets: wave w takes tiles w, w + NW,
 // ... (lane j reads the offsets of the j-th of them), 64 movers per load and
@@ -593,10 +633,13 @@ __device__ __forceinline__ void copy_segments(const uint32_t *__restrict__ segk,
 // sort) when fb is set. Then:
 //  * m <= kIncCap: the movers (index order, from the tiles' segments) into
 //    LDS at their tiles' offsets, sorted stably by key there;
-//  * m > kIncCap and allow_full: the radix passes are chosen, nothing more;
+//  * m > kIncCap and allow_full: the movers' own radix passes are chosen
+//    when m <= mid (kModeMid: k_move_compact, the passes and k_move_split
+//    do the rest), else the radix passes over all keys; nothing more here;
 //  * m > kIncCap otherwise (the host expected few movers): the movers are
 //    copied to global memory and sorted there by the same passes, slowly
 //    but exactly.
+// The offsets end with moff[ntiles] = m.
 // Out: the movers sorted by (key, index) in (outk, outi); per tile the range
 // of sorted movers its particles can fall between; the stayer split of the
 // label-1 and label-2 movers (a search of the previous keys; the gather
@@ -609,7 +652,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
     const uint32_t *__restrict__ segi, uint32_t *__restrict__ mcnt, const uint32_t *__restrict__ prev,
     uint32_t nprev, uint32_t cell_bits, uint32_t *outk, uint32_t *outi, uint32_t *tmpk,
     uint32_t *tmpi, uint2 *__restrict__ mtile,
-    DevInfo *__restrict__ info, int allow_full, unsigned long long *fb) {
+    DevInfo *__restrict__ info, int allow_full, uint32_t mid, unsigned long long *fb) {
     __shared__ uint32_t s_k[2][kIncCap];
     __shared__ uint32_t s_i[2][kIncCap];
     __shared__ uint32_t s_wc[kPlanWaves][256];
@@ -665,13 +708,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
         }
     }
     const uint32_t m = running;  // the same in every thread
+    if (tid == 0) mcnt[ntiles] = m;
     if (tid == 0 && fb)
         __hip_atomic_store(fb, (unsigned long long)m << 1 | (nprev > 0 ? 1ull : 0ull),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     const bool small = m <= kIncCap;
     if (!small && allow_full) {
         if (tid == 0) {
-            info->sort_mode = kModeFull;
+            info->sort_mode = m <= mid ? kModeMid : kModeFull;
             info->movers = m;
         }
         return;
@@ -736,6 +780,67 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
     if (tid == 0) {
         info->sort_mode = kModeIncr;
         info->movers = m;
+    }
+}
+
+// kModeMid, before the movers' radix passes: the movers of each tile's
+// segment (index order) to their offsets in (ck, ci), one wave per tile.
+__global__ __launch_bounds__(64) void k_move_compact(const uint32_t *__restrict__ segk,
+                                                     const uint32_t *__restrict__ segi,
+                                                     const uint32_t *__restrict__ moff,
+                                                     uint32_t ntiles, uint32_t *__restrict__ ck,
+                                                     uint32_t *__restrict__ ci,
+                                                     const uint32_t *__restrict__ mode) {
+    if (*mode != kModeMid) return;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t o = moff[t], cnt = moff[t + 1] - o;
+        const uint32_t sb = t * (uint32_t)kSortTile;
+        for (uint32_t r = threadIdx.x; r < cnt; r += 64u) {
+            ck[o + r] = segk[sb + r];
+            ci[o + r] = segi[sb + r];
+        }
+    }
+}
+
+// kModeMid, after the passes: what the plan's block does for few movers, over
+// the grid: per tile the range of the sorted movers (fk, fi) its particles
+// can fall between, and the stayer split of the label-1 and label-2 movers
+// into split[].
+__global__ __launch_bounds__(256) void k_move_split(const uint32_t *__restrict__ fk,
+                                                    const uint32_t *__restrict__ fi,
+                                                    uint32_t n, uint32_t ntiles,
+                                                    const uint32_t *__restrict__ prev,
+                                                    uint32_t nprev, uint32_t cell_bits,
+                                                    uint2 *__restrict__ mtile,
+                                                    uint32_t *__restrict__ split,
+                                                    const DevInfo *__restrict__ info) {
+    if (info->sort_mode != kModeMid) return;
+    const uint32_t m = info->movers;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
+    // one wave per tile: 64-way search steps (ballot over 64 pivots) instead
+    // of a chain of dependent halvings
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t t = g >> 6; t < ntiles; t += gs >> 6) {
+        const uint2 kr = mtile[t];
+        const uint32_t i0 = t * (uint32_t)kSortTile;
+        const uint32_t a = wave_lower_bound(fk, fi, m, kr.x, i0, lane);
+        const uint32_t b = wave_lower_bound(fk, fi, m, kr.y, i0 + (uint32_t)kSortTile, lane);
+        if (lane == 0) mtile[t] = make_uint2(a, b);
+    }
+    const uint32_t ns = nprev < n ? nprev : n;
+    for (uint32_t k = g; k < m; k += gs) {
+        const uint32_t key = fk[k], idx = fi[k];
+        const uint32_t l = key >> cell_bits;
+        uint32_t q = kNoSplit;
+        if ((l == 1u || l == 2u) && ns > 0) {
+            uint32_t hi = info->lstart[l + 1];
+            hi = hi < nprev ? hi : nprev;
+            uint32_t lo = info->lstart[l];
+            lo = lo < hi ? lo : hi;
+            const uint32_t lb = lower_in(prev, lo, hi, key);
+            q = stayer_split(idx, lb, upper_in(prev, lb, hi, key), nprev, ns);
+        }
+        split[k] = q;
     }
 }
 
@@ -920,24 +1025,53 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
                                                 float4 *__restrict__ vel4,
                                                 DevInfo *__restrict__ info, MoveArgs mv,
                                                 int skip_rv) {
+    // the sorted movers that a block's particles (one tile's) can fall
+    // between, staged when they are few
+    constexpr uint32_t kStageMovers = 1024;
+    __shared__ uint32_t s_mk[kStageMovers], s_mi[kStageMovers];
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) reset_step_reductions(info);
-    if (k >= n) return;
-    if (info->sort_mode != kModeIncr) {
-        move_particle(kp, in, out, (uint32_t)perm[k], k, pos4, vel4, skip_rv != 0);
+    if (n == 0) return;
+    if (info->sort_mode == kModeFull) {
+        if (k < n) move_particle(kp, in, out, (uint32_t)perm[k], k, pos4, vel4, skip_rv != 0);
         return;
     }
+    const uint32_t b0 = blockIdx.x * blockDim.x;  // 256 | kSortTile: one tile per block
+    const uint2 range = mv.mtile[b0 / (uint32_t)kSortTile];
+    const uint32_t len = range.y - range.x;
+    const bool staged = len <= kStageMovers;  // the same in every thread
+    if (staged) {
+        for (uint32_t r = threadIdx.x; r < len; r += blockDim.x) {
+            s_mk[r] = mv.mk[range.x + r];
+            s_mi[r] = mv.mi[range.x + r];
+        }
+    }
+    __syncthreads();
+    if (k >= n) return;
     const uint32_t i = k, m = info->movers;
     const uint32_t key = mv.keys[i];
-    const uint2 range = mv.mtile[i / (uint32_t)kSortTile];
     uint32_t lo = range.x, hi = range.y;  // movers below (key, i) in (key, index) order
-    while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        const uint32_t ek = mv.mk[mid], ei = mv.mi[mid];
-        if (ek < key || (ek == key && ei < i))
-            lo = mid + 1;
-        else
-            hi = mid;
+    if (staged) {
+        lo = 0;
+        hi = len;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            const uint32_t ek = s_mk[mid], ei = s_mi[mid];
+            if (ek < key || (ek == key && ei < i))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        lo += range.x;
+    } else {
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            const uint32_t ek = mv.mk[mid], ei = mv.mi[mid];
+            if (ek < key || (ek == key && ei < i))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
     }
     const uint32_t wd = i >> 6;
     const unsigned long long bits = mv.mmask[wd];
@@ -984,10 +1118,32 @@ hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_
         hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kKeysThreads), 0, s, c->kp, in.x,
                            in.y, in.z, in.type, n, ntiles, c->keys_a, c->hist, c->keys_sorted,
                            nprev, c->mmask, c->mwpre, c->mcnt, segk, segi, c->mtile);
+        const uint32_t mid = mid_cap(n) > kIncCap ? mid_cap(n) : 0u;
         hipLaunchKernelGGL(k_move_plan, dim3(1), dim3(kPlanThreads), 0, s, n, ntiles, passes, segk,
                            segi, c->mcnt, c->keys_sorted, nprev, (uint32_t)c->cell_bits, outk,
-                           outi, tmpk, tmpi, c->mtile, c->info, expect_merge ? 0 : 1, c->fb_dev);
+                           outi, tmpk, tmpi, c->mtile, c->info, expect_merge ? 0 : 1, mid,
+                           c->fb_dev);
         if (!expect_merge) {
+            if (mid > 0) {
+                // kModeMid: the movers to (xk, xi), their radix passes (the
+                // count read on the device, the grid sized for mid), ending in
+                // (outk, outi) with the other pair as scratch, then the ranges
+                // and splits
+                const uint32_t cblocks = ntiles < 65535u ? ntiles : 65535u;
+                hipLaunchKernelGGL(k_move_compact, dim3(cblocks), dim3(64), 0, s, segk, segi,
+                                   c->mcnt, ntiles, xk, xi, mode);
+                hipError_t e = radix_sort_bufs(xk, (const int32_t *)xi, outk, (int32_t *)outi, mid,
+                                               key_bits, tmpk, (int32_t *)tmpi, c->hist,
+                                               c->digit_tot, s, mode, kModeMid, &c->info->movers);
+                if (e != hipSuccess) return e;
+                // a wave per tile for the ranges, then a thread per mover
+                const uint32_t sw = (ntiles + 3u) / 4u, sm = (mid + 255u) / 256u;
+                const uint32_t sneed = sw > sm ? sw : sm;
+                const uint32_t sblocks = sneed < 4096u ? sneed : 4096u;
+                hipLaunchKernelGGL(k_move_split, dim3(sblocks), dim3(256), 0, s, outk, outi, n,
+                                   ntiles, c->keys_sorted, nprev, (uint32_t)c->cell_bits, c->mtile,
+                                   tmpk, c->info);
+            }
             // the first pass takes each key's index as its value
             hipError_t e = radix_sort(c, c->keys_a, nullptr, c->keys_sorted, c->perm, n,
                                       key_bits, s, true, mode);

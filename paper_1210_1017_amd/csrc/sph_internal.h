@@ -19,10 +19,12 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = SPH_SORT_ITEMS;  // keys per thread of a radix tile
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix tile
 constexpr int kInteractThreads = 256;
-// Incremental sort: at most kIncCap particles may change their key between
-// two sorts for the merge path; with more, the radix passes run.
+// Incremental sort: when at most kIncCap particles change their key between
+// two sorts, one block sorts them and the merge places every particle; up to
+// mid_cap(n) (below), the movers' own radix passes sort them for the merge;
+// with more, the radix passes over all keys run (kModeFull).
 constexpr uint32_t kIncCap = 8192;
-constexpr uint32_t kModeFull = 0u, kModeIncr = 1u;
+constexpr uint32_t kModeFull = 0u, kModeIncr = 1u, kModeMid = 2u;
 constexpr int kRunBits = 12;                          // offset bits of a neighbour entry
 constexpr uint32_t kRunMax = (1u << kRunBits) - 1u;
 
@@ -56,7 +58,7 @@ struct DevInfo {
     unsigned long long pairs;        // neighbour pairs of the last interaction
     unsigned long long pairs_total;  // summed over every interaction since creation
     unsigned long long cand_total;   // candidates tested, summed likewise
-    uint32_t sort_mode;  // kModeFull / kModeIncr: the path the last plain sort took
+    uint32_t sort_mode;  // kModeFull / kModeIncr / kModeMid: the path the last plain sort took
     uint32_t movers;     // particles whose key differs from the previous sort's at their index
     uint32_t pad2_[2];
 };
@@ -126,9 +128,14 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
                       const uint32_t *skip_mode = nullptr);
 hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
                       uint32_t nprev, bool expect_merge, bool skip_rv, hipStream_t s);
+// Largest number of movers the merge takes with the movers' own radix passes
+// (more: the full radix passes).
+inline uint32_t mid_cap(uint32_t n) { return n / 4u; }
 hipError_t radix_sort_bufs(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
                            int32_t *vals_out, uint32_t n, int key_bits, uint32_t *ks,
-                           int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s);
+                           int32_t *vs, uint32_t *hist, uint32_t *tot, hipStream_t s,
+                           const uint32_t *skip = nullptr, uint32_t run_mode = 0u,
+                           const uint32_t *n_dev = nullptr);
 hipError_t launch_tables(sph_ctx *c, uint32_t n, hipStream_t s, bool counts = true);
 hipError_t launch_pack(sph_ctx *c, const sph_soa &in, uint32_t n, hipStream_t s);
 hipError_t launch_clear_flags(sph_ctx *c, hipStream_t s);

@@ -466,12 +466,13 @@ class Context:
         return int(v.value)
 
     def sort_stats(self, stream=None) -> tuple:
-        """(movers, merged) of the last plain sort: merged is True when the
-        movers were sorted and merged, False when the full radix sort ran."""
+        """(movers, path) of the last plain sort: path 0 when the radix sort
+        of all keys ran, 1 when one block sorted the movers for the merge, 2
+        when the movers' own radix passes did (truthy: merged)."""
         m, g = C.c_uint32(), C.c_uint32()
         self._check(self.L.sph_get_sort_stats(self.h, C.byref(m), C.byref(g),
                                                _stream_ptr(stream)))
-        return int(m.value), bool(g.value)
+        return int(m.value), int(g.value)
 
     def pair_total(self, stream=None) -> int:
         v = C.c_uint64()

@@ -1,17 +1,19 @@
 """The two ways of the sort step (Sec. 3.1) against the oracle's stable sort.
 
 A sort on a context whose previous sort left keys at the same indices takes
-the mover merge when at most 8192 keys differ, else the full radix passes;
-either way every array, the sorted keys, the cell tables and the counts must
-equal the oracle's bits. These cases steer the choice: steps of one
-simulation, an exact number of particles moved by hand around the limit,
-a shrinking and growing n, and an unrelated state on the same context.
+the mover merge when at most n / 4 keys differ (the movers sorted by one
+block up to 8192, by their own radix passes above), else the full radix
+passes; either way every array, the sorted keys, the cell tables and the
+counts must equal the oracle's bits. These cases steer the choice: steps of
+one simulation, an exact number of particles moved by hand around both
+limits, a shrinking and growing n, an unrelated state on the same context,
+and migrants injected into the 8.8M slab.
 """
 import numpy as np
 import pytest
 
 import oracle
-from paper_1210_1017_amd import cases, sph
+from paper_1210_1017_amd import cases, migration, sph
 from parity_util import announce, assert_sorted_equal
 
 pytestmark = pytest.mark.gpu
@@ -242,3 +244,50 @@ def test_expected_merge_of_every_particle_at_full_size():
     movers, merged = ctx.sort_stats()
     assert merged and movers > 1 << 16
     _check(ctx, p, rev, spare, n)
+
+
+@pytest.mark.parametrize("which", ["cap+1", "100k", "quarter", "quarter+1"])
+def test_mover_passes_at_full_size(which):
+    """Above 8192 and up to n / 4 movers their own radix passes sort them for
+    the merge (path 2); above n / 4 the radix sort of all keys runs (path 0).
+    The 1.47M obstacle dam break, sorted once; then j fluid particles of the
+    sorted state moved by 1.5 cells in x and sorted again on the same
+    context: j movers, bits equal to the oracle's."""
+    case = cases.case_c2()
+    p, n = case.params, case.n
+    j = {"cap+1": CAP + 1, "100k": 100_000, "quarter": n // 4, "quarter+1": n // 4 + 1}[which]
+    announce(f"mover passes, j={j} n={n}")
+    ctx = sph.Context(p, n)
+    st = _sort(ctx, case.state, n).to_numpy(n)
+    fluid = np.nonzero(st["type"] == cases.FLUID)[0]
+    pick = np.random.default_rng(j).choice(fluid, j, replace=False)
+    st["x"][pick] = (st["x"][pick].astype(np.float64) + 3.0 * p["h"]).astype(np.float32)
+    out = _sort(ctx, st, n)
+    movers, path = ctx.sort_stats()
+    assert movers == j
+    assert path == (2 if j <= n // 4 else 0)
+    _check(ctx, p, st, out, n)
+
+
+def test_mover_passes_with_migrants_on_the_slab():
+    """The 8.8M slab (ghost strips, labels 1 and 2): after a first sort, 0.25 %
+    of the fluid per face is injected across the faces as the slab bench does;
+    the second sort has tens of thousands of movers, among them the migrants
+    with their labels, and takes the movers' radix passes. Bits, counts and
+    packing ranges equal the oracle's."""
+    case = cases.perturb(cases.slab_c3(), 6)
+    p, n = case.params, case.n
+    nmig = int(round(0.0025 * case.counts()["fluid"]))
+    announce(f"mover passes with {nmig} migrants per face, slab n={n}")
+    ctx = sph.Context(p, n)
+    a = sph.DeviceState.from_numpy(case.state, capacity=n)
+    b = sph.DeviceState.empty(n)
+    ctx.sort(a, b, n)
+    migration.inject(b, n, p, 0, nmig)
+    torch.cuda.synchronize()
+    st = b.to_numpy(n)
+    ctx.sort(b, a, n)
+    torch.cuda.synchronize()
+    movers, path = ctx.sort_stats()
+    assert path == 2 and CAP < movers <= n // 4, (movers, path)
+    _check(ctx, p, st, a, n)
