@@ -194,7 +194,7 @@ hipError_t launch_gather_cell(sph_ctx *c, const sph_cstate &in, const sph_cstate
 constexpr int kCEnt = 15;       // list slots per lane (one for the sentinel)
 constexpr int kCUnroll = 8;     // candidates tested per group
 constexpr int kCStage = 768;    // staged candidate positions per column offset
-constexpr int kCSlack = 4;      // converged flush when a lane cannot take this many more
+constexpr int kCSlack = 3;      // converged flush when a lane cannot take this many more
 
 __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 k_interact_cell(KParams kp, const float4 *__restrict__ pos4, const float4 *__restrict__ vel4,
