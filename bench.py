@@ -466,7 +466,7 @@ def main() -> int:
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU "
-              "exchange of the method is not part of this build.", file=sys.stderr)
+              "exchange of the method is not implemented in this package.", file=sys.stderr)
         return 2
 
     import torch
