@@ -671,7 +671,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_move_plan(
     // offsets, one tile per thread per round; a thread copies the movers of
     // its tile to LDS when there are at most kSmall (loads in flight
     // together), a wave those of larger tiles below
-    constexpr uint32_t kSmall = 12;
+    constexpr uint32_t kSmall = 32;
     uint32_t running = 0;
     for (uint32_t start = 0; start < ntiles; start += kPlanThreads) {
         const uint32_t t = start + (uint32_t)tid;
