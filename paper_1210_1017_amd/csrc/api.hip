@@ -62,7 +62,7 @@ void free_events(sph_ctx *c) {
 
 void free_all(sph_ctx *c) {
     free_events(c);
-    void *vptrs[] = {c->p64,    c->drate, c->tot_part, c->nn_part,
+    void *vptrs[] = {c->pos8,   c->vel8,  c->drate, c->tot_part, c->nn_part,
                      c->nn_out, c->nn_x,  c->nn_y,     c->nn_rate};
     for (void *p : vptrs)
         if (p) (void)hipFree(p);
@@ -224,7 +224,8 @@ int sph_create(const sph_params *p, sph_ctx **out) {
     ALLOC(c->nn_part, (size_t)8 * (cap / 256 + 2) * sizeof(double));
     ALLOC(c->nn_out, 8 * sizeof(double));
     if (p->features & SPH_F_FP64) {
-        ALLOC(c->p64, cap * sizeof(double));
+        ALLOC(c->pos8, cap * sizeof(double4));
+        ALLOC(c->vel8, cap * sizeof(double4));
         ALLOC(c->drate, 4 * cap * sizeof(double));
     }
     if (p->features & SPH_F_SURROGATE) {

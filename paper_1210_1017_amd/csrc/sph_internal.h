@@ -96,7 +96,8 @@ struct sph_ctx {
     // variant paths (allocated when params.features asks for them)
     uint32_t features = 0;
     double cs64 = 0.0;
-    double *p64 = nullptr;        // p/rho^2 of the sorted FP64 state
+    double4 *pos8 = nullptr;      // packed (x, y, z, p/rho^2) of the sorted FP64 state
+    double4 *vel8 = nullptr;      // packed (vx, vy, vz, rho) of it
     double *drate = nullptr;      // 4 * capacity FP64 rates of sph_dstep
     double *tot_part = nullptr;   // 8 doubles per totals block
     double *nn_part = nullptr;    // 8 doubles per surrogate-judge block

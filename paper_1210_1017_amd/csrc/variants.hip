@@ -742,87 +742,253 @@ __device__ __forceinline__ double tait_p64(const DParams &d, double rho) {
 
 __global__ __launch_bounds__(256) void k_gather_d(DParams dp, sph_dstate in, sph_dstate out,
                                                   const int32_t *__restrict__ perm, uint32_t n,
-                                                  double *__restrict__ p64,
+                                                  double4 *__restrict__ pos8,
+                                                  double4 *__restrict__ vel8,
                                                   DevInfo *__restrict__ info) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) reset_variant_reductions(info);
     if (k >= n) return;
     const uint32_t s = (uint32_t)perm[k];
     const double rho = in.rho[s];
-    out.x[k] = in.x[s]; out.y[k] = in.y[s]; out.z[k] = in.z[s];
-    out.vx[k] = in.vx[s]; out.vy[k] = in.vy[s]; out.vz[k] = in.vz[s];
+    const double x = in.x[s], y = in.y[s], z = in.z[s];
+    const double vx = in.vx[s], vy = in.vy[s], vz = in.vz[s];
+    out.x[k] = x; out.y[k] = y; out.z[k] = z;
+    out.vx[k] = vx; out.vy[k] = vy; out.vz[k] = vz;
     out.rho[k] = rho;
     out.vxp[k] = in.vxp[s]; out.vyp[k] = in.vyp[s]; out.vzp[k] = in.vzp[s];
     out.rhop[k] = in.rhop[s];
     out.type[k] = in.type[s];
     out.id[k] = in.id[s];
-    p64[k] = tait_p64(dp, rho) / (rho * rho);
+    // the interaction's packed inputs: (x, y, z, p / rho^2), (v, rho)
+    pos8[k] = make_double4(x, y, z, tait_p64(dp, rho) / (rho * rho));
+    vel8[k] = make_double4(vx, vy, vz, rho);
 }
 
 hipError_t launch_gather_d(sph_ctx *c, const sph_dstate &in, const sph_dstate &out, uint32_t n,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_gather_d, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, dparams(c),
-                       in, out, c->perm, n, c->p64, c->info);
+                       in, out, c->perm, n, c->pos8, c->vel8, c->info);
     return hipGetLastError();
 }
 
-// Reference interaction in FP64: lane per particle, direct loop over the 9
-// z-runs, support test |r_ij|^2 < 4h^2 in FP64, the pair terms of Sec. 2.2.
-__global__ __launch_bounds__(256) void k_interact_d(
-    DParams dp, KParams kp, sph_dstate st, const double *__restrict__ p64,
-    const uint32_t *__restrict__ sk, const uint32_t *__restrict__ cbeg,
-    const uint32_t *__restrict__ cend, DevInfo *__restrict__ info, sph_drates out) {
-    __shared__ double s_rdt[4];
-    __shared__ uint32_t s_rnp[4];
+// Interaction in FP64 (the reference path): the pair terms of Sec. 2.2
+// written as plainly as the oracle's, with the search of the FP32 kernels:
+// lane per particle, the 9 contiguous z-runs, the candidates of each column
+// offset staged in LDS, the FP64 support test |r_ij|^2 < 4h^2 into 32-bit hit
+// masks in a per-lane LDS list, then the pair terms for the hits only. Pairs
+// are summed in the order of a direct loop over the runs (the list keeps it);
+// the particle itself is in the list and adds exactly zero.
+constexpr int kDEnt = 19;     // list slots per lane (one for the sentinel)
+constexpr int kDSlack = 3;    // converged flush when a lane cannot take this many more
+constexpr int kDUnroll = 8;   // candidates tested per group
+constexpr int kDStage = 512;  // staged candidate positions per column offset
+struct DPos {
+    double x, y, z;
+};
+
+__global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void
+k_interact_d(DParams dp, KParams kp, const double4 *__restrict__ pos8,
+             const double4 *__restrict__ vel8, const uint8_t *__restrict__ type,
+             const uint32_t *__restrict__ sk, const uint32_t *__restrict__ cbeg,
+             const uint32_t *__restrict__ cend, DevInfo *__restrict__ info, sph_drates out) {
+    constexpr int kWaves = kInteractThreads / 64;
+    __shared__ uint2 s_ent[kDEnt][kInteractThreads];  // (j, mask with the first candidate in bit 31)
+    __shared__ DPos s_stage[kDStage + kDUnroll];
+    __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+    __shared__ double s_rdt[kWaves];
+    __shared__ uint32_t s_rnp[kWaves];
+
     const int tid = threadIdx.x;
     const uint32_t n0 = info->n_label[0];
-    const uint32_t i = blockIdx.x * 256 + tid;
+    const uint32_t i =
+        layer_block(blockIdx.x, (n0 + kInteractThreads - 1) / kInteractThreads, sk, cbeg, kp) *
+            kInteractThreads + tid;
+    const bool inrange = i < n0;
+    const uint8_t ti = inrange ? type[i] : (uint8_t)kGhost;
+    const bool act = ti != kGhost;
     double dtmin = INFINITY;
     uint32_t npair = 0;
-    if (i < n0) {
-        const uint8_t ti = st.type[i];
-        double axs = 0, ays = 0, azs = 0, drho = 0, nu = 0;
-        const double xi = st.x[i], yi = st.y[i], zi = st.z[i];
-        const double vxi = st.vx[i], vyi = st.vy[i], vzi = st.vz[i], rhoi = st.rho[i];
-        const double Pi = p64[i];
-        const double ci = dp.c0 * (rhoi / dp.rho0) * (rhoi / dp.rho0) * (rhoi / dp.rho0);
-        if (ti != kGhost) {
-            const uint32_t cell = sk[i] & kp.cell_mask;
-            const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
-            const int cz = (int)(cell % ncz);
-            const int cy = (int)((cell / ncz) % ncy);
-            const int cx = (int)(cell / (ncz * ncy));
-            const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
-            const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
-            for (int col = 0; col < 9; col++) {
-                const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
-                if (X < 0 || X >= kp.ncx || Y < 0 || Y >= kp.ncy) continue;
-                const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
-                const uint32_t jb = cbeg[c0 + zlo], je = cend[c0 + zhi];
-                for (uint32_t j = jb; j < je; j++) {
-                    if (j == i) continue;
-                    const double dx = xi - st.x[j], dy = yi - st.y[j], dz = zi - st.z[j];
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (!(r2 < dp.r2max)) continue;
-                    const double rhoj = st.rho[j];
-                    const double t = 1.0 - 0.5 * sqrt(r2) / dp.h;
-                    const double F = t * t * t;
-                    const double ux = vxi - st.vx[j], uy = vyi - st.vy[j], uz = vzi - st.vz[j];
-                    const double vr = ux * dx + uy * dy + uz * dz;
-                    drho += F * vr;
-                    const double mu = dp.h * vr / (r2 + dp.eta2);
-                    nu = fmax(nu, fabs(mu));
-                    const double sj = rhoj / dp.rho0;
-                    const double cj = dp.c0 * sj * sj * sj;
-                    const double visc = vr < 0.0 ? -dp.alpha * 0.5 * (ci + cj) * mu / (0.5 * (rhoi + rhoj)) : 0.0;
-                    const double f = (Pi + p64[j] + visc) * F;
-                    axs += f * dx;
-                    ays += f * dy;
-                    azs += f * dz;
-                    npair++;
-                }
+
+    double4 pi = make_double4(0.0, 0.0, 0.0, 0.0), vi = pi;
+    if (inrange) {
+        pi = pos8[i];
+        vi = vel8[i];
+    }
+    const double rhoi = vi.w, Pi = pi.w;
+    const double ci = dp.c0 * (rhoi / dp.rho0) * (rhoi / dp.rho0) * (rhoi / dp.rho0);
+    double axs = 0.0, ays = 0.0, azs = 0.0, drho = 0.0, nu = 0.0;
+    const uint32_t ncz = (uint32_t)kp.ncz, ncy = (uint32_t)kp.ncy;
+    int cx = 0, cy = 0, cz = 0;
+    if (act) {
+        const uint32_t cell = sk[i] & kp.cell_mask;
+        cz = (int)(cell % ncz);
+        cy = (int)((cell / ncz) % ncy);
+        cx = (int)(cell / (ncz * ncy));
+    }
+    const uint32_t zlo = (uint32_t)(cz > 0 ? cz - 1 : 0);
+    const uint32_t zhi = (uint32_t)(cz + 1 < kp.ncz ? cz + 1 : kp.ncz - 1);
+
+    auto pair = [&](const double4 pj, const double4 vj) {
+        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double rhoj = vj.w;
+        const double t = 1.0 - 0.5 * sqrt(r2) / dp.h;
+        const double F = t * t * t;
+        const double ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+        const double vr = ux * dx + uy * dy + uz * dz;
+        drho += F * vr;
+        const double mu = dp.h * vr / (r2 + dp.eta2);
+        nu = fmax(nu, fabs(mu));
+        const double sj = rhoj / dp.rho0;
+        const double cj = dp.c0 * sj * sj * sj;
+        const double pv = -dp.alpha * 0.5 * (ci + cj) * mu / (0.5 * (rhoi + rhoj));
+        const double visc = vr < 0.0 ? pv : 0.0;
+        const double f = (Pi + pj.w + visc) * F;
+        axs += f * dx;
+        ays += f * dy;
+        azs += f * dz;
+    };
+
+    // compute phase over the cnt entries of the lane's list holding nhit set
+    // bits; the sentinel (i, bit 31) after the last entry stands in for every
+    // position past the end
+    auto flush = [&](uint32_t cnt, uint32_t nhit) {
+        s_ent[cnt][tid] = make_uint2(i, 0x80000000u);
+        uint32_t pk = 0, cb = 0, cj = 0;
+        uint2 nx = s_ent[0][tid];
+        auto draw = [&](uint32_t (&jj)[2]) {
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const bool empty = cb == 0u;
+                cb = empty ? nx.y : cb;
+                cj = empty ? nx.x : cj;
+                pk = min(pk + (empty ? 1u : 0u), cnt);
+                nx = s_ent[pk][tid];
+                const uint32_t off = (uint32_t)__builtin_clz(cb);
+                jj[u] = cj + off;
+                cb &= 0x7fffffffu >> off;
+            }
+        };
+        uint32_t jn[2];
+        draw(jn);
+        for (uint32_t t = 0; t < nhit; t += 2) {
+            double4 qp[2], qv[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                qp[u] = pos8[jn[u]];
+                qv[u] = vel8[jn[u]];
+            }
+            draw(jn);
+#pragma unroll
+            for (int u = 0; u < 2; u++) pair(qp[u], qv[u]);
+        }
+    };
+
+    uint32_t lp = 0, nhit = 0, listed = 0;
+    auto put = [&](uint32_t j0, uint32_t b) {
+        s_ent[lp][tid] = make_uint2(j0, b);
+        lp += b != 0u ? 1u : 0u;
+        nhit += (uint32_t)__builtin_popcount(b);
+        if (lp >= (uint32_t)(kDEnt - 1)) {  // full: this lane alone
+            flush(lp, nhit);
+            listed += nhit;
+            lp = 0;
+            nhit = 0;
+        }
+    };
+    for (int col = 0; col < 9; col++) {
+        if (__any(act && lp > (uint32_t)(kDEnt - 1 - kDSlack))) {
+            if (act) {
+                flush(lp, nhit);
+                listed += nhit;
+                lp = 0;
+                nhit = 0;
             }
         }
+        const int X = cx + col / 3 - 1, Y = cy + col % 3 - 1;
+        uint32_t jb = 0, je = 0;
+        if (act && X >= 0 && X < kp.ncx && Y >= 0 && Y < kp.ncy) {
+            const uint32_t c0 = ((uint32_t)X * ncy + (uint32_t)Y) * ncz;
+            jb = cbeg[c0 + zlo];
+            je = cend[c0 + zhi];
+        }
+        const uint32_t len = je - jb;
+        // the block's index range of this column offset (jb, je never
+        // decrease along the lanes), staged when it fits
+        const unsigned long long wm = __ballot(len != 0u);
+        uint32_t lo = 0xffffffffu, hi = 0u;
+        if (wm) {
+            lo = (uint32_t)__builtin_amdgcn_readlane((int)jb, __builtin_ctzll(wm));
+            hi = (uint32_t)__builtin_amdgcn_readlane((int)je, 63 - __builtin_clzll(wm));
+        }
+        if ((tid & 63) == 0) {
+            s_lo[tid >> 6] = lo;
+            s_hi[tid >> 6] = hi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
+        const bool staged = hi > lo && hi - lo <= (uint32_t)kDStage;
+        if (staged) {
+            for (uint32_t t = tid; t < hi - lo; t += kInteractThreads) {
+                const double4 q = pos8[lo + t];
+                s_stage[t] = DPos{q.x, q.y, q.z};
+            }
+        }
+        __syncthreads();
+        if (!len) continue;
+        uint32_t bits = 0, k0 = 0;
+        auto test = [&](const DPos (&q)[kDUnroll], uint32_t k) {
+#pragma unroll
+            for (int u = 0; u < kDUnroll; u++) {
+                const double dx = pi.x - q[u].x, dy = pi.y - q[u].y, dz = pi.z - q[u].z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                // bits = bits << 1 | (r2 < 4h^2): the sign of the difference
+                const double e = r2 - dp.r2max;
+                bits = __builtin_amdgcn_alignbit(bits, (uint32_t)(__double_as_longlong(e) >> 32), 31);
+            }
+            if ((k & 31u) == 32u - kDUnroll) {
+                const uint32_t c0 = k + kDUnroll - 32u;
+                const uint32_t v = len - c0;
+                put(jb + c0, v >= 32u ? bits : bits & ~(0xffffffffu >> v));
+                bits = 0;
+            }
+        };
+        if (staged) {
+            const DPos *sp = s_stage + (jb - lo);
+            for (; k0 < len; k0 += kDUnroll) {
+                DPos q[kDUnroll];
+#pragma unroll
+                for (int u = 0; u < kDUnroll; u++) q[u] = sp[k0 + u];
+                test(q, k0);
+            }
+        } else {  // a range too wide to stage: loads clamped to the run
+            for (; k0 < len; k0 += kDUnroll) {
+                DPos q[kDUnroll];
+#pragma unroll
+                for (int u = 0; u < kDUnroll; u++) {
+                    const uint32_t kk = k0 + (uint32_t)u;
+                    const double4 t = pos8[jb + (kk < len ? kk : len - 1u)];
+                    q[u] = DPos{t.x, t.y, t.z};
+                }
+                test(q, k0);
+            }
+        }
+        const uint32_t tail = k0 & 31u;
+        if (tail) {
+            const uint32_t c0 = k0 - tail;
+            const uint32_t v = len - c0;
+            put(jb + c0, (bits << (32u - tail)) & ~(0xffffffffu >> v));
+        }
+    }
+    if (act) {
+        flush(lp, nhit);
+        npair = listed + nhit - 1u;  // minus the self entry
+    }
+    if (inrange) {
         const double mk = dp.mass * dp.kgrad;
         double ax = 0, ay = 0, az = 0, ar = 0;
         if (ti == kFluid) {
@@ -854,8 +1020,12 @@ __global__ __launch_bounds__(256) void k_interact_d(
     }
     __syncthreads();
     if (tid == 0) {
-        const double d = fmin(fmin(s_rdt[0], s_rdt[1]), fmin(s_rdt[2], s_rdt[3]));
-        const uint32_t np = s_rnp[0] + s_rnp[1] + s_rnp[2] + s_rnp[3];
+        double d = s_rdt[0];
+        uint32_t np = s_rnp[0];
+        for (int k = 1; k < kWaves; k++) {
+            d = fmin(d, s_rdt[k]);
+            np += s_rnp[k];
+        }
         if (d < INFINITY) atomic_min_pos_double(&info->dtmin64_bits, d);
         if (np) {
             atomicAdd(&info->pairs, (unsigned long long)np);
@@ -866,9 +1036,10 @@ __global__ __launch_bounds__(256) void k_interact_d(
 
 hipError_t launch_interact_d(sph_ctx *c, const sph_dstate &st, uint32_t n, const sph_drates &out,
                              hipStream_t s) {
-    const uint32_t nb = n == 0 ? 1 : (n + 255) / 256;
-    hipLaunchKernelGGL(k_interact_d, dim3(nb), dim3(256), 0, s, dparams(c), c->kp, st, c->p64,
-                       c->keys_sorted, c->cell_begin, c->cell_end, c->info, out);
+    const uint32_t nb = n == 0 ? 1 : (n + kInteractThreads - 1) / kInteractThreads;
+    hipLaunchKernelGGL(k_interact_d, dim3(nb), dim3(kInteractThreads), 0, s, dparams(c), c->kp,
+                       c->pos8, c->vel8, st.type, c->keys_sorted, c->cell_begin, c->cell_end,
+                       c->info, out);
     return hipGetLastError();
 }
 
