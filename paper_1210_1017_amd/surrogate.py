@@ -298,7 +298,8 @@ def run(case: cases.Case, steps: int, net: sph.Mlp | None = None, cfg: NnConfig 
         if fallback or dt is None or steps - step < K_STEPS:
             nxt = others(cur)[0]
             ctx.step(cur, nxt, n, step)
-            dt = ctx.dt()
+            if dt is None:  # the advances' span; after a fallback and in the
+                dt = ctx.dt()  # tail no advance follows, so no host wait
             cur, step = nxt, step + 1
             books["plain_steps"] += 1
             continue
