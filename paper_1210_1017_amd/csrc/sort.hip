@@ -35,7 +35,7 @@ constexpr int kKeysItems = kSortTile / kKeysThreads;
 __global__ __launch_bounds__(kKeysThreads) void k_keys_move(
     KParams kp, const float *__restrict__ x, const float *__restrict__ y,
     const float *__restrict__ z, const uint8_t *__restrict__ type, uint32_t n, uint32_t ntiles,
-    uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,  // hist: null, no digit counts
     const uint32_t *__restrict__ prev, uint32_t nprev, unsigned long long *__restrict__ mmask,
     uint32_t *__restrict__ mwpre, uint32_t *__restrict__ mcnt, uint32_t *__restrict__ segk,
     uint32_t *__restrict__ segi, uint2 *__restrict__ mtile) {
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys_move(
         key[r] = cell_key(kp, px[r], py[r], pz[r], pt[r]);
         if (valid) {
             keys[idx] = key[r];
-            atomicAdd(&h[key[r] & 255u], 1u);
+            if (hist) atomicAdd(&h[key[r] & 255u], 1u);
             kmin = key[r] < kmin ? key[r] : kmin;
             kmax = key[r] > kmax ? key[r] : kmax;
         }
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys_move(
         atomicMax(&s_kmax, kmax);
     }
     __syncthreads();
-    if (tid < 256) hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
+    if (hist && tid < 256) hist[(uint32_t)tid * ntiles + blockIdx.x] = h[tid];
     if (tid == 0) mtile[blockIdx.x] = make_uint2(s_kmin, s_kmax);
     if (tid < 64) {  // word r * NW + w covers particles base + 64 (r * NW + w) + [0, 64)
         const uint32_t v = tid < WPT ? s_wc[tid] : 0u;
@@ -1115,9 +1115,11 @@ hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_
     uint32_t *tmpk = (passes & 1) ? xk : segk, *tmpi = (passes & 1) ? xi : segi;
     if (n > 0) {
         const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
+        // the first radix pass's digit counts only when its kernels are launched
         hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kKeysThreads), 0, s, c->kp, in.x,
-                           in.y, in.z, in.type, n, ntiles, c->keys_a, c->hist, c->keys_sorted,
-                           nprev, c->mmask, c->mwpre, c->mcnt, segk, segi, c->mtile);
+                           in.y, in.z, in.type, n, ntiles, c->keys_a,
+                           expect_merge ? nullptr : c->hist, c->keys_sorted, nprev, c->mmask,
+                           c->mwpre, c->mcnt, segk, segi, c->mtile);
         const uint32_t mid = mid_cap(n) > kIncCap ? mid_cap(n) : 0u;
         hipLaunchKernelGGL(k_move_plan, dim3(1), dim3(kPlanThreads), 0, s, n, ntiles, passes, segk,
                            segi, c->mcnt, c->keys_sorted, nprev, (uint32_t)c->cell_bits, outk,
