@@ -294,8 +294,11 @@ static int do_sort(sph_ctx *c, const sph_soa *in, const sph_soa *out, uint32_t n
     // merge (which still sorts any number of movers, slowly); else launch
     // the radix passes too and let the plan choose
     const unsigned long long fb = __atomic_load_n(c->fb, __ATOMIC_RELAXED);
-    const bool expect = nprev > 0 && c->last_path == 0 && in->x == c->last_out_x && (fb & 1ull) &&
-                        (fb >> 1) <= kIncCap;
+    const bool loop = nprev > 0 && c->last_path == 0 && in->x == c->last_out_x && (fb & 1ull);
+    const unsigned long long last_m = fb >> 1;
+    const int expect = !loop ? kExpectAny
+                             : (last_m <= kIncCap ? kExpectFew
+                                                  : (last_m <= mid_cap(n) ? kExpectMid : kExpectAny));
     hipError_t e = sort_state(c, *in, *out, n, nprev, expect, skip_rv, s);
     if (e != hipSuccess) return hip_fail(c, e, "sort step");
     c->last_out_x = out->x;

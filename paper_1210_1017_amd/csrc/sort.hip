@@ -1102,7 +1102,8 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
 // expects few movers, the plan then sorting any number itself), reorder,
 // cell tables and counts of the new order.
 hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
-                      uint32_t nprev, bool expect_merge, bool skip_rv, hipStream_t s) {
+                      uint32_t nprev, int expect, bool skip_rv, hipStream_t s) {
+    const bool expect_merge = expect == kExpectFew;
     const uint32_t *mode = &c->info->sort_mode;
     const int key_bits = c->cell_bits + 2;
     const int passes = (key_bits + 7) / 8;
@@ -1115,10 +1116,13 @@ hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_
     uint32_t *tmpk = (passes & 1) ? xk : segk, *tmpi = (passes & 1) ? xi : segi;
     if (n > 0) {
         const uint32_t ntiles = (n + kSortTile - 1) / kSortTile;
-        // the first radix pass's digit counts only when its kernels are launched
+        // the first radix pass's digit counts here only when the full passes
+        // are likely to run (with a middle number of movers expected, their
+        // first pass counts for itself if the plan chooses it after all)
+        const bool keys_hist = expect == kExpectAny;
         hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kKeysThreads), 0, s, c->kp, in.x,
                            in.y, in.z, in.type, n, ntiles, c->keys_a,
-                           expect_merge ? nullptr : c->hist, c->keys_sorted, nprev, c->mmask,
+                           keys_hist ? c->hist : nullptr, c->keys_sorted, nprev, c->mmask,
                            c->mwpre, c->mcnt, segk, segi, c->mtile);
         const uint32_t mid = mid_cap(n) > kIncCap ? mid_cap(n) : 0u;
         hipLaunchKernelGGL(k_move_plan, dim3(1), dim3(kPlanThreads), 0, s, n, ntiles, passes, segk,
@@ -1148,7 +1152,7 @@ hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_
             }
             // the first pass takes each key's index as its value
             hipError_t e = radix_sort(c, c->keys_a, nullptr, c->keys_sorted, c->perm, n,
-                                      key_bits, s, true, mode);
+                                      key_bits, s, keys_hist, mode);
             if (e != hipSuccess) return e;
         }
     }

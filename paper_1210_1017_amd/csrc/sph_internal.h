@@ -127,8 +127,14 @@ hipError_t radix_sort(sph_ctx *c, const uint32_t *keys_in, const int32_t *vals_i
                       uint32_t *keys_out, int32_t *vals_out, uint32_t n, int key_bits,
                       hipStream_t s, bool first_hist_done = false,
                       const uint32_t *skip_mode = nullptr);
+// What the host expects of the next sort's movers, from the count of the
+// last plan that has run: any number (all kernels launched, the keys kernel
+// counting the first radix digit), at most kIncCap (the merge kernels only),
+// or between kIncCap and mid_cap(n) (all kernels, no first-digit counts in
+// the keys kernel).
+enum SortExpect { kExpectAny = 0, kExpectFew = 1, kExpectMid = 2 };
 hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_t n,
-                      uint32_t nprev, bool expect_merge, bool skip_rv, hipStream_t s);
+                      uint32_t nprev, int expect, bool skip_rv, hipStream_t s);
 // Largest number of movers the merge takes with the movers' own radix passes
 // (more: the full radix passes).
 inline uint32_t mid_cap(uint32_t n) { return n / 4u; }

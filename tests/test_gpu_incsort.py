@@ -291,3 +291,34 @@ def test_mover_passes_with_migrants_on_the_slab():
     movers, path = ctx.sort_stats()
     assert path == 2 and CAP < movers <= n // 4, (movers, path)
     _check(ctx, p, st, a, n)
+
+
+def test_middle_count_expected_then_every_particle_moves():
+    """After a sort that took the movers' radix passes (100,000 movers at
+    1.47M) the host expects a middle count again for the buffer that sort
+    wrote, and launches the keys kernel without the first digit counts; a
+    reversed copy written over that buffer makes every particle a mover, the
+    plan chooses the full radix passes, whose first pass then counts for
+    itself. Bits equal to the oracle's."""
+    case = cases.case_c2()
+    p, n = case.params, case.n
+    announce(f"middle count expected, then all move n={n}")
+    ctx = sph.Context(p, n)
+    a = sph.DeviceState.from_numpy(case.state, capacity=n)
+    b, c = sph.DeviceState.empty(n), sph.DeviceState.empty(n)
+    ctx.sort(a, b, n)
+    st = b.to_numpy(n)
+    fluid = np.nonzero(st["type"] == cases.FLUID)[0]
+    pick = np.random.default_rng(12).choice(fluid, 100_000, replace=False)
+    st["x"][pick] = (st["x"][pick].astype(np.float64) + 3.0 * p["h"]).astype(np.float32)
+    _write(b, st)
+    ctx.sort(b, c, n)
+    torch.cuda.synchronize()
+    assert ctx.sort_stats() == (100_000, 2)
+    rev = {k: v[::-1].copy() for k, v in c.to_numpy(n).items()}
+    _write(c, rev)
+    ctx.sort(c, b, n)
+    torch.cuda.synchronize()
+    movers, path = ctx.sort_stats()
+    assert path == 0 and movers > n // 4
+    _check(ctx, p, rev, b, n)
