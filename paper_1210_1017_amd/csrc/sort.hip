@@ -35,7 +35,7 @@ constexpr int kKeysItems = kSortTile / kKeysThreads;
 __global__ __launch_bounds__(kKeysThreads) void k_keys_move(
     KParams kp, const float *__restrict__ x, const float *__restrict__ y,
     const float *__restrict__ z, const uint8_t *__restrict__ type, uint32_t n, uint32_t ntiles,
-    uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,  // hist: null, no digit counts
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,  // null: not stored / counted
     const uint32_t *__restrict__ prev, uint32_t nprev, unsigned long long *__restrict__ mmask,
     uint32_t *__restrict__ mwpre, uint32_t *__restrict__ mcnt, uint32_t *__restrict__ segk,
     uint32_t *__restrict__ segi, uint2 *__restrict__ mtile) {
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys_move(
         const bool valid = idx < n;
         key[r] = cell_key(kp, px[r], py[r], pz[r], pt[r]);
         if (valid) {
-            keys[idx] = key[r];
+            if (keys) keys[idx] = key[r];
             if (hist) atomicAdd(&h[key[r] & 255u], 1u);
             kmin = key[r] < kmin ? key[r] : kmin;
             kmax = key[r] > kmax ? key[r] : kmax;
@@ -984,7 +984,7 @@ __device__ __forceinline__ void reset_step_reductions(DevInfo *info) {
 // pulls particle perm[k] into place k; after the merge path thread i pushes
 // particle i to its destination and writes its key there (the sorted keys).
 struct MoveArgs {
-    const uint32_t *keys;  // unsorted keys (index order)
+    const uint32_t *keys;  // unsorted keys (index order); null: formed again from the particle
     uint32_t *skeys;       // sorted keys: read as the previous ones, written by the merge
     const uint32_t *mk, *mi;  // the movers sorted by (key, index)
     const uint2 *mtile;       // per tile: the range of them its particles fall between
@@ -1049,7 +1049,9 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, sph_soa in, sph_soa 
     __syncthreads();
     if (k >= n) return;
     const uint32_t i = k, m = info->movers;
-    const uint32_t key = mv.keys[i];
+    // the key from the particle's own data when the keys kernel did not
+    // store it (the same function of the same values)
+    const uint32_t key = mv.keys ? mv.keys[i] : cell_key(kp, in.x[i], in.y[i], in.z[i], in.type[i]);
     uint32_t lo = range.x, hi = range.y;  // movers below (key, i) in (key, index) order
     if (staged) {
         lo = 0;
@@ -1120,8 +1122,10 @@ hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_
         // are likely to run (with a middle number of movers expected, their
         // first pass counts for itself if the plan chooses it after all)
         const bool keys_hist = expect == kExpectAny;
+        // with only the merge kernels launched the reorder forms each key
+        // again from the particle's data instead of reading it back
         hipLaunchKernelGGL(k_keys_move, dim3(ntiles), dim3(kKeysThreads), 0, s, c->kp, in.x,
-                           in.y, in.z, in.type, n, ntiles, c->keys_a,
+                           in.y, in.z, in.type, n, ntiles, expect_merge ? nullptr : c->keys_a,
                            keys_hist ? c->hist : nullptr, c->keys_sorted, nprev, c->mmask,
                            c->mwpre, c->mcnt, segk, segi, c->mtile);
         const uint32_t mid = mid_cap(n) > kIncCap ? mid_cap(n) : 0u;
@@ -1156,8 +1160,9 @@ hipError_t sort_state(sph_ctx *c, const sph_soa &in, const sph_soa &out, uint32_
             if (e != hipSuccess) return e;
         }
     }
-    const MoveArgs mv = {c->keys_a, c->keys_sorted, outk,  outi,      c->mtile,   tmpk,
-                         c->mmask,  c->mwpre,       c->mcnt, c->cell_begin, c->cell_end, nprev};
+    const MoveArgs mv = {expect_merge ? nullptr : c->keys_a, c->keys_sorted, outk, outi,
+                         c->mtile, tmpk, c->mmask, c->mwpre, c->mcnt, c->cell_begin, c->cell_end,
+                         nprev};
     hipLaunchKernelGGL(k_gather, dim3(n == 0 ? 1 : (n + 255) / 256), dim3(256), 0, s, c->kp, in,
                        out, c->perm, n, c->pos4, c->vel4, c->info, mv, skip_rv ? 1 : 0);
     hipError_t e = hipGetLastError();
