@@ -180,18 +180,31 @@ __global__ __launch_bounds__(kInteractThreads) __attribute__((amdgpu_waves_per_e
                 cb &= 0x7fffffffu >> off;
             }
         };
+        // two groups in flight: the next group's data loads while the
+        // current one is evaluated (past the end the sentinel's own index)
         uint32_t jn[4];
         draw(jn);
+        v4f qp[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            qp[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, jn[u], 0, 0);
+            qv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, jn[u], 0, 0);
+        }
+        draw(jn);
         for (uint32_t t = 0; t < nhit; t += 4) {
-            v4f qp[4], qv[4];
+            v4f np[4], nv[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                qp[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, jn[u], 0, 0);
-                qv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, jn[u], 0, 0);
+                np[u] = __builtin_amdgcn_raw_buffer_load_b128(rp, jn[u], 0, 0);
+                nv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, jn[u], 0, 0);
             }
             draw(jn);
 #pragma unroll
-            for (int u = 0; u < 4; u++) pair(qp[u], qv[u]);
+            for (int u = 0; u < 4; u++) {
+                pair(qp[u], qv[u]);
+                qp[u] = np[u];
+                qv[u] = nv[u];
+            }
         }
     };
 
