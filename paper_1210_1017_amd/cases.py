@@ -375,6 +375,35 @@ def random_cloud(n: int, dp: float, extent, seed: int, types=(FLUID,)) -> Case:
     return Case("random_cloud", params, _make_state(pos, typ, rho, vel), pos)
 
 
+def isolated_clusters(seed: int, copies: int = 8, kmax: int = 12, dp: float = 0.02) -> Case:
+    """`copies` clusters of each size k = 1..kmax, shuffled over a lattice of
+    spacing 8h: a cluster's particles lie within 0.45h of its centre (so
+    within 0.9h of each other) and 7h from any other cluster, so each has
+    exactly k - 1 neighbours besides itself. Random fluid/boundary types,
+    velocities and +-1 % densities."""
+    rng = _rng(seed)
+    params = base_params(dp)
+    h = params["h"]
+    sizes = np.repeat(np.arange(1, kmax + 1), copies)
+    rng.shuffle(sizes)
+    side = int(np.ceil(len(sizes) ** (1.0 / 3.0)))
+    pos = []
+    for c, k in enumerate(sizes):
+        centre = (np.array([c % side, (c // side) % side, c // (side * side)]) + 0.5) * 8.0 * h
+        d = rng.normal(size=(k, 3))
+        d *= (0.45 * h * rng.uniform(0.0, 1.0, size=(k, 1)) ** (1.0 / 3.0)
+              / np.linalg.norm(d, axis=1, keepdims=True))
+        pos.append(centre + d)
+    pos = np.concatenate(pos)
+    n = pos.shape[0]
+    typ = rng.choice(np.array([FLUID, BOUNDARY]), size=n)
+    rho = 1000.0 * (1.0 + rng.uniform(-0.01, 0.01, size=n))
+    vel = rng.uniform(-0.5, 0.5, size=(n, 3))
+    ext = side * 8.0 * h
+    set_grid(params, (-2.0 * h,) * 3, (ext + 2.0 * h,) * 3)
+    return Case("isolated_clusters", params, _make_state(pos, typ, rho, vel), pos)
+
+
 def periodic_block(n_side: int, dp: float, seed: int, jitter: float = 0.15) -> Case:
     """n_side^3 fluid particles on a jittered lattice filling a periodic cube of
     side n_side*dp, random velocities and +-1 % densities (for invariance pins)."""

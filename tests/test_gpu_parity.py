@@ -239,47 +239,28 @@ def test_interact_dense_cells_flush():
 
 
 def test_interact_isolated_clusters_every_group_remainder():
-    """Clusters of 1 to 12 particles, each far (8h) from the others: every
+    """Clusters of 1 to 12 particles, each far (7h) from the others: every
     particle has exactly k - 1 neighbours besides itself, so the lanes' hit
     counts take every remainder modulo the four neighbours evaluated together,
     and a lone particle has none but itself."""
-    rng = np.random.default_rng(23)
-    p = cases.base_params(0.02)
-    h = p["h"]
-    sizes = np.repeat(np.arange(1, 13), 8)
-    rng.shuffle(sizes)
-    side = int(np.ceil(len(sizes) ** (1.0 / 3.0)))
-    pos, kid = [], []
-    for c, k in enumerate(sizes):
-        centre = (np.array([c % side, (c // side) % side, c // (side * side)]) + 0.5) * 8.0 * h
-        d = rng.normal(size=(k, 3))
-        d *= (0.45 * h * rng.uniform(0.0, 1.0, size=(k, 1)) ** (1.0 / 3.0)
-              / np.linalg.norm(d, axis=1, keepdims=True))
-        pos.append(centre + d)
-        kid.append(np.full(k, k))
-    pos, kid = np.concatenate(pos), np.concatenate(kid)
-    n = pos.shape[0]
-    typ = rng.choice(np.array([cases.FLUID, cases.BOUNDARY]), size=n)
-    rho = 1000.0 * (1.0 + rng.uniform(-0.01, 0.01, size=n))
-    vel = rng.uniform(-0.5, 0.5, size=(n, 3))
-    ext = np.full(3, side * 8.0 * h)
-    cases.set_grid(p, (-2.0 * h,) * 3, tuple(ext + 2.0 * h))
-    state = cases._make_state(pos, typ, rho, vel)
+    case = cases.isolated_clusters(23)
+    p, n = case.params, case.n
     announce(f"interact isolated clusters n={n}")
     ctx = _ctx(p, n)
-    _, out = gpu_sort(ctx, state, n)
+    _, out = gpu_sort(ctx, case.state, n)
     rates = sph.make_rates(n)
     ctx.interact(out, n, rates)
     torch.cuda.synchronize()
-    srt = oracle.sort_state(p, state)
+    srt = oracle.sort_state(p, case.state)
     assert_sorted_equal(out.to_numpy(n), srt, n)
     g = {k: v.cpu().numpy() for k, v in rates.items()}
     err, acc = interact_compare(p, srt, g)
     for k, v in err.items():
         assert v <= TOL, (k, v)
-    ids = srt["state"]["id"][:n]
-    assert np.array_equal(g["npair"][:n].astype(np.int64), kid[ids] - 1)
-    assert ctx.pairs() == int((kid - 1).sum())
+    # k x 8 particles have k - 1 neighbours, for k = 1..12
+    counts = np.bincount(g["npair"][:n].astype(np.int64), minlength=12)
+    assert np.array_equal(counts, 8 * np.arange(1, 13))
+    assert ctx.pairs() == int(acc["npair"].sum()) == 8 * int((np.arange(1, 13) * np.arange(12)).sum())
 
 
 def test_interact_deterministic():

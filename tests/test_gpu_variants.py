@@ -60,6 +60,7 @@ def _cases():
         "tank": lambda: cases.perturb(cases.small_tank(), 13),
         "slab": lambda: cases.perturb(cases.small_slab(), 14),
         "c1": lambda: cases.perturb(cases.case_c1(), 15),
+        "clusters": lambda: cases.isolated_clusters(24),
     }
 
 

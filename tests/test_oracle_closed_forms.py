@@ -271,3 +271,20 @@ def test_support_edge_is_strict_and_three_dimensional(orc):
             st = _state([ri, ri - sep], [[0.0] * 3] * 2, [1000.0, 1000.0])
             acc, _, _ = _by_id(orc, p, st)
             assert acc["npair"].tolist() == [want, want], (d, perm)
+
+
+def test_isolated_cluster_neighbour_counts(orc):
+    """Clusters of k = 1..12 particles far apart: the oracle's neighbour count
+    of every particle is the number of others within 2h by brute force over
+    the FP64 positions, k - 1 here (a wrong cell offset, a dropped z-run or a
+    counted self pair breaks it)."""
+    case = cases.isolated_clusters(23)
+    p, st, n = case.params, case.state, case.n
+    pos = case.pos64
+    d2 = ((pos[:, None, :] - pos[None, :, :]) ** 2).sum(-1)
+    brute = (d2 < (2.0 * p["h"]) ** 2).sum(1) - 1
+    assert np.array_equal(np.bincount(brute, minlength=12), 8 * np.arange(1, 13))
+    srt = orc.sort_state(p, st)
+    acc = orc.interact(p, srt)
+    ids = srt["state"]["id"][:n]
+    assert np.array_equal(acc["npair"].astype(np.int64), brute[ids])
